@@ -1,0 +1,285 @@
+"""FP64 CPU oracle for the QV-tree search hot path -- TEST INFRASTRUCTURE.
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its binding) never does, and the two share no code: the oracle is the plain C
+file ``qvo.c`` compiled with gcc, driven from here through ctypes.
+
+Every function takes a ``workloads.Problem``-like object; FP32 inputs are
+widened exactly to FP64 and all arithmetic is FP64.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "qvo.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile ``qvo.c`` with gcc (strict IEEE FP64: no fast-math, no FMA
+    contraction) into ``liboracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
+                               "-ffp-contract=off", "-fno-fast-math",
+                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Model(C.Structure):
+    _fields_ = [("W", C.c_int), ("H", C.c_int),
+                ("occ", C.POINTER(C.c_ubyte)),
+                ("A", C.c_int),
+                ("slip", C.POINTER(C.c_double)),
+                ("flip", C.POINTER(C.c_double)),
+                ("L", C.c_int),
+                ("lm_cell", C.POINTER(C.c_int)),
+                ("lm_p", C.c_double),
+                ("R", C.POINTER(C.c_double)),
+                ("goal", C.c_int),
+                ("gamma", C.c_double)]
+
+
+class _Dump(C.Structure):
+    _fields_ = [("valid", C.POINTER(C.c_ubyte)),
+                ("z", C.POINTER(C.c_int)),
+                ("count", C.POINTER(C.c_int)),
+                ("pz", C.POINTER(C.c_double)),
+                ("V", C.POINTER(C.c_double)),
+                ("qtree", C.POINTER(C.c_double)),
+                ("rb", C.POINTER(C.c_double)),
+                ("margin", C.POINTER(C.c_double)),
+                ("beliefs", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        mp = C.POINTER(_Model)
+        L.qvo_predict.argtypes = [mp, dp, C.c_int, dp]
+        L.qvo_predict.restype = None
+        L.qvo_likelihood.argtypes = [mp, dp, dp]
+        L.qvo_obs_prob.argtypes = [mp, C.c_int, C.c_int]
+        L.qvo_obs_prob.restype = C.c_double
+        L.qvo_belief_update.argtypes = [mp, C.c_int, dp, ip, ip, dp, dp]
+        L.qvo_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                       C.POINTER(C.c_uint32)]
+        L.qvo_philox4x32_10.restype = None
+        L.qvo_obs_uniform.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_uint32,
+                                     C.c_int, C.c_int, C.c_int]
+        L.qvo_obs_uniform.restype = C.c_double
+        L.qvo_draw_obs.argtypes = [dp, C.c_int, C.c_double, dp]
+        L.qvo_alg4_sample.argtypes = [mp, dp, C.c_int, C.c_int, C.c_uint64, ip]
+        L.qvo_value_iterate.argtypes = [mp, C.c_double, C.c_int, dp, dp, ip]
+        L.qvo_tree_slots.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.qvo_tree_slots.restype = C.c_long
+        L.qvo_plan.argtypes = [mp, dp, dp, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                              C.c_int, ip, dp, C.POINTER(_Dump), C.POINTER(C.c_long)]
+        L.qvo_filter_nll_grad.argtypes = [mp, dp, dp, C.c_int, C.c_int, dp, ip, ip,
+                                         dp, dp, dp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+class Model:
+    """FP64 copy of a problem's model arrays, kept alive for the C calls."""
+
+    def __init__(self, prob, slip=None, flip=None):
+        self.W, self.H = int(prob.W), int(prob.H)
+        self.occ = np.ascontiguousarray(prob.occ, dtype=np.uint8)
+        self.slip = np.ascontiguousarray(prob.slip if slip is None else slip,
+                                         dtype=np.float64).reshape(-1)
+        self.A = self.slip.size // 9
+        self.flip = np.ascontiguousarray(prob.flip if flip is None else flip,
+                                         dtype=np.float64)
+        self.lm = np.ascontiguousarray(prob.lm_cell, dtype=np.int32)
+        self.R = np.ascontiguousarray(prob.R, dtype=np.float64).reshape(-1)
+        self.c = _Model(self.W, self.H, _ptr(self.occ, C.c_ubyte), self.A,
+                        _ptr(self.slip, C.c_double), _ptr(self.flip, C.c_double),
+                        int(self.lm.size), _ptr(self.lm, C.c_int),
+                        float(np.float32(prob.lm_p)), _ptr(self.R, C.c_double),
+                        int(prob.goal), float(np.float32(prob.gamma)))
+        self.S = self.W * self.H
+        self.Z = 16 * (int(self.lm.size) + 1)
+
+    @property
+    def ref(self):
+        return C.byref(self.c)
+
+
+def _f64(x):
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def predict(prob, b, a) -> np.ndarray:
+    m = Model(prob)
+    b = _f64(b)
+    out = np.zeros(m.S)
+    lib().qvo_predict(m.ref, _ptr(b, C.c_double), int(a), _ptr(out, C.c_double))
+    return out
+
+
+def likelihood(prob, bp) -> np.ndarray:
+    m = Model(prob)
+    bp = _f64(bp)
+    p = np.zeros(m.Z)
+    st = lib().qvo_likelihood(m.ref, _ptr(bp, C.c_double), _ptr(p, C.c_double))
+    assert st == 0
+    return p
+
+
+def obs_prob(prob, z, s) -> float:
+    m = Model(prob)
+    return float(lib().qvo_obs_prob(m.ref, int(z), int(s)))
+
+
+def belief_update(prob, b, a, z):
+    """Batched filter step; returns (posterior [batch, S], p [batch], status)."""
+    m = Model(prob)
+    b = _f64(b).reshape(-1, m.S)
+    bt = b.shape[0]
+    a = np.ascontiguousarray(np.broadcast_to(a, (bt,)), dtype=np.int32)
+    z = np.ascontiguousarray(np.broadcast_to(z, (bt,)), dtype=np.int32)
+    out = np.zeros_like(b)
+    p = np.zeros(bt)
+    st = lib().qvo_belief_update(m.ref, bt, _ptr(b, C.c_double), _ptr(a, C.c_int),
+                                 _ptr(z, C.c_int), _ptr(out, C.c_double),
+                                 _ptr(p, C.c_double))
+    return out, p, int(st)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib().qvo_philox4x32_10(_ptr(c, C.c_uint32), _ptr(k, C.c_uint32), _ptr(o, C.c_uint32))
+    return o
+
+
+def obs_uniform(seed, qid, level, slot, a, n, k) -> float:
+    return float(lib().qvo_obs_uniform(C.c_uint64(seed), qid, level, slot, a, n, k))
+
+
+def draw_obs(p, u):
+    """Inverse-CDF observation draw; returns (z, margin)."""
+    p = _f64(p)
+    mg = C.c_double(0.0)
+    z = lib().qvo_draw_obs(_ptr(p, C.c_double), int(p.size), float(u), C.byref(mg))
+    return int(z), mg.value
+
+
+def alg4_sample(prob, b, a, nsamp, seed) -> np.ndarray:
+    m = Model(prob)
+    b = _f64(b)
+    out = np.zeros(nsamp, dtype=np.int32)
+    st = lib().qvo_alg4_sample(m.ref, _ptr(b, C.c_double), int(a), int(nsamp),
+                               C.c_uint64(seed), _ptr(out, C.c_int))
+    assert st == 0
+    return out
+
+
+def value_iterate(prob, tol=1e-12, max_sweeps=100000):
+    """Returns (Q [S, A] FP64, residual, sweeps)."""
+    m = Model(prob)
+    Q = np.zeros((m.S, m.A))
+    res = C.c_double(0.0)
+    sw = C.c_int(0)
+    st = lib().qvo_value_iterate(m.ref, float(tol), int(max_sweeps),
+                                 _ptr(Q, C.c_double), C.byref(res), C.byref(sw))
+    assert st == 0
+    return Q, res.value, sw.value
+
+
+class TreeDump:
+    """Capacity-slot tree records of one plan (see ``qvo.c``)."""
+
+    def __init__(self, A, n, D, S, beliefs=False):
+        self.A, self.n, self.D, self.S, self.K = A, n, D, S, A * n
+        self.level_size = [self.K ** d for d in range(D + 1)]
+        self.level_off = np.concatenate([[0], np.cumsum(self.level_size)]).astype(np.int64)
+        tot = int(self.level_off[-1])
+        self.valid = np.zeros(tot, dtype=np.uint8)
+        self.z = np.full(tot, -1, dtype=np.int32)
+        self.count = np.zeros(tot, dtype=np.int32)
+        self.pz = np.zeros(tot)
+        self.V = np.full(tot, np.nan)
+        self.qtree = np.full(tot * A, np.nan)
+        self.rb = np.full(tot * A, np.nan)
+        self.margin = np.full(tot * A * n, np.inf)
+        self.beliefs = np.zeros(tot * S) if beliefs else None
+        self.c = _Dump(_ptr(self.valid, C.c_ubyte), _ptr(self.z, C.c_int),
+                       _ptr(self.count, C.c_int), _ptr(self.pz, C.c_double),
+                       _ptr(self.V, C.c_double), _ptr(self.qtree, C.c_double),
+                       _ptr(self.rb, C.c_double), _ptr(self.margin, C.c_double),
+                       _ptr(self.beliefs, C.c_double) if beliefs else None)
+
+    def level(self, arr, d, width=1):
+        o, n = int(self.level_off[d]), self.level_size[d]
+        return arr[o * width:(o + n) * width]
+
+
+def plan(prob, Q, b0=None, D=None, n=None, seed=None, qid=None, full=False,
+         dump: Optional[TreeDump] = None, dump_beliefs=False):
+    """One planning step; returns dict(action, rootQ, expansions, dump)."""
+    m = Model(prob)
+    D = prob.D if D is None else D
+    n = prob.n if n is None else n
+    seed = prob.seed if seed is None else seed
+    qid = prob.query_id if qid is None else qid
+    Qd = _f64(Q).reshape(-1)
+    b0 = _f64(prob.b0 if b0 is None else b0)
+    if dump is None and not full:
+        dump = TreeDump(m.A, n, D, m.S, beliefs=dump_beliefs)
+    act = C.c_int(-1)
+    rq = np.zeros(m.A)
+    ex = C.c_long(0)
+    st = lib().qvo_plan(m.ref, _ptr(Qd, C.c_double), _ptr(b0, C.c_double), int(D), int(n),
+                        C.c_uint64(seed), int(qid), 1 if full else 0, C.byref(act),
+                        _ptr(rq, C.c_double), C.byref(dump.c) if dump is not None else None,
+                        C.byref(ex))
+    assert st == 0, st
+    return dict(action=act.value, rootQ=rq, expansions=ex.value, dump=dump)
+
+
+def filter_nll_grad(prob, theta, phi, acts, obs, b0=None):
+    """Returns (nll per trajectory [ntraj], g_theta [A, 9], g_phi [4])."""
+    m = Model(prob)
+    theta = _f64(theta).reshape(-1)
+    phi = _f64(phi)
+    acts = np.ascontiguousarray(acts, dtype=np.int32)
+    obs = np.ascontiguousarray(obs, dtype=np.int32)
+    ntraj, T = acts.shape
+    b0 = _f64(prob.b0 if b0 is None else b0)
+    if b0.ndim == 1:
+        b0 = np.ascontiguousarray(np.broadcast_to(b0, (ntraj, m.S)))
+    nll = np.zeros(ntraj)
+    gt = np.zeros(theta.size)
+    gp = np.zeros(4)
+    m.c.A = theta.size // 9
+    st = lib().qvo_filter_nll_grad(m.ref, _ptr(theta, C.c_double), _ptr(phi, C.c_double),
+                                   int(ntraj), int(T), _ptr(b0, C.c_double),
+                                   _ptr(acts, C.c_int), _ptr(obs, C.c_int),
+                                   _ptr(nll, C.c_double), _ptr(gt, C.c_double),
+                                   _ptr(gp, C.c_double))
+    assert st == 0, st
+    return nll, gt.reshape(-1, 9), gp
