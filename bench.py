@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Benchmark of the QV-tree search hot path on one MI355X.
+
+One step = one call of qv_plan_step: a full planning step (map signature,
+then for each of the D levels the prediction/likelihood statistics, the
+observation draws, and the child beliefs or the fused leaf scores, then the
+expectimax backup) on the 64 x 64 workload: seeded random rectangles (20%
+blocked), 8 actions with 8-neighbour slip, wall bits plus 32 landmarks,
+depth 3, 4 samples per action, Gaussian start belief (sigma 5 cells), Q
+from the library's own value iteration to a 1e-6 relative residual.  Inputs
+are resident on the GPU before the timed region; the timed steps cycle over
+a fixed set of draw seeds whose trees were counted during warm-up.
+
+Prints one JSON line: belief-state updates/s (value), plans/s, V-node
+expansions/s, the roofline of the dominant kernel (HIP events around its
+launches inside the timed region), the per-kernel breakdown, the value
+iteration, and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "belief-state updates/sec + plans/sec (1 GPU), % of HBM roofline"
+PEAK_HBM_GBS = 8000.0
+PEAK_FP32_TFLOPS = 157.3
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rect64.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seeds", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 512 MiB device copy (PMC byte-count calibration)")
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1810_00204_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def kernel_models(prob, counts):
+    """Algorithmic FP32 flops and HBM bytes of each kernel launch of one plan,
+    from the numbers of valid nodes per level.
+    Returns {kernel: [(flops, bytes) per launch in launch order]}."""
+    S, A, D = prob.S, prob.A, prob.D
+    out = {"k_stats": [], "k_update": [], "k_leaf": []}
+    for d in range(D):
+        P, C = counts[d], counts[d + 1]
+        out["k_stats"].append((P * S * A * 21.0, P * S * 4.0))
+        if d < D - 1:
+            out["k_update"].append((P * S * A * 18.0 + C * S * 6.0, P * S * 4.0 + C * S * 4.0))
+        else:
+            out["k_leaf"].append((P * S * A * 18.0 + C * S * (6.0 + 2 * A), P * S * 4.0))
+    return out
+
+
+def cpu_baseline(prob, Q32, seeds):
+    import numpy as np
+    import oracle
+    t0 = time.perf_counter()
+    upd = 0
+    for s in seeds:
+        res = oracle.plan(prob, Q32, seed=s)
+        d = res["dump"]
+        upd += sum(int(d.level(d.valid, k).sum()) for k in range(1, prob.D + 1)) * prob.S
+    dt = time.perf_counter() - t0
+    return {"value": upd / dt, "unit": "belief-state updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(seeds)} full planning steps (draw seeds {seeds[0]}..{seeds[-1]}) of "
+                      f"the same workload by the single-threaded FP64 oracle, {dt:.1f} s",
+            "plans_per_s": len(seeds) / dt, "seconds": dt}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the planning path runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_1810_00204_amd import binding as B
+    from paper_1810_00204_amd import workloads as wl
+    from paper_1810_00204_amd.planner import Planner
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    B.lib()
+    dev = "cuda:0"
+    prob = wl.make_rect(seed=0)
+    pl = Planner(prob, device=dev)
+
+    # offline Q-MDP values (timed on its own)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Q, res, sweeps = pl.value_iterate(tol=1e-6, max_sweeps=10000)
+    torch.cuda.synchronize()
+    vi_ms = (time.perf_counter() - t0) * 1e3
+
+    seeds = [prob.seed + i for i in range(args.seeds)]
+    counts = {}
+    for i in range(max(args.warmup, len(seeds))):
+        s = seeds[i % len(seeds)]
+        pl.plan(Q, seed=s)
+        if s not in counts:
+            t = pl.tree(beliefs=False)
+            lf = t["level_first"]
+            counts[s] = [int(t["valid"][lf[d]:lf[d + 1]].sum()) for d in range(prob.D + 1)]
+    torch.cuda.synchronize()
+
+    K = args.steps
+    step_seeds = [seeds[k % len(seeds)] for k in range(K)]
+    # timed region: K planning steps, nothing else on the stream
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in step_seeds:
+        pl.plan(Q, seed=s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # the same K steps again with HIP events bracketing every kernel launch
+    # on the launch stream: per-kernel durations for the roofline
+    B.qv_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in step_seeds:
+        pl.plan(Q, seed=s)
+    torch.cuda.synchronize()
+    wall_ev = time.perf_counter() - t0
+    st, ktimes = B.qv_timing_read()
+    B.qv_timing_enable(False)
+    B.check(st, "qv_timing_read")
+
+    # work done in the timed region
+    upd = sum(sum(counts[s][1:]) for s in step_seeds) * prob.S
+    exp = sum(sum(counts[s][:-1]) for s in step_seeds)
+    kids = sum(sum(counts[s][1:]) for s in step_seeds)
+
+    # per-kernel algorithmic work and measured time
+    kern = {}
+    tot_ms = sum(v[1] for v in ktimes.values())
+    for name, (launches, ms) in ktimes.items():
+        kern[name] = {"launches": launches, "avg_us": 1e3 * ms / launches,
+                      "share": ms / tot_ms if tot_ms else None}
+    per_plan = {s: kernel_models(prob, counts[s]) for s in seeds}
+    for name in ("k_stats", "k_update", "k_leaf"):
+        if name not in kern:
+            continue
+        fl = sum(f for s in step_seeds for f, _ in per_plan[s][name])
+        by = sum(b for s in step_seeds for _, b in per_plan[s][name])
+        n = sum(len(per_plan[s][name]) for s in step_seeds)
+        ms = ktimes[name][1]
+        kern[name].update({"alg_gflop_per_launch": fl / n / 1e9, "alg_mb_per_launch": by / n / 1e6,
+                           "tflops": fl / (ms * 1e-3) / 1e12, "gbs": by / (ms * 1e-3) / 1e9})
+    dom = max(ktimes, key=lambda k: ktimes[k][1])
+    roof = {"kernel": dom}
+    if dom in ("k_stats", "k_leaf"):
+        roof.update({"bound": "alu", "achieved": kern[dom]["tflops"], "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s"})
+    else:
+        roof.update({"bound": "hbm", "achieved": kern[dom].get("gbs", 0.0), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s"})
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("source_hash") == source_hash() and dom in tr.get("kernels", {}):
+            roof["traffic"] = tr["kernels"][dom]["bytes_per_launch"]
+    upd_kernel = kern.get("k_update", {})
+
+    if args.copy_calibration:
+        a = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    line = {
+        "metric": METRIC, "value": upd / wall, "unit": "belief-state updates/s",
+        "n_gpus": 1, "steps": K, "warmup": args.warmup, "ms_per_step": wall * 1e3 / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": prob.name, "grid": f"{prob.W}x{prob.H}", "actions": prob.A,
+                   "landmarks": prob.L, "depth": prob.D, "samples_per_action": prob.n,
+                   "blocked_fraction": round(float(prob.occ.mean()), 4),
+                   "draw_seeds": len(seeds), "parallelism": "single GPU"},
+        "ms_per_step_with_kernel_events": wall_ev * 1e3 / K,
+        "plans_per_s": K / wall, "v_node_expansions_per_s": exp / wall,
+        "child_nodes_per_s": kids / wall,
+        "hbm_frac_update_kernel": (upd_kernel.get("gbs", 0.0) / PEAK_HBM_GBS) if upd_kernel else None,
+        "roofline": roof, "kernels": kern,
+        "value_iteration": {"sweeps": sweeps, "residual": res, "ms": vi_ms,
+                            "sweeps_per_s": sweeps / (vi_ms * 1e-3)},
+    }
+    if not args.no_cpu_baseline:
+        Q32 = Q.cpu().numpy().reshape(prob.S, prob.A)
+        line["cpu_baseline"] = cpu_baseline(prob, Q32, seeds[:4])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

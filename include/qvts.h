@@ -1,0 +1,190 @@
+/*
+ * qvts.h -- C ABI of the MI355X (gfx950) QV-tree search library, libqvts.so.
+ *
+ * The library runs the data-parallel hot path of QV-Tree Search (Sun &
+ * Kumar, "Stochastic 2-D Motion Planning with a POMDP Framework"): the
+ * frontier-by-frontier expansion of the belief tree (Sec. IV-C, Alg. 2-7)
+ * over a 2-D occupancy grid (Sec. V), the Bayes filter step (Sec. III,
+ * posterior belief update), and the Q-MDP value iteration that scores the
+ * leaves (Sec. V-B, the MDP value iteration; the alpha-vector form of
+ * Sec. IV-A).
+ *
+ * Conventions for every call:
+ *  - Array arguments are DEVICE pointers unless marked "host".  The caller
+ *    owns all memory; the library never allocates device memory in a call:
+ *    scratch space is a caller-provided workspace whose size comes from the
+ *    matching *_workspace_bytes function.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *    work asynchronously on it and return; outputs are valid once the
+ *    stream has been synchronised.  Calls documented as synchronous
+ *    synchronise `stream` themselves before returning.
+ *  - Scalar and host-table checks run on the host before anything is
+ *    enqueued; on such an error nothing is enqueued and outputs are
+ *    untouched.  No exception or abort crosses this boundary.
+ *  - Grid layout: cell s = y*W + x, y = 0 is the top row; "north" is y-1.
+ *    Neighbour index k = (dy+1)*3 + (dx+1) for dy, dx in {-1,0,1}; k = 4 is
+ *    the cell itself (the 3x3 numbering of Sec. V).
+ *  - Observation z = zw + 16*zl: zw holds four wall bits (bit 0 up, bit 1
+ *    left, bit 2 right, bit 3 down: the neighbours N1, N3, N5, N7 of Sec. V,
+ *    1 = occupied, off-grid reads as occupied); zl is 0 ("no landmark") or
+ *    the id 1..L of the landmark the robot stands on.  |Z| = 16*(L+1).
+ */
+#ifndef QVTS_H
+#define QVTS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define QV_OK 0
+#define QV_ERR_INVALID_ARG 1     /* a scalar, size or pointer is out of range */
+#define QV_ERR_NOT_STOCHASTIC 2  /* a slip row is negative or does not sum to 1 */
+#define QV_ERR_BELIEF_INVALID 3  /* (validated calls) belief not a distribution */
+#define QV_ERR_ZERO_LIKELIHOOD 4 /* P(z|b,a) = 0 for a requested observation */
+#define QV_ERR_WORKSPACE 5       /* workspace NULL, misaligned or too small */
+#define QV_ERR_HIP 6             /* a HIP runtime call failed; see qv_last_hip_error */
+#define QV_ERR_UNSUPPORTED 7     /* valid request outside this build's limits */
+
+/* ---- limits ------------------------------------------------------------ */
+#define QV_MAX_ACTIONS 9      /* one action per 3x3 neighbour (Sec. V) */
+#define QV_MAX_DEPTH 6        /* tree depth D (action-observation layers) */
+#define QV_MAX_SAMPLES 16     /* samples per action n */
+#define QV_MAX_LANDMARKS 511
+#define QV_MAX_SIDE 2048      /* W and H */
+#define QV_WORKSPACE_ALIGN 256
+
+/* ---- plan flags -------------------------------------------------------- */
+/* Store the depth-D (leaf) beliefs in the workspace and score them in a
+ * separate pass, instead of scoring each leaf belief as it is produced. */
+#define QV_PLAN_STORE_LEAVES 1
+
+/* ---- problem statement ------------------------------------------------- */
+/* The POMDP tuple (X, A, Z, T, O, R, b0, gamma) of Sec. II, specialised to
+ * the grid world of Sec. V.  X is every cell of the W x H grid (blocked
+ * cells included; beliefs are zero there).  T follows the slip table: under
+ * action a the robot takes neighbour move k with probability slip[a*9+k];
+ * a move aimed at a blocked or off-grid cell leaves it in place (Sec. V,
+ * transitions with occupied cells); the goal cell, if any, is absorbing.
+ * O multiplies the wall-bit likelihoods (bit j read correctly with
+ * probability 1 - flip[j]) by the landmark channel (a landmark cell reports
+ * its id with probability lm_p and "no landmark" otherwise; other cells
+ * always report "no landmark"). */
+typedef struct qv_model {
+  int32_t W, H;             /* grid size, 1..QV_MAX_SIDE */
+  const uint8_t *occ;       /* device [H*W]: 1 = blocked (the map m, Sec. II) */
+  int32_t A;                /* number of actions, 1..QV_MAX_ACTIONS */
+  float slip[81];           /* host: T'(a,k), rows a < A used, each summing to 1 */
+  float flip[4];            /* host: wall-bit misread probabilities, in [0,1] */
+  int32_t L;                /* number of landmarks, 0..QV_MAX_LANDMARKS */
+  const int32_t *lm_cell;   /* device [L]: cell of landmark id l+1, distinct free cells */
+  float lm_p;               /* probability a landmark reports its id, in [0,1] */
+  const float *R;           /* device [S*A]: stage reward R(s,a), row-major by cell */
+  int32_t goal;             /* absorbing goal cell, or -1 */
+  float gamma;              /* discount, in (0,1) */
+} qv_model;
+
+/* Human-readable name of a status code (static storage). */
+const char *qv_status_string(int32_t status);
+
+/* The hipError_t of the last failing HIP call made by this thread. */
+int32_t qv_last_hip_error(void);
+
+/* ---- Bayes filter step (Sec. III, posterior belief update) -------------
+ * For each i < batch:  b'(x') = sum_x T(x,a_i,x') b_i(x),
+ *   p_i = P(z_i|b_i,a_i) = sum_x' O(z_i|x') b'(x'),
+ *   b_out_i(x') = O(z_i|x') b'(x') / p_i.
+ * b, b_out: [batch*S] FP32 (may not overlap); a, z: [batch] int32 (device);
+ * p_out: [batch] FP32.  Rows with p_i = 0 are left untouched in b_out.
+ * Workspace: qv_belief_update_workspace_bytes(m, batch).
+ * check != 0 makes the call synchronous: it then returns
+ * QV_ERR_ZERO_LIKELIHOOD if some p_i = 0 or some a_i, z_i is out of range
+ * (such rows are skipped either way). */
+size_t qv_belief_update_workspace_bytes(const qv_model *m, int32_t batch);
+int32_t qv_belief_update(const qv_model *m, int32_t batch, const float *b,
+                         const int32_t *a, const int32_t *z, float *b_out,
+                         float *p_out, int32_t check, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/* ---- Q-MDP value iteration (Sec. V-B; Sec. IV-A with a perfect sensor) --
+ * Jacobi sweeps from V_0 = 0:
+ *   Q_k(s,a) = R(s,a) + gamma * sum_s' T(s,a,s') V_k(s'),
+ *   V_{k+1}(s) = max_a Q_k(s,a),  (blocked cells: Q = V = 0),
+ * in FP32, with the residual r_k = max_s |V_{k+1}(s) - V_k(s)| formed in
+ * FP64.  Stops after the first sweep with r_k = 0 or
+ * r_k <= tol * max(1, max_s |V_{k+1}(s)|), or after max_sweeps sweeps.
+ * Q: [S*A] FP32 output, Q_k of the last sweep.  Synchronous: on return
+ * *residual_out (host) and *sweeps_out (host) hold r_k and k. */
+size_t qv_vi_workspace_bytes(const qv_model *m, int32_t max_sweeps);
+int32_t qv_value_iterate(const qv_model *m, float tol, int32_t max_sweeps,
+                         float *Q, double *residual_out, int32_t *sweeps_out,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* ---- one planning step (Alg. 1 inner loop + getOptimalAction) ---------
+ * Builds the QV-tree of depth D from b0 level by level: every V-node is
+ * expanded with all |A| actions (Alg. 2); each Q-node predicts, forms
+ * P(z|b,a) over all z, draws n observations (Alg. 3/4; inverse-CDF draws on
+ * the exact P(z|b,a), uniforms from Philox4x32-10 with key = seed and
+ * counter (a*ceil(n/4) + k/4, slot, level, query_id), word k%4, u = (r>>8)
+ * * 2^-24), keeps each distinct z once with its frequency f, and makes the
+ * child belief Phi(b,a,z) (Sec. III).  Leaves at depth D score
+ * max_a' sum_s b(s) Q(s,a') (Alg. 5 with the Q-MDP alpha vectors).  The
+ * backup is Q(v,a) = R(b_v,a) + gamma * sum_children (f/n) V(child) and
+ * V(v) = max_a Q(v,a) (Alg. 6/7); the action is the lowest a whose root
+ * Q-value is within 1e-9 of the maximum.
+ * Q: [S*A] FP32 leaf table; b0: [S] FP32 start belief (a distribution with
+ * no mass on blocked cells); action_out: [1] int32; rootQ_out: [A] FP32.
+ * The tree records stay in the workspace afterwards (qv_plan_layout). */
+size_t qv_plan_workspace_bytes(const qv_model *m, int32_t D, int32_t n, int32_t flags);
+int32_t qv_plan_step(const qv_model *m, const float *Q, const float *b0,
+                     int32_t D, int32_t n, uint64_t seed, uint32_t query_id,
+                     int32_t flags, int32_t *action_out, float *rootQ_out,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* Where qv_plan_step leaves the tree in its workspace.  Node records are
+ * indexed by capacity slot: level d holds K^d slots (K = A*n), the children
+ * of slot s under action a are slots s*K + a*n + r for r = 0,1,... in
+ * ascending z, and level d starts at global slot level_first[d].  Offsets
+ * are byte offsets from the workspace base; arrays span all levels unless
+ * noted.  A field of value 0 for belief_offset[d] means "not stored". */
+typedef struct qv_tree_layout {
+  int32_t D, n, K, A, S;
+  int32_t tile_rows, tiles;        /* rows per tile and tiles per belief */
+  int64_t level_slots[QV_MAX_DEPTH + 1];
+  int64_t level_first[QV_MAX_DEPTH + 2];
+  size_t valid;       /* int32 [slots]: 1 if the node exists */
+  size_t z;           /* int32 [slots]: observation that created it (levels >= 1) */
+  size_t count;       /* int32 [slots]: frequency f among the n draws */
+  size_t pz;          /* float [slots]: P(z|b_parent,a) */
+  size_t value;       /* float [slots]: V of the node */
+  size_t qvalue;      /* float [slots*A]: Q-node values (levels < D) */
+  size_t reward;      /* float [slots*A]: R(b,a) (levels < D) */
+  size_t belief_offset[QV_MAX_DEPTH + 1];  /* float [level_slots[d]*S] */
+  size_t total_bytes;
+} qv_tree_layout;
+int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
+                       qv_tree_layout *out /* host */);
+
+/* ---- kernel timing (benchmarking aid) ----------------------------------
+ * While enabled, each kernel the library launches is bracketed by two
+ * hipEvents recorded on its launch stream.  qv_timing_read (after the
+ * caller has synchronised those streams) returns, per kernel name, the
+ * number of launches and the summed event-to-event time, then clears the
+ * records.  qv_timing_enable(on) also clears them.  Host-side only; not
+ * meant for concurrent use from several threads. */
+typedef struct qv_kernel_time {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+} qv_kernel_time;
+int32_t qv_timing_enable(int32_t on);
+int32_t qv_timing_read(qv_kernel_time *out /* host [max_entries] */, int32_t max_entries,
+                       int32_t *n_out /* host */);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QVTS_H */

@@ -91,6 +91,10 @@ def lib():
         L.qvo_tree_slots.restype = C.c_long
         L.qvo_plan.argtypes = [mp, dp, dp, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
                               C.c_int, ip, dp, C.POINTER(_Dump), C.POINTER(C.c_long)]
+        L.qvo_expand_node.argtypes = [mp, dp, C.c_int, C.c_long, C.c_int, C.c_uint64,
+                                      C.c_uint32, ip, ip, ip, dp, dp, dp, dp]
+        L.qvo_leaf_score.argtypes = [mp, dp, dp]
+        L.qvo_leaf_score.restype = C.c_double
         L.qvo_filter_nll_grad.argtypes = [mp, dp, dp, C.c_int, C.c_int, dp, ip, ip,
                                          dp, dp, dp]
         _lib = L
@@ -259,6 +263,38 @@ def plan(prob, Q, b0=None, D=None, n=None, seed=None, qid=None, full=False,
                         C.byref(ex))
     assert st == 0, st
     return dict(action=act.value, rootQ=rq, expansions=ex.value, dump=dump)
+
+
+def expand_node(prob, b, d, slot, n=None, seed=None, qid=None, beliefs=True):
+    """One V-node expansion of belief b at (level d, capacity slot); returns a
+    dict of per-(action, rank) child records, child beliefs and R(b, a)."""
+    m = Model(prob)
+    n = prob.n if n is None else n
+    seed = prob.seed if seed is None else seed
+    qid = prob.query_id if qid is None else qid
+    b = _f64(b)
+    K = m.A * n
+    valid = np.zeros(K, np.int32)
+    z = np.zeros(K, np.int32)
+    cnt = np.zeros(K, np.int32)
+    pz = np.zeros(K)
+    mg = np.zeros(K)
+    bel = np.zeros(K * m.S) if beliefs else None
+    rb = np.zeros(m.A)
+    st = lib().qvo_expand_node(m.ref, _ptr(b, C.c_double), int(d), int(slot), int(n),
+                               C.c_uint64(seed), int(qid), _ptr(valid, C.c_int), _ptr(z, C.c_int),
+                               _ptr(cnt, C.c_int), _ptr(pz, C.c_double), _ptr(mg, C.c_double),
+                               _ptr(bel, C.c_double) if beliefs else None, _ptr(rb, C.c_double))
+    assert st == 0, st
+    return dict(valid=valid, z=z, count=cnt, pz=pz, margin=mg, rb=rb,
+                beliefs=bel.reshape(K, m.S) if beliefs else None)
+
+
+def leaf_score(prob, Q, b) -> float:
+    m = Model(prob)
+    Qd = _f64(Q).reshape(-1)
+    b = _f64(b)
+    return float(lib().qvo_leaf_score(m.ref, _ptr(Qd, C.c_double), _ptr(b, C.c_double)))
 
 
 def filter_nll_grad(prob, theta, phi, acts, obs, b0=None):

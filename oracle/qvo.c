@@ -371,6 +371,31 @@ typedef struct {
   long expansions;
 } qvo_tree;
 
+/* Alg. 3, forwardSampling then "unique measurements and frequencies": the n
+ * observation draws of the Q-node (level d, slot, action a) from P(z|b,a)
+ * given as p[Z], returned as distinct values zu[] in ascending order with
+ * their counts fu[]; returns how many there are. */
+static int qvo_qnode_draws(int Z, const double *p, uint64_t seed, uint32_t qid, int d,
+                           long slot, int a, int n, int *zu, int *fu, double *margins) {
+  int zs[64];
+  for (int k = 0; k < n; k++) {
+    double u = qvo_obs_uniform(seed, qid, d, (uint32_t)slot, a, n, k);
+    double mg;
+    zs[k] = qvo_draw(p, Z, u, &mg);
+    if (margins) margins[k] = mg;
+  }
+  for (int i = 1; i < n; i++)     /* insertion sort, ascending z */
+    for (int j = i; j > 0 && zs[j - 1] > zs[j]; j--) { int x = zs[j]; zs[j] = zs[j - 1]; zs[j - 1] = x; }
+  int U = 0;
+  for (int i = 0; i < n; ) {
+    int j = i;
+    while (j < n && zs[j] == zs[i]) j++;
+    if (zs[i] >= 0) { zu[U] = zs[i]; fu[U] = j - i; U++; }
+    i = j;
+  }
+  return U;
+}
+
 /* U_V(b) = max_a sum_s b(s) Q(s,a): the alpha-vector value of Eq. (PWLC form)
  * with the Q-MDP vectors as the offline bound (Alg. 5). */
 static double qvo_leaf_value(const qvo_tree *t, const double *b) {
@@ -408,20 +433,11 @@ static double qvo_vnode(qvo_tree *t, const double *b, int d, long slot,
     double q = rb;
     if (!t->full) {
       /* n forward samples, then unique observations with frequencies */
-      int zs[64];
-      for (int k = 0; k < t->n; k++) {
-        double u = qvo_obs_uniform(t->seed, t->qid, d, (uint32_t)slot, a, t->n, k);
-        double mg;
-        zs[k] = qvo_draw(p, t->Z, u, &mg);
-        if (dp && dp->margin) dp->margin[((size_t)gslot * t->A + a) * t->n + k] = mg;
-      }
-      for (int i = 1; i < t->n; i++)     /* insertion sort, ascending z */
-        for (int j = i; j > 0 && zs[j - 1] > zs[j]; j--) { int x = zs[j]; zs[j] = zs[j - 1]; zs[j - 1] = x; }
-      int r = 0;
-      for (int i = 0; i < t->n; ) {
-        int j = i;
-        while (j < t->n && zs[j] == zs[i]) j++;
-        int z = zs[i], f = j - i;
+      int zu[64], fu[64];
+      double *mg = (dp && dp->margin) ? dp->margin + ((size_t)gslot * t->A + a) * t->n : NULL;
+      int U = qvo_qnode_draws(t->Z, p, t->seed, t->qid, d, slot, a, t->n, zu, fu, mg);
+      for (int r = 0; r < U; r++) {
+        int z = zu[r], f = fu[r];
         long cslot = slot * t->K + (long)a * t->n + r;
         long cg = t->level_off[d + 1] + cslot;
         qvo_bayes(m, t->lm, bp, z, p[z], child);
@@ -435,8 +451,6 @@ static double qvo_vnode(qvo_tree *t, const double *b, int d, long slot,
         /* Alg. 6 with the discount of the Bellman equation and the
          * normalised sampling frequency as the child weight */
         q += m->gamma * ((double)f / (double)t->n) * v;
-        r++;
-        i = j;
       }
     } else {
       /* full expansion: every observation of positive probability, weighted
@@ -531,6 +545,56 @@ done:
   if (t.bp) for (int d = 0; d < D; d++) { free(t.bp[d]); free(t.p[d]); free(t.child[d]); }
   free(t.bp); free(t.p); free(t.child); free(t.level_off); free(lm);
   return st;
+}
+
+/* One V-node expansion (Alg. 2 with Alg. 3 for every action) of belief b
+ * sitting at capacity slot `slot` of level d, without recursing: for each
+ * action a and rank r < n, the child records at index a*n + r (valid, z,
+ * count, P(z|b,a), draw margins) and, if beliefs != NULL, the child beliefs
+ * [A*n*S]; rb[a] = R(b,a).  Lets a test check any single node of a large
+ * tree from its parent belief. */
+int qvo_expand_node(const qvo_model *m, const double *b, int d, long slot, int n,
+                    uint64_t seed, uint32_t qid, int *valid, int *z, int *count,
+                    double *pz, double *margin, double *beliefs, double *rb) {
+  int S = m->W * m->H, Z = 16 * (m->L + 1), A = m->A;
+  if (n < 1 || n > 64) return QVO_ERR_ARG;
+  int *lm = qvo_landmark_map(m);
+  double *bp = (double *)malloc(sizeof(double) * (size_t)S);
+  double *p = (double *)malloc(sizeof(double) * (size_t)Z);
+  int st = QVO_OK;
+  if (!lm || !bp || !p) { st = QVO_ERR_MEM; goto done; }
+  for (int a = 0; a < A; a++) {
+    qvo_predict(m, b, a, bp);
+    qvo_likelihood_lm(m, lm, bp, p);
+    double r = 0.0;
+    for (int s = 0; s < S; s++) r += m->R[(size_t)s * A + a] * b[s];
+    rb[a] = r;
+    int zu[64], fu[64];
+    int U = qvo_qnode_draws(Z, p, seed, qid, d, slot, a, n, zu, fu, margin + (size_t)a * n);
+    for (int i = 0; i < n; i++) {
+      int c = a * n + i;
+      valid[c] = i < U;
+      z[c] = i < U ? zu[i] : -1;
+      count[c] = i < U ? fu[i] : 0;
+      pz[c] = i < U ? p[zu[i]] : 0.0;
+      if (beliefs && i < U) qvo_bayes(m, lm, bp, zu[i], p[zu[i]], beliefs + (size_t)c * S);
+    }
+  }
+done:
+  free(lm); free(bp); free(p);
+  return st;
+}
+
+/* The leaf score max_a sum_s b(s) Q(s,a) of Alg. 5 (Q-MDP alpha vectors). */
+double qvo_leaf_score(const qvo_model *m, const double *Q, const double *b) {
+  int S = m->W * m->H;
+  double best = -INFINITY;
+  for (int a = 0; a < m->A; a++) {
+    double v = 0.0;
+    for (int s = 0; s < S; s++) v += b[s] * Q[(size_t)s * m->A + a];
+    if (v > best) best = v;
+  }
+  return best;
 }
 
 /* ------------------------------------------------------------------------ */

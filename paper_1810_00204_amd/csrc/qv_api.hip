@@ -1,0 +1,253 @@
+// qv_api.hip -- the extern "C" entry points of libqvts: host-side checks of
+// the problem statement (the tuple of Sec. II with the grid world of
+// Sec. V), workspace layouts, and dispatch to the kernels.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+#include "qv_internal.h"
+
+namespace qv {
+
+static thread_local int32_t g_last_hip = 0;
+
+static int32_t hip_status(hipError_t e) {
+  if (e == hipSuccess) return QV_OK;
+  g_last_hip = (int32_t)e;
+  return QV_ERR_HIP;
+}
+
+// Cells per band of rows processed by one workgroup (whole rows).
+int tile_rows(int W, int H) {
+  static int target = 0;
+  if (target == 0) {
+    const char *e = std::getenv("QVTS_TILE_CELLS");
+    int t = e ? std::atoi(e) : 0;
+    target = (t >= 64 && t <= (1 << 20)) ? t : 4096;
+  }
+  int th = target / (W > 0 ? W : 1);
+  if (th < 1) th = 1;
+  if (th > H) th = H;
+  return th;
+}
+
+DevModel make_dev_model(const qv_model *m) {
+  DevModel d;
+  std::memset(&d, 0, sizeof d);
+  d.W = m->W;
+  d.H = m->H;
+  d.S = m->W * m->H;
+  d.A = m->A;
+  d.L = m->L;
+  d.goal = m->goal;
+  d.gamma = m->gamma;
+  d.lm_p = m->lm_p;
+  for (int i = 0; i < 9 * m->A; ++i) d.slip[i] = m->slip[i];
+  for (int j = 0; j < 4; ++j) d.flip[j] = m->flip[j];
+  d.occ = m->occ;
+  d.lm_cell = m->lm_cell;
+  d.R = m->R;
+  return d;
+}
+
+static int32_t check_model(const qv_model *m) {
+  if (!m) return QV_ERR_INVALID_ARG;
+  if (m->W < 1 || m->H < 1 || m->W > QV_MAX_SIDE || m->H > QV_MAX_SIDE) return QV_ERR_INVALID_ARG;
+  if (m->A < 1 || m->A > QV_MAX_ACTIONS) return QV_ERR_INVALID_ARG;
+  if (m->L < 0 || m->L > QV_MAX_LANDMARKS) return QV_ERR_INVALID_ARG;
+  if (!m->occ || !m->R || (m->L > 0 && !m->lm_cell)) return QV_ERR_INVALID_ARG;
+  const long long S = (long long)m->W * m->H;
+  if (m->goal < -1 || m->goal >= S) return QV_ERR_INVALID_ARG;
+  if (!(m->gamma > 0.f && m->gamma < 1.f)) return QV_ERR_INVALID_ARG;
+  if (!(m->lm_p >= 0.f && m->lm_p <= 1.f)) return QV_ERR_INVALID_ARG;
+  for (int j = 0; j < 4; ++j)
+    if (!(m->flip[j] >= 0.f && m->flip[j] <= 1.f)) return QV_ERR_INVALID_ARG;
+  for (int a = 0; a < m->A; ++a) {
+    double s = 0.0;
+    for (int k = 0; k < 9; ++k) {
+      const float v = m->slip[a * 9 + k];
+      if (!(v >= 0.f) || !std::isfinite(v)) return QV_ERR_NOT_STOCHASTIC;
+      s += v;
+    }
+    if (std::fabs(s - 1.0) > 1e-5) return QV_ERR_NOT_STOCHASTIC;
+  }
+  return QV_OK;
+}
+
+static bool ws_ok(const void *ws, size_t have, size_t need) {
+  if (need == 0) return true;
+  return ws && have >= need && ((uintptr_t)ws % QV_WORKSPACE_ALIGN) == 0;
+}
+
+// Workspace of a planning query.  Returns false when the tree does not fit
+// this build's index ranges.
+static bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L) {
+  std::memset(L, 0, sizeof *L);
+  qv_tree_layout &T = L->pub;
+  const long long S = (long long)m->W * m->H;
+  const int A = m->A, K = A * n;
+  T.D = D;
+  T.n = n;
+  T.K = K;
+  T.A = A;
+  T.S = (int32_t)S;
+  T.tile_rows = tile_rows(m->W, m->H);
+  T.tiles = (m->H + T.tile_rows - 1) / T.tile_rows;
+  long long tot = 0, lv = 1;
+  for (int d = 0; d <= D; ++d) {
+    T.level_slots[d] = lv;
+    T.level_first[d] = tot;
+    tot += lv;
+    if (d < D) {
+      lv *= K;
+      if (lv > (1LL << 26)) return false;
+    }
+  }
+  T.level_first[D + 1] = tot;
+  if (T.level_slots[D] * T.tiles >= (1LL << 31)) return false;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes, 256);
+    return o;
+  };
+  L->sig = take((size_t)S * 4);
+  L->staytab = take((size_t)A * 256 * 4);
+  T.valid = take((size_t)tot * 4);
+  T.z = take((size_t)tot * 4);
+  T.count = take((size_t)tot * 4);
+  T.pz = take((size_t)tot * 4);
+  T.value = take((size_t)tot * 4);
+  T.qvalue = take((size_t)tot * A * 4);
+  T.reward = take((size_t)tot * A * 4);
+  const bool store = (flags & QV_PLAN_STORE_LEAVES) != 0;
+  for (int d = 1; d <= D; ++d)
+    if (d < D || store) T.belief_offset[d] = take((size_t)T.level_slots[d] * S * 4);
+  long long ps = 1;
+  for (int d = 0; d < D; ++d) ps = std::max<long long>(ps, T.level_slots[d]);
+  L->part_slots = (size_t)ps;
+  L->part = take((size_t)ps * A * T.tiles * 17 * 4);
+  L->lmv = take((size_t)ps * A * (m->L > 0 ? m->L : 1) * 4);
+  L->leafpart = take((size_t)T.level_slots[D] * T.tiles * A * 4);
+  L->err = take(256);
+  T.total_bytes = off;
+  return true;
+}
+
+}  // namespace qv
+
+using namespace qv;
+
+extern "C" {
+
+const char *qv_status_string(int32_t s) {
+  switch (s) {
+    case QV_OK: return "ok";
+    case QV_ERR_INVALID_ARG: return "invalid argument";
+    case QV_ERR_NOT_STOCHASTIC: return "slip row is not a probability distribution";
+    case QV_ERR_BELIEF_INVALID: return "belief is not a distribution over free cells";
+    case QV_ERR_ZERO_LIKELIHOOD: return "observation has zero likelihood";
+    case QV_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+    case QV_ERR_HIP: return "HIP runtime error";
+    case QV_ERR_UNSUPPORTED: return "request outside the limits of this build";
+    default: return "unknown status";
+  }
+}
+
+int32_t qv_last_hip_error(void) { return g_last_hip; }
+
+size_t qv_belief_update_workspace_bytes(const qv_model *m, int32_t batch) {
+  if (check_model(m) != QV_OK || batch < 0) return 0;
+  return belief_update_ws(m, batch);
+}
+
+int32_t qv_belief_update(const qv_model *m, int32_t batch, const float *b, const int32_t *a,
+                         const int32_t *z, float *b_out, float *p_out, int32_t check, void *ws,
+                         size_t ws_bytes, void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (batch < 0) return QV_ERR_INVALID_ARG;
+  if (batch > 0 && (!b || !a || !z || !b_out || !p_out)) return QV_ERR_INVALID_ARG;
+  const size_t S = (size_t)m->W * m->H;
+  if (batch > 0 && (const void *)b < (const void *)(b_out + (size_t)batch * S) &&
+      (const void *)b_out < (const void *)(b + (size_t)batch * S))
+    return QV_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, belief_update_ws(m, batch))) return QV_ERR_WORKSPACE;
+  hipStream_t hs = (hipStream_t)stream;
+  const DevModel dm = make_dev_model(m);
+  st = hip_status(launch_belief_update(dm, batch, b, a, z, b_out, p_out, (char *)ws, hs));
+  if (st != QV_OK || !check) return st;
+  const size_t TH = tile_rows(m->W, m->H);
+  const size_t tiles = (m->H + TH - 1) / TH;
+  size_t off = align_up(S * 4, 256) + align_up((size_t)m->A * 256 * 4, 256) +
+               align_up((size_t)batch * tiles * 4, 256);
+  int32_t herr = 0;
+  st = hip_status(hipMemcpyAsync(&herr, (char *)ws + off, 4, hipMemcpyDeviceToHost, hs));
+  if (st != QV_OK) return st;
+  st = hip_status(hipStreamSynchronize(hs));
+  if (st != QV_OK) return st;
+  if (herr & (4 | 8)) return QV_ERR_ZERO_LIKELIHOOD;
+  if (herr) return QV_ERR_INVALID_ARG;
+  return QV_OK;
+}
+
+size_t qv_vi_workspace_bytes(const qv_model *m, int32_t max_sweeps) {
+  if (check_model(m) != QV_OK || max_sweeps < 1) return 0;
+  return vi_ws(m, max_sweeps);
+}
+
+int32_t qv_value_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *Q,
+                         double *residual_out, int32_t *sweeps_out, void *ws, size_t ws_bytes,
+                         void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (max_sweeps < 1 || !(tol >= 0.f) || !Q || !residual_out || !sweeps_out)
+    return QV_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, vi_ws(m, max_sweeps))) return QV_ERR_WORKSPACE;
+  const DevModel dm = make_dev_model(m);
+  double r = 0.0;
+  int k = 0;
+  st = hip_status(run_value_iteration(dm, tol, max_sweeps, Q, &r, &k, (char *)ws,
+                                      (hipStream_t)stream));
+  if (st != QV_OK) return st;
+  *residual_out = r;
+  *sweeps_out = k;
+  return QV_OK;
+}
+
+size_t qv_plan_workspace_bytes(const qv_model *m, int32_t D, int32_t n, int32_t flags) {
+  if (check_model(m) != QV_OK || D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES)
+    return 0;
+  PlanLayout L;
+  if (!plan_layout_impl(m, D, n, flags, &L)) return 0;
+  return L.pub.total_bytes;
+}
+
+int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
+                       qv_tree_layout *out) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (!out || D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES)
+    return QV_ERR_INVALID_ARG;
+  PlanLayout L;
+  if (!plan_layout_impl(m, D, n, flags, &L)) return QV_ERR_UNSUPPORTED;
+  *out = L.pub;
+  return QV_OK;
+}
+
+int32_t qv_plan_step(const qv_model *m, const float *Q, const float *b0, int32_t D, int32_t n,
+                     uint64_t seed, uint32_t query_id, int32_t flags, int32_t *action_out,
+                     float *rootQ_out, void *ws, size_t ws_bytes, void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES) return QV_ERR_INVALID_ARG;
+  if (!Q || !b0 || !action_out || !rootQ_out) return QV_ERR_INVALID_ARG;
+  if (flags & ~QV_PLAN_STORE_LEAVES) return QV_ERR_INVALID_ARG;
+  PlanLayout L;
+  if (!plan_layout_impl(m, D, n, flags, &L)) return QV_ERR_UNSUPPORTED;
+  if (!ws_ok(ws, ws_bytes, L.pub.total_bytes)) return QV_ERR_WORKSPACE;
+  return hip_status(launch_plan(m, Q, b0, D, n, seed, query_id, flags, action_out, rootQ_out,
+                                (char *)ws, L, (hipStream_t)stream));
+}
+
+}  // extern "C"

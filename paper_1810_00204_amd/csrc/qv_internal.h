@@ -1,0 +1,89 @@
+// qv_internal.h -- host-side structures shared by the translation units of
+// libqvts (workspace layouts, per-level launch arguments, launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/qvts.h"
+#include "qv_device.h"
+
+namespace qv {
+
+// Record arrays and scratch of one planning query, as device pointers.
+struct PlanPtrs {
+  int32_t *valid, *z, *count;
+  float *pz, *value, *qvalue, *reward;
+  float *belief[QV_MAX_DEPTH + 1];
+  uint32_t *sig;
+  float *staytab;   // [A][256] stay probability by blocked-neighbour pattern
+  float *part;      // [slots_d][A][tiles][17] wall-pattern histograms + R(b,a)
+  float *lmv;       // [slots_d][A][L] predicted mass on landmark cells
+  float *leafpart;  // [slots_D][tiles][A]
+  int32_t *err;
+};
+
+// Byte layout of the plan workspace.
+struct PlanLayout {
+  qv_tree_layout pub;
+  size_t sig, staytab, part, lmv, leafpart, err;
+  size_t part_slots;   // max slots of a non-leaf level
+};
+
+// Per-level kernel arguments (passed by value).
+struct LevelArgs {
+  int d, nslots, tiles, TH, n, K;
+  uint32_t key0, key1, qid;
+  const float *pbel;      // parent beliefs [nslots*S]
+  const int32_t *pvalid;  // [nslots]
+  float *part, *lmv;
+  int32_t *cvalid, *cz, *ccount;
+  float *cpz;             // child records (level d+1), [nslots*K]
+  float *reward;          // level d [nslots*A]
+  float *cbel;            // child beliefs [nslots*K*S] or null
+  float *leafpart;        // [nslots*K*tiles*A] or null
+  const float *Q;
+  const uint32_t *sig;
+  const float *staytab;
+};
+
+int tile_rows(int W, int H);
+void plan_layout(const qv_model *m, int D, int n, int flags, PlanLayout *L);
+DevModel make_dev_model(const qv_model *m);
+
+// launchers (return hipError_t)
+hipError_t launch_plan(const qv_model *m, const float *Q, const float *b0, int D, int n,
+                       uint64_t seed, uint32_t qid, int flags, int32_t *action_out,
+                       float *rootQ_out, char *ws, const PlanLayout &L, hipStream_t st);
+hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
+                       hipStream_t st);
+hipError_t launch_belief_update(const DevModel &dm, int batch, const float *b,
+                                const int32_t *a, const int32_t *z, float *b_out,
+                                float *p_out, char *ws, hipStream_t st);
+size_t belief_update_ws(const qv_model *m, int batch);
+hipError_t run_value_iteration(const DevModel &dm, float tol, int max_sweeps, float *Q,
+                               double *residual, int *sweeps, char *ws, hipStream_t st);
+size_t vi_ws(const qv_model *m, int max_sweeps);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Brackets one kernel launch with timing events while timing is enabled.
+class TimingScope {
+ public:
+  TimingScope(const char *name, hipStream_t st);
+  ~TimingScope();
+
+ private:
+  const char *name_;
+  hipStream_t st_;
+  void *ev_;
+};
+
+#define QV_LAUNCH(kernel, grid, block, lds, st, ...)                        \
+  do {                                                                      \
+    ::qv::TimingScope qv_ts_(#kernel, st);                                  \
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);          \
+  } while (0)
+
+}  // namespace qv

@@ -1,0 +1,101 @@
+"""Convenience layer over the C ABI: device buffers and workspaces for one
+problem, and readers for the tree records the library leaves in its
+workspace.  All computation happens in libqvts.so."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import binding as B
+
+
+class Planner:
+    def __init__(self, prob, device="cuda", flags: int = 0, D=None, n=None):
+        import torch
+        self.torch = torch
+        self.prob = prob
+        self.device = device
+        self.flags = flags
+        self.D = prob.D if D is None else D
+        self.n = prob.n if n is None else n
+        self.m = B.DeviceModel(prob, device)
+        nb = B.qv_plan_workspace_bytes(self.m, self.D, self.n, flags)
+        if nb == 0:
+            raise B.QvError(B.QV_ERR_UNSUPPORTED, "qv_plan_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        st, self.layout = B.qv_plan_layout(self.m, self.D, self.n, flags)
+        B.check(st, "qv_plan_layout")
+        self.action = torch.zeros(1, dtype=torch.int32, device=device)
+        self.rootQ = torch.zeros(self.m.A, dtype=torch.float32, device=device)
+        self.b0 = torch.as_tensor(np.ascontiguousarray(prob.b0, np.float32)).to(device)
+
+    # -- offline Q-MDP values ---------------------------------------------
+    def value_iterate(self, tol=1e-6, max_sweeps=10000):
+        torch = self.torch
+        Q = torch.empty(self.m.S * self.m.A, dtype=torch.float32, device=self.device)
+        ws = torch.empty(B.qv_vi_workspace_bytes(self.m, max_sweeps), dtype=torch.uint8,
+                         device=self.device)
+        st, res, sw = B.qv_value_iterate(self.m, tol, max_sweeps, Q, ws)
+        B.check(st, "qv_value_iterate")
+        return Q, res, sw
+
+    # -- one planning step ------------------------------------------------
+    def plan(self, Q, b0=None, seed=None, query_id=None, stream=None):
+        prob = self.prob
+        st = B.qv_plan_step(self.m, Q, self.b0 if b0 is None else b0, self.D, self.n,
+                            prob.seed if seed is None else seed,
+                            prob.query_id if query_id is None else query_id, self.flags,
+                            self.action, self.rootQ, self.ws, stream)
+        B.check(st, "qv_plan_step")
+        return self.action, self.rootQ
+
+    # -- tree records -----------------------------------------------------
+    def tree(self, beliefs: bool = True) -> dict:
+        """Copies the tree records out of the workspace (after a sync)."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        L = self.layout
+        tot = int(L.level_first[L.D + 1])
+        A, S = L.A, L.S
+        raw = self.ws
+
+        def arr(off, count, dt):
+            nbytes = count * np.dtype(dt).itemsize
+            return raw[off:off + nbytes].cpu().numpy().view(dt).copy()
+
+        out = dict(valid=arr(L.valid, tot, np.int32), z=arr(L.z, tot, np.int32),
+                   count=arr(L.count, tot, np.int32), pz=arr(L.pz, tot, np.float32),
+                   value=arr(L.value, tot, np.float32),
+                   qvalue=arr(L.qvalue, tot * A, np.float32),
+                   reward=arr(L.reward, tot * A, np.float32),
+                   level_first=[int(L.level_first[d]) for d in range(L.D + 2)],
+                   level_slots=[int(L.level_slots[d]) for d in range(L.D + 1)],
+                   tiles=int(L.tiles), tile_rows=int(L.tile_rows))
+        if beliefs:
+            out["beliefs"] = {}
+            for d in range(1, L.D + 1):
+                off = int(L.belief_offset[d])
+                if off:
+                    out["beliefs"][d] = arr(off, int(L.level_slots[d]) * S, np.float32).reshape(-1, S)
+        return out
+
+    def belief_of(self, d: int, slot: int):
+        """One stored belief of level d as a float32 numpy array."""
+        L = self.layout
+        off = int(L.belief_offset[d])
+        if not off:
+            raise ValueError(f"level {d} beliefs are not stored")
+        S = L.S
+        start = off + slot * S * 4
+        return self.ws[start:start + S * 4].cpu().numpy().view(np.float32).copy()
+
+
+def belief_update(m: B.DeviceModel, b, a, z, check: bool = True, stream=None):
+    """Batched filter step on device tensors; returns (b_out, p_out, status)."""
+    import torch
+    batch = int(a.numel())
+    b_out = torch.zeros_like(b)
+    p_out = torch.zeros(batch, dtype=torch.float32, device=b.device)
+    ws = torch.empty(max(B.qv_belief_update_workspace_bytes(m, batch), 1), dtype=torch.uint8,
+                     device=b.device)
+    st = B.qv_belief_update(m, batch, b, a, z, b_out, p_out, 1 if check else 0, ws, stream)
+    return b_out, p_out, st
