@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--banded", action="store_true",
+                    help="force the banded multi-pass kernels (QV_PLAN_TILED)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (PMC byte-count calibration)")
     return ap.parse_args()
@@ -53,20 +55,32 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def kernel_models(prob, counts):
-    """Algorithmic FP32 flops and HBM bytes of each kernel launch of one plan,
-    from the numbers of valid nodes per level.
-    Returns {kernel: [(flops, bytes) per launch in launch order]}."""
+def kernel_work(name, prob, counts):
+    """Algorithmic FP32 flops, HBM bytes and the bounding resource of one
+    launch of a per-level planning kernel ("<kernel>@L<d>"), from the numbers
+    of valid nodes per level.  None for others."""
+    if "@L" not in name:
+        return None
+    base, lvl = name.rsplit("@L", 1)
+    d = int(lvl)
     S, A, D = prob.S, prob.A, prob.D
-    out = {"k_stats": [], "k_update": [], "k_leaf": []}
-    for d in range(D):
-        P, C = counts[d], counts[d + 1]
-        out["k_stats"].append((P * S * A * 21.0, P * S * 4.0))
-        if d < D - 1:
-            out["k_update"].append((P * S * A * 18.0 + C * S * 6.0, P * S * 4.0 + C * S * 4.0))
-        else:
-            out["k_leaf"].append((P * S * A * 18.0 + C * S * (6.0 + 2 * A), P * S * 4.0))
-    return out
+    P, C = counts[d], counts[d + 1]
+    leaf = d == D - 1
+    stencil = P * A * S * 18.0          # 9 FMA per (parent, action, cell)
+    stats = P * A * S * 3.0             # bin add, R(b,a) FMA
+    child = C * S * 6.0                 # O product, normalisation
+    score = C * S * 2.0 * A             # A FMAs against Q per leaf cell
+    if "k_node" in base:
+        if leaf:
+            return stencil + stats + child + score, P * S * 4.0, "alu"
+        return stencil + stats + child, P * S * 4.0 + C * S * 4.0, "hbm"
+    if "k_stats" in base:
+        return stencil + stats, P * S * 4.0, "alu"
+    if "k_update" in base:
+        return stencil + child, P * S * 4.0 + C * S * 4.0, "hbm"
+    if "k_leaf" in base:
+        return stencil + child + score, P * S * 4.0, "alu"
+    return None
 
 
 def cpu_baseline(prob, Q32, seeds):
@@ -102,7 +116,7 @@ def main():
     B.lib()
     dev = "cuda:0"
     prob = wl.make_rect(seed=0)
-    pl = Planner(prob, device=dev)
+    pl = Planner(prob, device=dev, flags=B.QV_PLAN_TILED if args.banded else 0)
 
     # offline Q-MDP values (timed on its own)
     torch.cuda.synchronize()
@@ -153,21 +167,19 @@ def main():
     kern = {}
     tot_ms = sum(v[1] for v in ktimes.values())
     for name, (launches, ms) in ktimes.items():
-        kern[name] = {"launches": launches, "avg_us": 1e3 * ms / launches,
-                      "share": ms / tot_ms if tot_ms else None}
-    per_plan = {s: kernel_models(prob, counts[s]) for s in seeds}
-    for name in ("k_stats", "k_update", "k_leaf"):
-        if name not in kern:
-            continue
-        fl = sum(f for s in step_seeds for f, _ in per_plan[s][name])
-        by = sum(b for s in step_seeds for _, b in per_plan[s][name])
-        n = sum(len(per_plan[s][name]) for s in step_seeds)
-        ms = ktimes[name][1]
-        kern[name].update({"alg_gflop_per_launch": fl / n / 1e9, "alg_mb_per_launch": by / n / 1e6,
-                           "tflops": fl / (ms * 1e-3) / 1e12, "gbs": by / (ms * 1e-3) / 1e9})
+        e = {"launches": launches, "avg_us": 1e3 * ms / launches,
+             "share": ms / tot_ms if tot_ms else None}
+        work = [kernel_work(name, prob, counts[s]) for s in step_seeds]
+        if work[0] is not None:
+            fl = sum(w[0] for w in work)
+            by = sum(w[1] for w in work)
+            e.update({"bound": work[0][2], "alg_gflop_per_launch": fl / len(work) / 1e9,
+                      "alg_mb_per_launch": by / len(work) / 1e6,
+                      "tflops": fl / (ms * 1e-3) / 1e12, "gbs": by / (ms * 1e-3) / 1e9})
+        kern[name] = e
     dom = max(ktimes, key=lambda k: ktimes[k][1])
     roof = {"kernel": dom}
-    if dom in ("k_stats", "k_leaf"):
+    if kern[dom].get("bound") == "alu":
         roof.update({"bound": "alu", "achieved": kern[dom]["tflops"], "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s"})
     else:
@@ -179,7 +191,8 @@ def main():
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("source_hash") == source_hash() and dom in tr.get("kernels", {}):
             roof["traffic"] = tr["kernels"][dom]["bytes_per_launch"]
-    upd_kernel = kern.get("k_update", {})
+    hbm_k = [k for k, v in kern.items() if v.get("bound") == "hbm"]
+    hbm_frac = {k: kern[k]["gbs"] / PEAK_HBM_GBS for k in hbm_k}
 
     if args.copy_calibration:
         a = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
@@ -196,11 +209,12 @@ def main():
         "config": {"workload": prob.name, "grid": f"{prob.W}x{prob.H}", "actions": prob.A,
                    "landmarks": prob.L, "depth": prob.D, "samples_per_action": prob.n,
                    "blocked_fraction": round(float(prob.occ.mean()), 4),
-                   "draw_seeds": len(seeds), "parallelism": "single GPU"},
+                   "draw_seeds": len(seeds), "parallelism": "single GPU",
+                   "kernels": "banded" if args.banded else "auto"},
         "ms_per_step_with_kernel_events": wall_ev * 1e3 / K,
         "plans_per_s": K / wall, "v_node_expansions_per_s": exp / wall,
         "child_nodes_per_s": kids / wall,
-        "hbm_frac_update_kernel": (upd_kernel.get("gbs", 0.0) / PEAK_HBM_GBS) if upd_kernel else None,
+        "hbm_frac_by_kernel": hbm_frac,
         "roofline": roof, "kernels": kern,
         "value_iteration": {"sweeps": sweeps, "residual": res, "ms": vi_ms,
                             "sweeps_per_s": sweeps / (vi_ms * 1e-3)},

@@ -61,6 +61,10 @@ extern "C" {
 /* Store the depth-D (leaf) beliefs in the workspace and score them in a
  * separate pass, instead of scoring each leaf belief as it is produced. */
 #define QV_PLAN_STORE_LEAVES 1
+/* Use the banded multi-pass kernels even where the whole belief would fit
+ * in one workgroup's LDS (the default for such grids is one workgroup per
+ * Q-node); results are the same up to FP32 summation order. */
+#define QV_PLAN_TILED 2
 
 /* ---- problem statement ------------------------------------------------- */
 /* The POMDP tuple (X, A, Z, T, O, R, b0, gamma) of Sec. II, specialised to
@@ -171,7 +175,8 @@ int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
 /* ---- kernel timing (benchmarking aid) ----------------------------------
  * While enabled, each kernel the library launches is bracketed by two
  * hipEvents recorded on its launch stream.  qv_timing_read (after the
- * caller has synchronised those streams) returns, per kernel name, the
+ * caller has synchronised those streams) returns, per kernel name (with
+ * "@L<d>" appended for per-level planning kernels), the
  * number of launches and the summed event-to-event time, then clears the
  * records.  qv_timing_enable(on) also clears them.  Host-side only; not
  * meant for concurrent use from several threads. */

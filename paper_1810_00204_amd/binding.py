@@ -29,6 +29,7 @@ QV_MAX_ACTIONS = 9
 QV_MAX_DEPTH = 6
 QV_MAX_SAMPLES = 16
 QV_PLAN_STORE_LEAVES = 1
+QV_PLAN_TILED = 2
 
 # every function the header declares
 EXPORTS = [

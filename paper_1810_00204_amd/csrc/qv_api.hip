@@ -23,7 +23,7 @@ int tile_rows(int W, int H) {
   if (target == 0) {
     const char *e = std::getenv("QVTS_TILE_CELLS");
     int t = e ? std::atoi(e) : 0;
-    target = (t >= 64 && t <= (1 << 20)) ? t : 4096;
+    target = (t >= 64 && t <= (1 << 20)) ? t : 1024;
   }
   int th = target / (W > 0 ? W : 1);
   if (th < 1) th = 1;
@@ -105,6 +105,7 @@ static bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLay
   }
   T.level_first[D + 1] = tot;
   if (T.level_slots[D] * T.tiles >= (1LL << 31)) return false;
+  if (D > 0 && T.level_slots[D - 1] * T.tiles * A >= (1LL << 31)) return false;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -129,6 +130,10 @@ static bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLay
   L->part = take((size_t)ps * A * T.tiles * 17 * 4);
   L->lmv = take((size_t)ps * A * (m->L > 0 ? m->L : 1) * 4);
   L->leafpart = take((size_t)T.level_slots[D] * T.tiles * A * 4);
+  L->stats_ctr_len = (size_t)ps * A;
+  L->node_ctr_len = (size_t)tot;
+  L->counters = take((L->stats_ctr_len + L->node_ctr_len) * 4);
+  L->lm_wall = take((size_t)(m->L > 0 ? m->L : 1) * 4);
   L->err = take(256);
   T.total_bytes = off;
   return true;
@@ -242,7 +247,7 @@ int32_t qv_plan_step(const qv_model *m, const float *Q, const float *b0, int32_t
   if (st != QV_OK) return st;
   if (D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES) return QV_ERR_INVALID_ARG;
   if (!Q || !b0 || !action_out || !rootQ_out) return QV_ERR_INVALID_ARG;
-  if (flags & ~QV_PLAN_STORE_LEAVES) return QV_ERR_INVALID_ARG;
+  if (flags & ~(QV_PLAN_STORE_LEAVES | QV_PLAN_TILED)) return QV_ERR_INVALID_ARG;
   PlanLayout L;
   if (!plan_layout_impl(m, D, n, flags, &L)) return QV_ERR_UNSUPPORTED;
   if (!ws_ok(ws, ws_bytes, L.pub.total_bytes)) return QV_ERR_WORKSPACE;

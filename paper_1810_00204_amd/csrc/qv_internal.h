@@ -27,8 +27,10 @@ struct PlanPtrs {
 // Byte layout of the plan workspace.
 struct PlanLayout {
   qv_tree_layout pub;
-  size_t sig, staytab, part, lmv, leafpart, err;
-  size_t part_slots;   // max slots of a non-leaf level
+  size_t sig, staytab, part, lmv, leafpart, err, counters, lm_wall;
+  size_t part_slots;      // max slots of a non-leaf level
+  size_t stats_ctr_len;   // int32 counters: bands done per (slot, action)
+  size_t node_ctr_len;    // int32 counters: parts done per node
 };
 
 // Per-level kernel arguments (passed by value).
@@ -46,6 +48,23 @@ struct LevelArgs {
   const float *Q;
   const uint32_t *sig;
   const float *staytab;
+  const uint32_t *lm_wall;  // [L] true wall reading of each landmark cell
+  int32_t *ctr;           // [nslots*A] bands finished per Q-node
+  int q_vec;              // Q rows can be read as float4 (A = 4 or 8, aligned)
+};
+
+// Whole-tree view for the expectimax backup (Alg. 6/7).
+struct TreeArgs {
+  int D, n, K, A;
+  float gamma;
+  long long first[QV_MAX_DEPTH + 2];
+  long long slots[QV_MAX_DEPTH + 1];
+  const int32_t *valid, *count;
+  float *value, *qvalue;
+  const float *reward;
+  int32_t *node_ctr;      // [total slots] finished parts per node
+  int32_t *action_out;
+  float *rootQ_out;
 };
 
 int tile_rows(int W, int H);
@@ -71,18 +90,26 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // Brackets one kernel launch with timing events while timing is enabled.
 class TimingScope {
  public:
-  TimingScope(const char *name, hipStream_t st);
+  TimingScope(const char *name, hipStream_t st, int tag = -1);
   ~TimingScope();
 
  private:
   const char *name_;
   hipStream_t st_;
   void *ev_;
+  int tag_;
 };
 
 #define QV_LAUNCH(kernel, grid, block, lds, st, ...)                        \
   do {                                                                      \
     ::qv::TimingScope qv_ts_(#kernel, st);                                  \
+    hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);          \
+  } while (0)
+
+// As QV_LAUNCH, with the tree level in the timing record ("name@L<tag>").
+#define QV_LAUNCH_L(tag, kernel, grid, block, lds, st, ...)                 \
+  do {                                                                      \
+    ::qv::TimingScope qv_ts_(#kernel, st, tag);                             \
     hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);          \
   } while (0)
 

@@ -1,19 +1,25 @@
 // qv_plan.hip -- level-synchronous QV-tree expansion on gfx950.
 //
 // One planning step builds the depth-D tree of Alg. 1-7 (Sec. IV-C) one
-// frontier at a time.  For every level d < D, over all capacity slots of
-// the level at once:
-//   k_stats    predicted belief b' = T_a^T b per action (slip stencil, Sec. V)
-//              reduced to a 16-bin histogram by true wall reading, the
-//              predicted mass on each landmark cell, and R(b,a) (Sec. III);
-//   k_sample   P(z|b,a) over all z from those sums, n inverse-CDF draws with
-//              Philox uniforms (Alg. 3/4), distinct z with frequencies;
-//   k_update   child beliefs Phi(b,a,z) (posterior belief update, Sec. III)
-//              written to HBM for the next level, or at d = D-1
-//   k_leaf     the same posterior values scored on the fly against the
-//              Q-MDP vectors, sum_s b(s) Q(s,a') (Alg. 5), never stored.
-// Then k_leaf_reduce and k_backup run the expectimax backup (Alg. 6/7).
-// Beliefs stream through LDS in bands of whole rows with a one-cell halo.
+// frontier at a time.  Work items are (parent slot, band of rows, action):
+// every Q-node of the level is spread over many workgroups.  For each level
+// d < D:
+//   k_stats   predicted belief b' = T_a^T b (slip stencil, Sec. V) reduced to
+//             a 16-bin histogram by true wall reading, the predicted mass on
+//             each landmark cell, and R(b,a) (Sec. III).  The last band of a
+//             Q-node to finish then forms P(z|b,a) over all z and draws the n
+//             observations (Alg. 3/4), keeping each distinct z with its
+//             frequency;
+//   k_update  (d < D-1) writes the child beliefs Phi(b,a,z) (posterior belief
+//             update, Sec. III) for the next level, or
+//   k_leaf    (d = D-1) forms the same posterior values and scores them on the
+//             fly against the Q-MDP vectors, sum_s b(s) Q(s,a') (Alg. 5),
+//             without storing them.  The last workgroup to finish a node
+//             completes its backup (Alg. 6/7) and, as the last child of its
+//             parent, the parent's, up to the root.
+// Beliefs stream through LDS in bands of whole rows with a one-cell halo;
+// all cross-workgroup sums run in a fixed order, so results are bitwise
+// reproducible.
 #include <algorithm>
 
 #include "qv_internal.h"
@@ -21,27 +27,31 @@
 namespace qv {
 
 // ---------------------------------------------------------------------------
-// map signature and stay table
+// map signature, stay table, counters
 // ---------------------------------------------------------------------------
-// root != nullptr: also define the root's records (valid, no observation)
-struct RootRecords {
-  int32_t *valid, *z, *count;
+struct PrepExtra {
+  int32_t *valid, *z, *count;  // root records (nullptr: none)
   float *pz;
+  int32_t *zero;               // counters cleared every call
+  long long nzero;
+  uint32_t *lm_wall;           // [L] wall reading of each landmark cell (or null)
 };
 
 __global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *err,
-                           RootRecords root) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s == 0) {
+                           PrepExtra x) {
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = (int)g;
+  if (g == 0) {
     err[0] = 0;
-    if (root.valid) {
-      root.valid[0] = 1;
-      root.z[0] = -1;
-      root.count[0] = 0;
-      root.pz[0] = 0.f;
+    if (x.valid) {
+      x.valid[0] = 1;
+      x.z[0] = -1;
+      x.count[0] = 0;
+      x.pz[0] = 0.f;
     }
   }
-  if (s < m.A * 256) {
+  if (g < x.nzero) x.zero[g] = 0;
+  if (g < m.A * 256) {
     // stay(a, pattern): T'(a,4) plus the slip mass of every move whose
     // target is blocked or off-grid (bit clear in the 8-neighbour pattern)
     const int a = s >> 8, pat = s & 255;
@@ -54,13 +64,13 @@ __global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *e
     }
     staytab[s] = st;
   }
-  if (s >= m.S) return;
-  const int y = s / m.W, x = s - y * m.W;
+  if (g >= m.S) return;
+  const int y = s / m.W, x0 = s - y * m.W;
   uint32_t v = 0;
   int bit = 0;
   for (int k = 0; k < 9; ++k) {
     if (k == 4) continue;
-    const int ny = y + k / 3 - 1, nx = x + k % 3 - 1;
+    const int ny = y + k / 3 - 1, nx = x0 + k % 3 - 1;
     const bool ok = ny >= 0 && ny < m.H && nx >= 0 && nx < m.W && m.occ[ny * m.W + nx] == 0;
     if (ok) v |= 1u << bit;
     ++bit;
@@ -73,14 +83,16 @@ __global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *e
   sig[s] = v | (w << 10);
 }
 
-__global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err) {
+__global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32_t *lm_wall) {
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= m.L) return;
   const int c = m.lm_cell[l];
   if (c < 0 || c >= m.S) {
+    if (lm_wall) lm_wall[l] = 0xFFFFFFFFu;   // never observed
     atomicOr(err, 1);
     return;
   }
+  if (lm_wall) lm_wall[l] = sig_wall(sig[c]);
   // a cell carries at most one landmark id: a second one is refused and flagged
   uint32_t cur = sig[c];
   while (sig_lm(cur) == 0u) {
@@ -91,15 +103,20 @@ __global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err) {
   atomicOr(err, 2);
 }
 
+static void prep_launch(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
+                        const PrepExtra &x, hipStream_t st) {
+  const long long n = std::max<long long>(std::max(dm.S, dm.A * 256), x.nzero);
+  QV_LAUNCH(k_prep_sig, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dm, sig, staytab,
+            err, x);
+  if (dm.L > 0)
+    QV_LAUNCH(k_prep_landmarks, dim3((dm.L + 255) / 256), dim3(256), 0, st, dm, sig, err,
+              x.lm_wall);
+}
+
 hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
                        hipStream_t st) {
-  const int n = std::max(dm.S, dm.A * 256);
-  const RootRecords none = {nullptr, nullptr, nullptr, nullptr};
-  QV_LAUNCH(k_prep_sig, dim3((n + 255) / 256), dim3(256), 0, st, dm, sig, staytab,
-                     err, none);
-  if (dm.L > 0)
-    QV_LAUNCH(k_prep_landmarks, dim3((dm.L + 255) / 256), dim3(256), 0, st, dm, sig,
-                       err);
+  const PrepExtra none = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr};
+  prep_launch(dm, sig, staytab, err, none, st);
   return hipGetLastError();
 }
 
@@ -108,28 +125,45 @@ hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_
 // ---------------------------------------------------------------------------
 
 // Rows y0-1 .. y0+th of belief b, columns -1 .. W, into LDS (pitch BW=W+2).
-// Off-grid, blocked and goal cells read as zero: none of them is a source of
-// moving mass (the goal is absorbing and keeps its own mass).
+// Off-grid cells and the goal read as zero: neither is a source of moving
+// mass (the goal is absorbing and keeps its own mass).  Blocked cells hold
+// zero mass in every belief the library forms; with `mask` (the caller's
+// start belief) they are zeroed here as well.  Loads are issued in batches
+// so that each thread has several in flight.
+constexpr int kBandBatch = 8;
 __device__ __forceinline__ void load_band(const DevModel &m, const uint32_t *sig,
                                           const float *b, int y0, int th, float *band,
-                                          int BW) {
+                                          int BW, bool mask) {
   const int n = (th + 2) * BW;
   const float rBW = 1.0f / (float)BW;
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    const int r = fdiv(i, BW, rBW);
-    const int gy = y0 - 1 + r, gx = i - r * BW - 1;
-    float v = 0.f;
-    if (gy >= 0 && gy < m.H && gx >= 0 && gx < m.W) {
-      const int s = gy * m.W + gx;
-      if ((sig[s] & (kSigFree | kSigGoal)) == kSigFree) v = b[s];
+  for (int i0 = threadIdx.x; i0 < n; i0 += kBandBatch * kBlock) {
+    int cell[kBandBatch];
+    float v[kBandBatch];
+#pragma unroll
+    for (int j = 0; j < kBandBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      const int r = fdiv(i, BW, rBW);
+      const int gy = y0 - 1 + r, gx = i - r * BW - 1;
+      const bool in = i < n && gy >= 0 && gy < m.H && gx >= 0 && gx < m.W;
+      cell[j] = in ? gy * m.W + gx : -1;
+      v[j] = (in && cell[j] != m.goal) ? b[cell[j]] : 0.f;
     }
-    band[i] = v;
+    if (mask) {
+#pragma unroll
+      for (int j = 0; j < kBandBatch; ++j)
+        if (cell[j] >= 0 && !(sig[cell[j]] & kSigFree)) v[j] = 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kBandBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      if (i < n) band[i] = v[j];
+    }
   }
 }
 
-// b'(t) for cell t = (y0+ly)*W + lx of the tile.
-__device__ __forceinline__ float predict_cell(const DevModel &m, const float *band, int BW,
-                                              int ly, int lx, uint32_t sg, const float *sl,
+// b'(t) for cell t = (y0+ly)*W + lx of the band.
+__device__ __forceinline__ float predict_cell(const float *band, int BW, int ly, int lx,
+                                              uint32_t sg, const float *sl,
                                               const float *stay_a, const float *b, int t) {
   if (!(sg & kSigFree)) return 0.f;
   const float *c = band + (ly + 1) * BW + lx + 1;
@@ -144,152 +178,135 @@ __device__ __forceinline__ float predict_cell(const DevModel &m, const float *ba
   return stencil(c, BW, sl, stay, self);
 }
 
-// Sum NV per-thread values over the workgroup; thread i < NV gets the total
-// of value i (fixed order: wavefront butterfly, then waves 0..3).
-template <int NV>
-__device__ __forceinline__ float block_sum_to_thread(float (&v)[NV], float *red) {
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+// As predict_cell with b(t) already loaded (bt).
+__device__ __forceinline__ float predict_cell_v(const float *band, int BW, int ly, int lx,
+                                                uint32_t sg, const float *sl,
+                                                const float *stay_a, float bt) {
+  if (!(sg & kSigFree)) return 0.f;
+  const float *c = band + (ly + 1) * BW + lx + 1;
+  if (sg & kSigGoal) return stencil(c, BW, sl, 1.f, bt);
+  return stencil(c, BW, sl, stay_a[sig_out8(sg)], c[0]);
+}
+
+constexpr int kCellBatch = 4;   // cells whose loads a thread issues together
+constexpr int kLeafBatch = 2;
+
+// Q(t, .) padded to APAD entries; float4 loads when rows are APAD wide.
+template <int APAD>
+__device__ __forceinline__ void load_q_row(const LevelArgs &lv, int A, int t, float (&q)[APAD]) {
+  if (APAD <= 8 && lv.q_vec) {
+    const float4 *q4 = (const float4 *)(lv.Q + (size_t)t * APAD);
 #pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const float s = wave_sum(v[i]);
-    if (lane == 0) red[wave * NV + i] = s;
+    for (int c4 = 0; c4 < APAD / 4; ++c4) {
+      const float4 v4 = q4[c4];
+      q[4 * c4 + 0] = v4.x;
+      q[4 * c4 + 1] = v4.y;
+      q[4 * c4 + 2] = v4.z;
+      q[4 * c4 + 3] = v4.w;
+    }
+  } else {
+    const float *Qr = lv.Q + (size_t)t * A;
+#pragma unroll
+    for (int c = 0; c < APAD; ++c) q[c] = (c < A) ? Qr[c] : 0.f;
   }
+}
+
+// Hand-off between workgroups of one launch.  Values another workgroup will
+// read are written with device-scope atomic stores (written through to the
+// device-coherent level, past this XCD's L2), the writer waits until its
+// stores have completed and only then bumps a counter; the workgroup that
+// sees the final count reads with device-scope atomic loads.  This orders
+// the hand-off without a device-scope fence, which on this GPU writes back
+// and invalidates the whole L2 of the XCD.
+__device__ __forceinline__ float ld_coherent(const float *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(float *p, float v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// wait until all memory operations this thread issued have completed
+__device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+__device__ __forceinline__ int count_arrival(int32_t *ctr) {
+  return __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Workgroup totals of 32 per-thread values through an LDS transpose: each
+// wave stores its 64 x 32 values (row pitch 33, so a column read touches 32
+// different banks), lane L sums column L & 31 over half the rows, the halves
+// combine with one shuffle, and the four waves combine in wave order.
+// scratch: [4][64*33 + 32] floats.  Thread i < 32 returns total i.
+constexpr int kTransPitch = 33;
+constexpr int kTransWave = kWave * kTransPitch + 32;
+__device__ __forceinline__ float block_sum32(const float (&v)[32], float *scratch) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  float *rw = scratch + wave * kTransWave;
+#pragma unroll
+  for (int i = 0; i < 32; ++i) rw[lane * kTransPitch + i] = v[i];
+  __syncthreads();
+  const int col = lane & 31, h = lane >> 5;
+  float s = 0.f;
+#pragma unroll 8
+  for (int j = 0; j < 32; ++j) s += rw[(h * 32 + j) * kTransPitch + col];
+  s += __shfl_xor(s, 32, kWave);
+  if (lane < 32) rw[kWave * kTransPitch + lane] = s;
   __syncthreads();
   float out = 0.f;
-  if (threadIdx.x < NV) {
+  if (threadIdx.x < 32) {
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) out += red[w * NV + threadIdx.x];
+    for (int w = 0; w < kBlock / kWave; ++w) out += scratch[w * kTransWave + kWave * kTransPitch + threadIdx.x];
   }
   __syncthreads();
   return out;
 }
 
 // ---------------------------------------------------------------------------
-// k_stats: per (parent slot, tile)
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
-  extern __shared__ float smem[];
-  const int p = blockIdx.x / lv.tiles;
-  const int tile = blockIdx.x - p * lv.tiles;
-  if (!lv.pvalid[p]) return;
-  const int W = m.W, BW = W + 2, A = m.A;
-  const int y0 = tile * lv.TH;
-  const int th = min(lv.TH, m.H - y0);
-  float *band = smem;
-  float *hist = band + (lv.TH + 2) * BW;   // [16][kBlock], per-thread bins
-  float *red = hist + 16 * kBlock;         // [4][QV_MAX_ACTIONS]
-  const float *b = lv.pbel + (size_t)p * m.S;
-  load_band(m, lv.sig, b, y0, th, band, BW);
-  __syncthreads();
-  const int tid = threadIdx.x;
-  const int ncell = th * W;
-  const float rW = 1.0f / (float)W;
-  float *part = lv.part + (size_t)p * A * lv.tiles * 17;
-
-  // R(b,a) = sum_x R(x,a) b(x) for every action (Sec. III)
-  float racc[QV_MAX_ACTIONS];
-#pragma unroll
-  for (int a = 0; a < QV_MAX_ACTIONS; ++a) racc[a] = 0.f;
-  for (int i = tid; i < ncell; i += kBlock) {
-    const int t = y0 * W + i;
-    const float bt = b[t];
-    const float *Rr = m.R + (size_t)t * A;
-#pragma unroll
-    for (int a = 0; a < QV_MAX_ACTIONS; ++a)
-      if (a < A) racc[a] = fmaf(bt, Rr[a], racc[a]);
-  }
-  {
-    const float tot = block_sum_to_thread<QV_MAX_ACTIONS>(racc, red);
-    if (tid < A) part[((size_t)tid * lv.tiles + tile) * 17 + 16] = tot;
-  }
-
-  const float rho = m.lm_p;
-  for (int a = 0; a < A; ++a) {
-    const float *sl = &m.slip[a * 9];
-    const float *stay_a = lv.staytab + a * 256;
-    float h0 = 0.f;
-#pragma unroll
-    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
-    for (int i = tid; i < ncell; i += kBlock) {
-      const int ly = fdiv(i, W, rW), lx = i - ly * W;
-      const int t = (y0 + ly) * W + lx;
-      const uint32_t sg = lv.sig[t];
-      const float bp = predict_cell(m, band, BW, ly, lx, sg, sl, stay_a, b, t);
-      const uint32_t lm = sig_lm(sg);
-      float contrib = bp;
-      if (lm && lm <= (uint32_t)m.L) {
-        contrib = bp * (1.f - rho);
-        lv.lmv[((size_t)p * A + a) * m.L + lm - 1] = bp;
-      }
-      const uint32_t w = sig_wall(sg);
-      if (w == 0u)
-        h0 += contrib;
-      else
-        hist[w * kBlock + tid] += contrib;
-    }
-    hist[tid] = h0;
-    __syncthreads();
-    // bin = tid/16 sums 16 consecutive per-thread entries, then 16 lanes combine
-    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
-    float s = 0.f;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) s += hb[i];
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-    if ((tid & 15) == 0) part[((size_t)a * lv.tiles + tile) * 17 + (tid >> 4)] = s;
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
-// k_sample: one wavefront per (parent slot, action)
+// observation draws of one Q-node, by one wavefront
 // ---------------------------------------------------------------------------
 struct ObsSource {
-  float p0;               // lanes 0..15: P(zw, no landmark)
-  const float *lmv;       // predicted mass on landmark cells of this (slot, action)
+  float p0;                 // lane zw < 16: P(zw, no landmark)
+  const uint32_t *lw;       // LDS [L]: wall reading of landmark l+1
+  const float *lv;          // LDS [L]: predicted mass on landmark l+1
+  int L;
 };
 
-// P(z|b,a) for z = zw + 16 zl.  Must be called by every lane of the wave
-// (it reads lane zw's no-landmark value with a shuffle).
-__device__ __forceinline__ float obs_prob(const DevModel &m, const uint32_t *sig,
-                                          const ObsSource &src, int z) {
+// P(z|b,a) for z = zw + 16 zl.  Called by every lane of the wavefront (it
+// reads lane zw's no-landmark value with a shuffle).
+__device__ __forceinline__ float obs_prob(const DevModel &m, const ObsSource &src, int z) {
   const int zw = z & 15, zl = z >> 4;
   const float from_p0 = __shfl(src.p0, zw, kWave);
   if (zl == 0) return from_p0;
-  if (zl > m.L) return 0.f;
-  const int c = m.lm_cell[zl - 1];
-  if (c < 0 || c >= m.S) return 0.f;
-  return wall_lik(m.flip, (uint32_t)zw, sig_wall(sig[c])) * m.lm_p * src.lmv[zl - 1];
+  if (zl > src.L) return 0.f;
+  const uint32_t w = src.lw[zl - 1];
+  if (w > 15u) return 0.f;
+  return wall_lik(m.flip, (uint32_t)zw, w) * m.lm_p * src.lv[zl - 1];
 }
 
-__global__ __launch_bounds__(256) void k_sample(DevModel m, LevelArgs lv) {
-  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
-  const int idx = blockIdx.x * (256 / kWave) + wave;
-  if (idx >= lv.nslots * m.A) return;
-  const int p = idx / m.A, a = idx - p * m.A;
+// Copy of the drawn children kept in LDS for the rest of a workgroup.
+struct DrawOut {
+  int z[QV_MAX_SAMPLES], count[QV_MAX_SAMPLES];
+  float inv[QV_MAX_SAMPLES];
+  int U;
+};
+
+// Observation draws of Q-node (slot p, action a) of level lv.d from its
+// statistics: lane w < 16 holds H[w], the predicted mass with true wall
+// reading w (landmark cells weighted by their "no landmark" factor); lw/lvv
+// (LDS) hold each landmark's wall reading and predicted mass.  Forms P(z|b,a)
+// over all z in ascending order, draws n observations by inverse CDF with
+// Philox uniforms, and writes one child record per distinct z (ascending)
+// with its frequency (Alg. 3/4).  One full wavefront; out (LDS) optional.
+__device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
+                             const uint32_t *lw, const float *lvv, DrawOut *out) {
+  const int lane = threadIdx.x & (kWave - 1);
   const int n = lv.n;
   const int cb = p * lv.K + a * n;
-  if (!lv.pvalid[p]) {
-    if (lane < n) {
-      lv.cvalid[cb + lane] = 0;
-      lv.cz[cb + lane] = -1;
-      lv.ccount[cb + lane] = 0;
-      lv.cpz[cb + lane] = 0.f;
-    }
-    return;
-  }
-  // totals over tiles of the 16 wall bins and of R(b,a), tile order fixed
-  float hs = 0.f;
-  if (lane < 17) {
-    const float *pp = lv.part + (size_t)idx * lv.tiles * 17 + lane;
-    for (int t = 0; t < lv.tiles; ++t) hs += pp[t * 17];
-  }
-  if (lane == 16) lv.reward[idx] = hs;
   // P(zw, no landmark) = sum_w O_w(zw|w) H[w]; landmark cells entered H with
   // their "no landmark" factor already
   ObsSource src;
   src.p0 = 0.f;
-  src.lmv = lv.lmv + (size_t)idx * m.L;
+  src.lw = lw;
+  src.lv = lvv;
+  src.L = m.L;
   for (int w = 0; w < 16; ++w) {
     const float hw = __shfl(hs, w, kWave);
     src.p0 = fmaf(wall_lik(m.flip, (uint32_t)(lane & 15), (uint32_t)w), hw, src.p0);
@@ -300,10 +317,11 @@ __global__ __launch_bounds__(256) void k_sample(DevModel m, LevelArgs lv) {
   float loc = 0.f;
   for (int j = 0; j < CH; ++j) {
     const int z = lane * CH + j;
-    const float v = obs_prob(m, lv.sig, src, min(z, Z - 1));
+    const float v = obs_prob(m, src, min(z, Z - 1));
     loc += (z < Z) ? v : 0.f;
   }
-  // exclusive prefix of the lane totals, summed in lane order
+  // exclusive prefix of the lane totals, summed in lane order, so the running
+  // totals are non-decreasing across lanes and the last one is the total P
   float exc = 0.f, P = 0.f;
   for (int i = 0; i < kWave; ++i) {
     const float s = __shfl(loc, i, kWave);
@@ -334,7 +352,7 @@ __global__ __launch_bounds__(256) void k_sample(DevModel m, LevelArgs lv) {
   float run = 0.f;
   for (int j = 0; j < CH; ++j) {
     const int z = lane * CH + j;
-    float v = obs_prob(m, lv.sig, src, min(z, Z - 1));
+    float v = obs_prob(m, src, min(z, Z - 1));
     if (z >= Z) v = 0.f;
     run += v;
     const float F = exc + run;
@@ -357,7 +375,7 @@ __global__ __launch_bounds__(256) void k_sample(DevModel m, LevelArgs lv) {
       int zz = wave_min(cand[k]);
       if (zz == kNone) zz = lastz;
       zk[k] = zz;
-      pk[k] = zz >= 0 ? obs_prob(m, lv.sig, src, zz) : 0.f;
+      pk[k] = zz >= 0 ? obs_prob(m, src, zz) : 0.f;
     }
   }
   if (lane == 0) {
@@ -380,9 +398,15 @@ __global__ __launch_bounds__(256) void k_sample(DevModel m, LevelArgs lv) {
       lv.cz[cb + r] = zk[i];
       lv.ccount[cb + r] = j - i;
       lv.cpz[cb + r] = pk[i];
+      if (out && ok) {
+        out->z[r] = zk[i];
+        out->count[r] = j - i;
+        out->inv[r] = 1.0f / pk[i];
+      }
       r += ok ? 1 : 0;
       i = j;
     }
+    if (out) out->U = r;
     for (; r < n; ++r) {
       lv.cvalid[cb + r] = 0;
       lv.cz[cb + r] = -1;
@@ -392,47 +416,199 @@ __global__ __launch_bounds__(256) void k_sample(DevModel m, LevelArgs lv) {
   }
 }
 
+// Tiled path: the statistics of the Q-node are spread over per-band partials
+// written by other workgroups of this launch; sum them in band order, stage
+// the landmark terms in LDS (lds: 2*L words), then draw.
+__device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int a, float *lds) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int idx = p * m.A + a;
+  float hs = 0.f;
+  if (lane < 17) {
+    const float *pp = lv.part + (size_t)idx * lv.tiles * 17 + lane;
+    for (int t = 0; t < lv.tiles; ++t) hs += ld_coherent(pp + t * 17);
+  }
+  if (lane == 16) lv.reward[idx] = hs;
+  uint32_t *lw = (uint32_t *)lds;
+  float *lvv = lds + m.L;
+  for (int l = lane; l < m.L; l += kWave) {
+    lw[l] = lv.lm_wall[l];
+    lvv[l] = ld_coherent(lv.lmv + (size_t)idx * m.L + l);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  sample_draws(m, lv, p, a, hs, lw, lvv, nullptr);
+}
+
+// Decodes blockIdx.x = (p * tiles + tile) * A + a.
+struct Item {
+  int p, tile, a;
+};
+__device__ __forceinline__ Item decode_item(int tiles, int A) {
+  Item it;
+  const int pt = blockIdx.x / A;
+  it.a = blockIdx.x - pt * A;
+  it.p = pt / tiles;
+  it.tile = pt - it.p * tiles;
+  return it;
+}
+
 // ---------------------------------------------------------------------------
-// k_update: per (parent slot, tile); writes Phi(b,a,z) for every child
+// k_stats: per (parent slot, band, action)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ float s_stay[256];
+  __shared__ float red[kBlock / kWave];
+  __shared__ int s_last;
+  const Item it = decode_item(lv.tiles, m.A);
+  const int p = it.p, tile = it.tile, a = it.a;
+  // children of an invalid parent are marked absent by its first band
+  if (!lv.pvalid[p]) {
+    if (tile == 0 && threadIdx.x < lv.n) {
+      const int c = p * lv.K + a * lv.n + threadIdx.x;
+      lv.cvalid[c] = 0;
+      lv.cz[c] = -1;
+      lv.ccount[c] = 0;
+      lv.cpz[c] = 0.f;
+    }
+    return;
+  }
+  const int W = m.W, BW = W + 2, A = m.A;
+  const int y0 = tile * lv.TH;
+  const int th = min(lv.TH, m.H - y0);
+  float *band = smem;
+  float *hist = band + (lv.TH + 2) * BW;   // [16][kBlock] per-thread bins
+  const float *b = lv.pbel + (size_t)p * m.S;
+  s_stay[threadIdx.x] = lv.staytab[a * 256 + threadIdx.x];
+  load_band(m, lv.sig, b, y0, th, band, BW, lv.d == 0);
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+  __syncthreads();
+  const int ncell = th * W;
+  const float rW = 1.0f / (float)W;
+  const float *sl = &m.slip[a * 9];
+  const float *stay_a = s_stay;
+  const float rho = m.lm_p;
+  float h0 = 0.f, racc = 0.f;
+  const int t00 = y0 * W;
+  for (int i0 = tid; i0 < ncell; i0 += kCellBatch * kBlock) {
+    uint32_t sg[kCellBatch];
+    float bt[kCellBatch], rr[kCellBatch];
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      const bool ok = i < ncell;
+      const int t = t00 + (ok ? i : 0);
+      sg[j] = ok ? lv.sig[t] : 0u;
+      bt[j] = ok ? b[t] : 0.f;
+      rr[j] = ok ? m.R[(size_t)t * A + a] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      if (i >= ncell) break;
+      // R(b,a) = sum_x R(x,a) b(x) (Sec. III)
+      racc = fmaf(bt[j], rr[j], racc);
+      const int ly = fdiv(i, W, rW), lx = i - ly * W;
+      const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
+      const uint32_t lm = sig_lm(sg[j]);
+      float contrib = bp;
+      if (lm && lm <= (uint32_t)m.L) {
+        contrib = bp * (1.f - rho);
+        st_coherent(lv.lmv + ((size_t)p * A + a) * m.L + lm - 1, bp);
+      }
+      const uint32_t w = sig_wall(sg[j]);
+      if (w == 0u)
+        h0 += contrib;
+      else
+        hist[w * kBlock + tid] += contrib;
+    }
+  }
+  hist[tid] = h0;
+  racc = wave_sum(racc);
+  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = racc;
+  __syncthreads();
+  float *part = lv.part + (((size_t)p * A + a) * lv.tiles + tile) * 17;
+  // bin = tid/16 sums 16 consecutive per-thread entries, then 16 lanes combine
+  {
+    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += hb[i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    if ((tid & 15) == 0) st_coherent(part + (tid >> 4), s);
+    if (tid == 0) st_coherent(part + 16, (red[0] + red[1]) + (red[2] + red[3]));
+  }
+  // the last band of this Q-node to finish draws its observations
+  wait_mem();
+  __syncthreads();
+  if (tid == 0) {
+    const int prev = count_arrival(&lv.ctr[p * A + a]);
+    s_last = (prev == lv.tiles - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  if (tid < kWave) sample_qnode(m, lv, p, a, hist);
+  if (tid == 0) lv.ctr[p * A + a] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// k_update: per (parent slot, band, action); writes Phi(b,a,z) per child
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
-  const int p = blockIdx.x / lv.tiles;
-  const int tile = blockIdx.x - p * lv.tiles;
+  __shared__ float s_stay[256];
+  const Item it = decode_item(lv.tiles, m.A);
+  const int p = it.p, tile = it.tile, a = it.a;
   if (!lv.pvalid[p]) return;
-  const int W = m.W, BW = W + 2, A = m.A, S = m.S;
+  const int cb = p * lv.K + a * lv.n;
+  int U = 0;
+  int zr[QV_MAX_SAMPLES];
+  float inv[QV_MAX_SAMPLES];
+#pragma unroll
+  for (int r = 0; r < QV_MAX_SAMPLES; ++r) {
+    zr[r] = 0;
+    inv[r] = 0.f;
+    if (r < lv.n && lv.cvalid[cb + r]) {
+      zr[r] = lv.cz[cb + r];
+      inv[r] = 1.0f / lv.cpz[cb + r];
+      ++U;
+    }
+  }
+  if (U == 0) return;
+  const int W = m.W, BW = W + 2, S = m.S;
   const int y0 = tile * lv.TH;
   const int th = min(lv.TH, m.H - y0);
   float *band = smem;
   const float *b = lv.pbel + (size_t)p * S;
-  load_band(m, lv.sig, b, y0, th, band, BW);
+  s_stay[threadIdx.x] = lv.staytab[a * 256 + threadIdx.x];
+  load_band(m, lv.sig, b, y0, th, band, BW, lv.d == 0);
   __syncthreads();
   const int ncell = th * W;
   const float rW = 1.0f / (float)W;
-  for (int a = 0; a < A; ++a) {
-    const int cb = p * lv.K + a * lv.n;
-    int U = 0;
-    int zr[QV_MAX_SAMPLES];
-    float inv[QV_MAX_SAMPLES];
+  const float *sl = &m.slip[a * 9];
+  const float *stay_a = s_stay;
+  const int t00 = y0 * W;
+  for (int i0 = threadIdx.x; i0 < ncell; i0 += kCellBatch * kBlock) {
+    uint32_t sg[kCellBatch];
+    float bt[kCellBatch];
 #pragma unroll
-    for (int r = 0; r < QV_MAX_SAMPLES; ++r) {
-      zr[r] = 0;
-      inv[r] = 0.f;
-      if (r < lv.n && lv.cvalid[cb + r]) {
-        zr[r] = lv.cz[cb + r];
-        inv[r] = 1.0f / lv.cpz[cb + r];
-        ++U;
-      }
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      const bool ok = i < ncell;
+      sg[j] = ok ? lv.sig[t00 + i] : 0u;
+      bt[j] = ok ? b[t00 + i] : 0.f;
     }
-    if (U == 0) continue;
-    const float *sl = &m.slip[a * 9];
-    const float *stay_a = lv.staytab + a * 256;
-    for (int i = threadIdx.x; i < ncell; i += kBlock) {
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      if (i >= ncell) break;
       const int ly = fdiv(i, W, rW), lx = i - ly * W;
-      const int t = (y0 + ly) * W + lx;
-      const uint32_t sg = lv.sig[t];
-      const float bp = predict_cell(m, band, BW, ly, lx, sg, sl, stay_a, b, t);
-      const uint32_t w = sig_wall(sg), lm = sig_lm(sg);
+      const int t = t00 + i;
+      const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
+      const uint32_t w = sig_wall(sg[j]), lm = sig_lm(sg[j]);
 #pragma unroll
       for (int r = 0; r < QV_MAX_SAMPLES; ++r) {
         if (r < U) {
@@ -446,37 +622,110 @@ __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
 }
 
 // ---------------------------------------------------------------------------
-// k_leaf: per (parent slot, tile) at the last level: each child belief
-// value is formed as in k_update and immediately dotted with Q(.,a')
+// expectimax backup of one node, by one thread (Alg. 6/7)
 // ---------------------------------------------------------------------------
-constexpr int kLeafGroup = 4;
 
-__global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv) {
+// V(v) = max_a Q(v,a) from the node's Q-values q[0..A); at the root also the
+// action (lowest a within 1e-9 of the best) and the root Q-values.  One thread.
+__device__ void finish_node(const TreeArgs &t, int d, long long g, const float *q) {
+  float best = -INFINITY;
+  for (int a = 0; a < t.A; ++a) best = fmaxf(best, q[a]);
+  st_coherent(t.value + g, best);
+  if (d == 0) {
+    int act = 0;
+    for (int a = 0; a < t.A; ++a)
+      if (q[a] >= best - 1e-9f) {
+        act = a;
+        break;
+      }
+    t.action_out[0] = act;
+    for (int a = 0; a < t.A; ++a) t.rootQ_out[a] = q[a];
+  }
+}
+
+// Backup of node (d, slot) by the whole workgroup (Alg. 6/7):
+//   Q(v,a) = R(b_v,a) + gamma * sum_children (f/n) V(child),  V(v) = max_a Q(v,a);
+// at the root also the action (lowest a within 1e-9 of the best).  sh holds
+// the node's K child values (entries of absent children unused) and has room
+// for A more.  Ends with a barrier.
+__device__ void backup_node_wg(const TreeArgs &t, int d, long long slot, float *sh) {
+  const long long g = t.first[d] + slot;
+  if (threadIdx.x < t.A) {
+    const int a = threadIdx.x;
+    float q = t.reward[g * t.A + a];
+    const long long cb = t.first[d + 1] + slot * t.K + (long long)a * t.n;
+    for (int r = 0; r < t.n; ++r) {
+      if (!t.valid[cb + r]) break;
+      q += t.gamma * ((float)t.count[cb + r] / (float)t.n) * sh[a * t.n + r];
+    }
+    t.qvalue[g * t.A + a] = q;
+    sh[t.K + a] = q;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) finish_node(t, d, g, sh + t.K);
+  __syncthreads();
+}
+
+// Node (d, slot) is complete: report to the parent; the workgroup holding
+// the last child of a parent completes the parent, and so on to the root.
+__device__ void climb_wg(const TreeArgs &t, int d, long long slot, float *sh, int *s_go) {
+  while (d > 0) {
+    const long long ps = slot / t.K;
+    const long long c0 = t.first[d] + ps * t.K;
+    wait_mem();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int expect = 0;
+      for (int c = 0; c < t.K; ++c) expect += t.valid[c0 + c] ? 1 : 0;
+      const int prev = count_arrival(&t.node_ctr[t.first[d - 1] + ps]);
+      *s_go = (prev == expect - 1);
+    }
+    __syncthreads();
+    if (!*s_go) return;
+    for (int c = threadIdx.x; c < t.K; c += kBlock)
+      sh[c] = t.valid[c0 + c] ? ld_coherent(t.value + c0 + c) : 0.f;
+    __syncthreads();
+    --d;
+    slot = ps;
+    backup_node_wg(t, d, slot, sh);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// k_leaf: per (parent slot, band, action) at the last level; each child
+// belief value is formed as in k_update and dotted with Q(.,a') at once
+// ---------------------------------------------------------------------------
+template <int APAD>
+__global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeArgs tr) {
+  constexpr int G = 32 / APAD;            // children per accumulation group
   extern __shared__ float smem[];
-  const int p = blockIdx.x / lv.tiles;
-  const int tile = blockIdx.x - p * lv.tiles;
+  __shared__ float s_stay[256];
+  __shared__ int s_last;
+  const Item it = decode_item(lv.tiles, m.A);
+  const int p = it.p, tile = it.tile, a = it.a;
   if (!lv.pvalid[p]) return;
   const int W = m.W, BW = W + 2, A = m.A, S = m.S;
-  const int y0 = tile * lv.TH;
-  const int th = min(lv.TH, m.H - y0);
-  float *band = smem;
-  float *red = band + (lv.TH + 2) * BW;    // [4][kLeafGroup*QV_MAX_ACTIONS]
-  const float *b = lv.pbel + (size_t)p * S;
-  load_band(m, lv.sig, b, y0, th, band, BW);
-  __syncthreads();
-  const int ncell = th * W;
-  const float rW = 1.0f / (float)W;
-  for (int a = 0; a < A; ++a) {
-    const int cb = p * lv.K + a * lv.n;
-    int U = 0;
-    for (int r = 0; r < lv.n; ++r) U += lv.cvalid[cb + r] ? 1 : 0;
+  const int cb = p * lv.K + a * lv.n;
+  float *red = smem + (lv.TH + 2) * BW;   // transpose / backup scratch
+  int U = 0;
+  for (int r = 0; r < lv.n; ++r) U += lv.cvalid[cb + r] ? 1 : 0;
+  if (U > 0) {
+    const int y0 = tile * lv.TH;
+    const int th = min(lv.TH, m.H - y0);
+    float *band = smem;
+    const float *b = lv.pbel + (size_t)p * S;
+    s_stay[threadIdx.x] = lv.staytab[a * 256 + threadIdx.x];
+  load_band(m, lv.sig, b, y0, th, band, BW, lv.d == 0);
+    __syncthreads();
+    const int ncell = th * W;
+    const float rW = 1.0f / (float)W;
     const float *sl = &m.slip[a * 9];
-    const float *stay_a = lv.staytab + a * 256;
-    for (int r0 = 0; r0 < U; r0 += kLeafGroup) {
-      int zr[kLeafGroup];
-      float inv[kLeafGroup];
+    const float *stay_a = s_stay;
+    for (int r0 = 0; r0 < U; r0 += G) {
+      int zr[G];
+      float inv[G];
 #pragma unroll
-      for (int r = 0; r < kLeafGroup; ++r) {
+      for (int r = 0; r < G; ++r) {
         zr[r] = 0;
         inv[r] = 0.f;
         if (r0 + r < U) {
@@ -484,42 +733,310 @@ __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv) {
           inv[r] = 1.0f / lv.cpz[cb + r0 + r];
         }
       }
-      float acc[kLeafGroup * QV_MAX_ACTIONS];
+      float acc[32];
 #pragma unroll
-      for (int i = 0; i < kLeafGroup * QV_MAX_ACTIONS; ++i) acc[i] = 0.f;
-      for (int i = threadIdx.x; i < ncell; i += kBlock) {
-        const int ly = fdiv(i, W, rW), lx = i - ly * W;
-        const int t = (y0 + ly) * W + lx;
-        const uint32_t sg = lv.sig[t];
-        const float bp = predict_cell(m, band, BW, ly, lx, sg, sl, stay_a, b, t);
-        const uint32_t w = sig_wall(sg), lm = sig_lm(sg);
-        float q[QV_MAX_ACTIONS];
-        const float *Qr = lv.Q + (size_t)t * A;
+      for (int i = 0; i < 32; ++i) acc[i] = 0.f;
+      const int t00 = y0 * W;
+      for (int i0 = threadIdx.x; i0 < ncell; i0 += kLeafBatch * kBlock) {
+        uint32_t sg[kLeafBatch];
+        float bt[kLeafBatch];
+        float q[kLeafBatch][APAD];
 #pragma unroll
-        for (int c = 0; c < QV_MAX_ACTIONS; ++c) q[c] = (c < A) ? Qr[c] : 0.f;
+        for (int j = 0; j < kLeafBatch; ++j) {
+          const int i = i0 + j * kBlock;
+          const bool ok = i < ncell;
+          const int t = t00 + (ok ? i : 0);
+          sg[j] = ok ? lv.sig[t] : 0u;
+          bt[j] = ok ? b[t] : 0.f;
+          load_q_row<APAD>(lv, A, t, q[j]);
+        }
 #pragma unroll
-        for (int r = 0; r < kLeafGroup; ++r) {
-          if (r0 + r < U) {
-            const float o = wall_lik(m.flip, (uint32_t)(zr[r] & 15), w) *
-                            lm_lik(m.lm_p, (uint32_t)(zr[r] >> 4), lm);
-            const float v = o * bp * inv[r];
+        for (int j = 0; j < kLeafBatch; ++j) {
+          const int i = i0 + j * kBlock;
+          if (i >= ncell) break;
+          const int ly = fdiv(i, W, rW), lx = i - ly * W;
+          const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
+          const uint32_t w = sig_wall(sg[j]), lm = sig_lm(sg[j]);
 #pragma unroll
-            for (int c = 0; c < QV_MAX_ACTIONS; ++c)
-              acc[r * QV_MAX_ACTIONS + c] = fmaf(v, q[c], acc[r * QV_MAX_ACTIONS + c]);
+          for (int r = 0; r < G; ++r) {
+            if (r0 + r < U) {
+              const float o = wall_lik(m.flip, (uint32_t)(zr[r] & 15), w) *
+                              lm_lik(m.lm_p, (uint32_t)(zr[r] >> 4), lm);
+              const float v = o * bp * inv[r];
+#pragma unroll
+              for (int c = 0; c < APAD; ++c)
+                acc[r * APAD + c] = fmaf(v, q[j][c], acc[r * APAD + c]);
+            }
           }
         }
       }
-      const float tot = block_sum_to_thread<kLeafGroup * QV_MAX_ACTIONS>(acc, red);
-      const int r = threadIdx.x / QV_MAX_ACTIONS, c = threadIdx.x - r * QV_MAX_ACTIONS;
-      if (threadIdx.x < kLeafGroup * QV_MAX_ACTIONS && r0 + r < U && c < A)
-        lv.leafpart[((size_t)(cb + r0 + r) * lv.tiles + tile) * A + c] = tot;
+      const float tot = block_sum32(acc, red);
+      const int r = threadIdx.x / APAD, c = threadIdx.x - r * APAD;
+      if (threadIdx.x < 32 && r0 + r < U && c < A)
+        st_coherent(lv.leafpart + ((size_t)(cb + r0 + r) * lv.tiles + tile) * A + c, tot);
     }
   }
+  // every (band, action) of the node reports; the last one scores the node's
+  // children and completes the node's backup
+  wait_mem();
+  __syncthreads();
+  const long long g = tr.first[lv.d] + p;
+  if (threadIdx.x == 0) {
+    const int prev = count_arrival(&tr.node_ctr[g]);
+    s_last = (prev == A * lv.tiles - 1);
+  }
+  __syncthreads();
+  if (!s_last) return;
+  // leaf values V(c) = max_a' sum over bands, K*A sums spread over the threads
+  const int K = lv.K;
+  const long long lf = tr.first[lv.d + 1] + (long long)p * K;
+  float *sums = red + K + A;
+  for (int i = threadIdx.x; i < K * A; i += kBlock) {
+    const int c = i / A, ap = i - c * A;
+    float s = 0.f;
+    if (tr.valid[lf + c])
+      for (int t = 0; t < lv.tiles; ++t)
+        s += ld_coherent(lv.leafpart + ((size_t)(p * K + c) * lv.tiles + t) * A + ap);
+    sums[i] = s;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < K; c += kBlock) {
+    float best = 0.f;
+    if (tr.valid[lf + c]) {
+      best = -INFINITY;
+      for (int ap = 0; ap < A; ++ap) best = fmaxf(best, sums[c * A + ap]);
+      st_coherent(tr.value + lf + c, best);
+    }
+    red[c] = best;
+  }
+  __syncthreads();
+  backup_node_wg(tr, lv.d, p, red);
+  climb_wg(tr, lv.d, p, red, &s_last);
 }
 
 // ---------------------------------------------------------------------------
-// k_leaf_score: per (stored leaf slot, tile), sum_s b(s) Q(s,a')
+// k_node: grids whose belief fits in LDS -- one workgroup per Q-node (parent
+// slot, action).  The parent belief and its prediction b' stay in LDS; the
+// workgroup forms the statistics, draws the observations, and then either
+// writes the child beliefs (LEAF = false) or scores the leaf children and
+// forms the Q-node value (LEAF = true; the last Q-node of a node completes
+// the node and climbs towards the root).
 // ---------------------------------------------------------------------------
+template <int APAD, bool LEAF>
+__global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeArgs tr) {
+  extern __shared__ float smem[];
+  __shared__ float s_stay[256];
+  __shared__ float s_red[kBlock / kWave];
+  __shared__ float s_H[17];
+  __shared__ DrawOut s_draw;
+  __shared__ float s_leaf[(QV_MAX_SAMPLES + 8) * 16];
+  __shared__ int s_last;
+  const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2;
+  const int p = blockIdx.x / A, a = blockIdx.x - p * A;
+  const int cb = p * lv.K + a * lv.n;
+  const int tid = threadIdx.x;
+  if (!lv.pvalid[p]) {
+    if (tid < lv.n) {
+      lv.cvalid[cb + tid] = 0;
+      lv.cz[cb + tid] = -1;
+      lv.ccount[cb + tid] = 0;
+      lv.cpz[cb + tid] = 0.f;
+    }
+    return;
+  }
+  float *bpl = smem;                      // [S] predicted belief b'
+  float *X = smem + ((S + 3) & ~3);       // band + bins, then scratch
+  float *band = X;
+  float *hist = X + (H + 2) * BW;         // [16][kBlock] per-thread bins
+  const float *b = lv.pbel + (size_t)p * S;
+  s_stay[threadIdx.x] = lv.staytab[a * 256 + threadIdx.x];
+  load_band(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
+#pragma unroll
+  for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+  __syncthreads();
+  const float rW = 1.0f / (float)W;
+  const float *sl = &m.slip[a * 9];
+  const float *stay_a = s_stay;
+  const float rho = m.lm_p;
+  float h0 = 0.f, racc = 0.f;
+  for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
+    uint32_t sg[kCellBatch];
+    float bt[kCellBatch], rr[kCellBatch];
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int t = t0 + j * kBlock;
+      const bool ok = t < S;
+      sg[j] = ok ? lv.sig[t] : 0u;
+      bt[j] = ok ? b[t] : 0.f;
+      rr[j] = ok ? m.R[(size_t)t * A + a] : 0.f;
+    }
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int t = t0 + j * kBlock;
+      if (t >= S) break;
+      // R(b,a) = sum_x R(x,a) b(x) (Sec. III)
+      racc = fmaf(bt[j], rr[j], racc);
+      const int ly = fdiv(t, W, rW), lx = t - ly * W;
+      const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
+      bpl[t] = bp;
+      const uint32_t lm = sig_lm(sg[j]);
+      const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
+      const uint32_t w = sig_wall(sg[j]);
+      if (w == 0u)
+        h0 += contrib;
+      else
+        hist[w * kBlock + tid] += contrib;
+    }
+  }
+  hist[tid] = h0;
+  racc = wave_sum(racc);
+  if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = racc;
+  __syncthreads();
+  {
+    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s += hb[i];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    if ((tid & 15) == 0) s_H[tid >> 4] = s;
+    if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  }
+  __syncthreads();
+  // observation draws by wave 0; the band and bins are dead, X takes the
+  // landmark terms
+  if (tid < kWave) {
+    if (tid == 16) lv.reward[p * A + a] = s_H[16];
+    uint32_t *lw = (uint32_t *)X;
+    float *lvv = X + m.L;
+    for (int l = tid; l < m.L; l += kWave) {
+      lw[l] = lv.lm_wall[l];
+      const int c = m.lm_cell[l];
+      lvv[l] = (c >= 0 && c < S) ? bpl[c] : 0.f;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    sample_draws(m, lv, p, a, tid < 17 ? s_H[tid] : 0.f, lw, lvv, &s_draw);
+  }
+  __syncthreads();
+  const int U = s_draw.U;
+  if (!LEAF) {
+    // Phi(b,a,z)(x') = O(z|x') b'(x') / P(z|b,a) for each drawn z
+    for (int r = 0; r < U; ++r) {
+      const uint32_t zw = (uint32_t)(s_draw.z[r] & 15), zl = (uint32_t)(s_draw.z[r] >> 4);
+      const float inv = s_draw.inv[r];
+      float *out = lv.cbel + (size_t)(cb + r) * S;
+      for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
+        uint32_t sg[kCellBatch];
+#pragma unroll
+        for (int j = 0; j < kCellBatch; ++j) {
+          const int t = t0 + j * kBlock;
+          sg[j] = t < S ? lv.sig[t] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < kCellBatch; ++j) {
+          const int t = t0 + j * kBlock;
+          if (t < S)
+            out[t] = wall_lik(m.flip, zw, sig_wall(sg[j])) * lm_lik(rho, zl, sig_lm(sg[j])) *
+                     bpl[t] * inv;
+        }
+      }
+    }
+    return;
+  }
+  // leaves: sum_x Phi(b,a,z)(x) Q(x,a') for every drawn z and every a'
+  constexpr int G = 32 / APAD;
+  float *red = X;
+  for (int r0 = 0; r0 < U; r0 += G) {
+    uint32_t zw[G], zl[G];
+    float inv[G];
+#pragma unroll
+    for (int r = 0; r < G; ++r) {
+      const bool ok = r0 + r < U;
+      zw[r] = ok ? (uint32_t)(s_draw.z[r0 + r] & 15) : 0u;
+      zl[r] = ok ? (uint32_t)(s_draw.z[r0 + r] >> 4) : 0u;
+      inv[r] = ok ? s_draw.inv[r0 + r] : 0.f;
+    }
+    float acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = 0.f;
+    for (int t0 = tid; t0 < S; t0 += kLeafBatch * kBlock) {
+      uint32_t sg[kLeafBatch];
+      float q[kLeafBatch][APAD];
+#pragma unroll
+      for (int j = 0; j < kLeafBatch; ++j) {
+        const int t = t0 + j * kBlock;
+        sg[j] = t < S ? lv.sig[t] : 0u;
+        load_q_row<APAD>(lv, A, t < S ? t : 0, q[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < kLeafBatch; ++j) {
+        const int t = t0 + j * kBlock;
+        if (t >= S) break;
+        const float bp = bpl[t];
+        const uint32_t w = sig_wall(sg[j]), lm = sig_lm(sg[j]);
+#pragma unroll
+        for (int r = 0; r < G; ++r) {
+          if (r0 + r < U) {
+            const float v = wall_lik(m.flip, zw[r], w) * lm_lik(rho, zl[r], lm) * bp * inv[r];
+#pragma unroll
+            for (int c = 0; c < APAD; ++c) acc[r * APAD + c] = fmaf(v, q[j][c], acc[r * APAD + c]);
+          }
+        }
+      }
+    }
+    const float tot = block_sum32(acc, red);
+    if (tid < 32) s_leaf[(r0 + tid / APAD) * APAD + (tid % APAD)] = tot;
+  }
+  __syncthreads();
+  const long long g = tr.first[lv.d] + p;
+  if (tid == 0) {
+    // leaf values V = max_a' (Alg. 5) and the Q-node value (Alg. 6)
+    float q = s_H[16];
+    const long long lf = tr.first[lv.d + 1] + cb;
+    for (int r = 0; r < U; ++r) {
+      float best = -INFINITY;
+      for (int c = 0; c < A; ++c) best = fmaxf(best, s_leaf[r * APAD + c]);
+      tr.value[lf + r] = best;
+      q += tr.gamma * ((float)s_draw.count[r] / (float)lv.n) * best;
+    }
+    st_coherent(tr.qvalue + g * A + a, q);
+  }
+  wait_mem();
+  __syncthreads();
+  if (tid == 0) s_last = (count_arrival(&tr.node_ctr[g]) == A - 1);
+  __syncthreads();
+  if (!s_last) return;
+  float *sh = X;
+  if (tid < A) sh[lv.K + tid] = ld_coherent(tr.qvalue + g * A + tid);
+  __syncthreads();
+  if (tid == 0) finish_node(tr, lv.d, g, sh + lv.K);
+  __syncthreads();
+  climb_wg(tr, lv.d, p, sh, &s_last);
+}
+
+// ---------------------------------------------------------------------------
+// stored-leaf path: k_leaf_score per (leaf slot, band), then k_leaf_reduce and
+// the single-workgroup k_backup
+// ---------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ float block_sum_to_thread(float (&v)[NV], float *red) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const float s = wave_sum(v[i]);
+    if (lane == 0) red[wave * NV + i] = s;
+  }
+  __syncthreads();
+  float out = 0.f;
+  if (threadIdx.x < NV) {
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) out += red[w * NV + threadIdx.x];
+  }
+  __syncthreads();
+  return out;
+}
+
 __global__ __launch_bounds__(kBlock) void k_leaf_score(DevModel m, const float *bel,
                                                        const int32_t *valid, int tiles, int TH,
                                                        const float *Q, float *leafpart) {
@@ -546,8 +1063,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_score(DevModel m, const float *
   if (threadIdx.x < A) leafpart[((size_t)c * tiles + tile) * A + threadIdx.x] = tot;
 }
 
-// V(leaf) = max_a' sum over tiles (tile order fixed).  With is_root the leaf
-// is the root itself (depth 0) and its per-action sums are its Q-values.
+// V(leaf) = max_a' sum over bands (band order fixed).  With qroot the leaf is
+// the root itself (depth 0) and its per-action sums are its Q-values.
 __global__ void k_leaf_reduce(const int32_t *valid, int nslots, int tiles, int A,
                               const float *leafpart, float *value, float *qroot) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -562,22 +1079,7 @@ __global__ void k_leaf_reduce(const int32_t *valid, int nslots, int tiles, int A
   value[c] = best;
 }
 
-// ---------------------------------------------------------------------------
-// k_backup: bottom-up expectimax (Alg. 6/7), one workgroup
-// ---------------------------------------------------------------------------
-struct BackupArgs {
-  int D, n, K, A;
-  float gamma;
-  long long first[QV_MAX_DEPTH + 2];
-  long long slots[QV_MAX_DEPTH + 1];
-  const int32_t *valid, *count;
-  float *value, *qvalue;
-  const float *reward;
-  int32_t *action_out;
-  float *rootQ_out;
-};
-
-__global__ __launch_bounds__(1024) void k_backup(BackupArgs g) {
+__global__ __launch_bounds__(1024) void k_backup(TreeArgs g) {
   for (int d = g.D - 1; d >= 0; --d) {
     const long long f = g.first[d], fc = g.first[d + 1];
     const long long npair = g.slots[d] * g.A;
@@ -621,12 +1123,24 @@ __global__ __launch_bounds__(1024) void k_backup(BackupArgs g) {
 // ---------------------------------------------------------------------------
 static size_t band_bytes(int W, int TH) { return (size_t)(TH + 2) * (W + 2) * sizeof(float); }
 
+// LDS of k_node: b' of the whole grid, then the largest of band + bins,
+// reduction scratch, backup scratch and landmark terms.
+constexpr size_t kSmallLdsMax = 64 * 1024;
+static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
+  const size_t S = (size_t)W * H;
+  size_t x = (size_t)(H + 2) * (W + 2) + 16 * kBlock;
+  x = std::max<size_t>(x, (size_t)(kBlock / kWave) * kTransWave);
+  x = std::max<size_t>(x, (size_t)A * n + A);
+  x = std::max<size_t>(x, (size_t)2 * L);
+  return (((S + 3) & ~(size_t)3) + x) * sizeof(float);
+}
+
 hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int D, int n,
                        uint64_t seed, uint32_t qid, int flags, int32_t *action_out,
                        float *rootQ_out, char *ws, const PlanLayout &L, hipStream_t st) {
   const DevModel m = make_dev_model(mm);
   const qv_tree_layout &T = L.pub;
-  const int A = m.A, K = A * n, S = m.S;
+  const int A = m.A, K = A * n;
   const int TH = T.tile_rows, tiles = T.tiles;
   const bool store_leaves = (flags & QV_PLAN_STORE_LEAVES) != 0;
   int32_t *valid = (int32_t *)(ws + T.valid);
@@ -642,19 +1156,38 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
   float *lmv = (float *)(ws + L.lmv);
   float *leafpart = (float *)(ws + L.leafpart);
   int32_t *err = (int32_t *)(ws + L.err);
+  int32_t *ctr = (int32_t *)(ws + L.counters);
 
-  {
-    const int nthr = std::max(S, A * 256);
-    const RootRecords root = {valid, zrec, cnt, pz};
-    QV_LAUNCH(k_prep_sig, dim3((nthr + 255) / 256), dim3(256), 0, st, m, sig, staytab,
-                       err, root);
-    if (m.L > 0)
-      QV_LAUNCH(k_prep_landmarks, dim3((m.L + 255) / 256), dim3(256), 0, st, m, sig,
-                         err);
-  }
+  TreeArgs tr;
+  tr.D = D;
+  tr.n = n;
+  tr.K = K;
+  tr.A = A;
+  tr.gamma = m.gamma;
+  for (int d = 0; d < QV_MAX_DEPTH + 2; ++d) tr.first[d] = d <= D + 1 ? T.level_first[d] : 0;
+  for (int d = 0; d < QV_MAX_DEPTH + 1; ++d) tr.slots[d] = d <= D ? T.level_slots[d] : 0;
+  tr.valid = valid;
+  tr.count = cnt;
+  tr.value = value;
+  tr.qvalue = qvalue;
+  tr.reward = reward;
+  tr.node_ctr = ctr + L.stats_ctr_len;
+  tr.action_out = action_out;
+  tr.rootQ_out = rootQ_out;
+
+  uint32_t *lm_wall = (uint32_t *)(ws + L.lm_wall);
+  const PrepExtra px = {valid, zrec, cnt, pz, ctr,
+                        (long long)(L.stats_ctr_len + L.node_ctr_len), lm_wall};
+  prep_launch(m, sig, staytab, err, px, st);
+
   const size_t lds_band = band_bytes(m.W, TH);
-  const size_t lds_stats = lds_band + 16 * kBlock * sizeof(float) + 4 * QV_MAX_ACTIONS * sizeof(float);
-  const size_t lds_leaf = lds_band + 4 * kLeafGroup * QV_MAX_ACTIONS * sizeof(float);
+  const size_t lds_stats = lds_band + 16 * kBlock * sizeof(float);
+  const size_t lds_leaf =
+      lds_band + std::max<size_t>((size_t)(kBlock / kWave) * kTransWave,
+                                  (size_t)K + A + (size_t)K * A) * sizeof(float);
+  const int q_vec = (A == 4 || A == 8) && ((uintptr_t)Q % 16 == 0);
+  const size_t lds_small = small_lds_bytes(m.W, m.H, A, n, m.L);
+  const bool small = !(flags & QV_PLAN_TILED) && lds_small <= kSmallLdsMax;
   for (int d = 0; d < D; ++d) {
     LevelArgs lv;
     lv.d = d;
@@ -681,41 +1214,45 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.Q = Q;
     lv.sig = sig;
     lv.staytab = staytab;
-    const unsigned nblk = (unsigned)(lv.nslots * tiles);
-    QV_LAUNCH(k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
-    const unsigned nsamp = (unsigned)((lv.nslots * A + 3) / 4);
-    QV_LAUNCH(k_sample, dim3(nsamp), dim3(256), 0, st, m, lv);
-    if (!last || store_leaves)
-      QV_LAUNCH(k_update, dim3(nblk), dim3(kBlock), lds_band, st, m, lv);
-    else
-      QV_LAUNCH(k_leaf, dim3(nblk), dim3(kBlock), lds_leaf, st, m, lv);
+    lv.lm_wall = lm_wall;
+    lv.ctr = ctr;
+    lv.q_vec = q_vec;
+    if (small) {
+      const unsigned nq = (unsigned)((long long)lv.nslots * A);
+      if (!last || store_leaves) {
+        QV_LAUNCH_L(d, (k_node<8, false>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
+      } else if (A <= 4) {
+        QV_LAUNCH_L(d, (k_node<4, true>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
+      } else if (A <= 8) {
+        QV_LAUNCH_L(d, (k_node<8, true>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
+      } else {
+        QV_LAUNCH_L(d, (k_node<16, true>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
+      }
+      continue;
+    }
+    const unsigned nblk = (unsigned)((long long)lv.nslots * tiles * A);
+    QV_LAUNCH_L(d, k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
+    if (!last || store_leaves) {
+      QV_LAUNCH_L(d, k_update, dim3(nblk), dim3(kBlock), lds_band, st, m, lv);
+    } else if (A <= 4) {
+      QV_LAUNCH_L(d, k_leaf<4>, dim3(nblk), dim3(kBlock), lds_leaf, st, m, lv, tr);
+    } else if (A <= 8) {
+      QV_LAUNCH_L(d, k_leaf<8>, dim3(nblk), dim3(kBlock), lds_leaf, st, m, lv, tr);
+    } else {
+      QV_LAUNCH_L(d, k_leaf<16>, dim3(nblk), dim3(kBlock), lds_leaf, st, m, lv, tr);
+    }
   }
-  const long long nleaf = T.level_slots[D];
-  const int32_t *lvalid = valid + T.level_first[D];
   if (store_leaves || D == 0) {
+    const long long nleaf = T.level_slots[D];
+    const int32_t *lvalid = valid + T.level_first[D];
     const float *lb = D == 0 ? b0 : (const float *)(ws + T.belief_offset[D]);
-    QV_LAUNCH(k_leaf_score, dim3((unsigned)(nleaf * tiles)), dim3(kBlock), 0, st, m, lb,
-                       lvalid, tiles, TH, Q, leafpart);
+    QV_LAUNCH(k_leaf_score, dim3((unsigned)(nleaf * tiles)), dim3(kBlock), 0, st, m, lb, lvalid,
+              tiles, TH, Q, leafpart);
+    QV_LAUNCH(k_leaf_reduce, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st, lvalid,
+              (int)nleaf, tiles, A, leafpart, value + T.level_first[D],
+              D == 0 ? qvalue : (float *)nullptr);
+    QV_LAUNCH(k_backup, dim3(1), dim3(1024), 0, st, tr);
   }
-  QV_LAUNCH(k_leaf_reduce, dim3((unsigned)((nleaf + 255) / 256)), dim3(256), 0, st,
-                     lvalid, (int)nleaf, tiles, A, leafpart, value + T.level_first[D],
-                     D == 0 ? qvalue : (float *)nullptr);
-  BackupArgs g;
-  g.D = D;
-  g.n = n;
-  g.K = K;
-  g.A = A;
-  g.gamma = m.gamma;
-  for (int d = 0; d <= D + 1 && d < QV_MAX_DEPTH + 2; ++d) g.first[d] = T.level_first[d];
-  for (int d = 0; d <= D; ++d) g.slots[d] = T.level_slots[d];
-  g.valid = valid;
-  g.count = cnt;
-  g.value = value;
-  g.qvalue = qvalue;
-  g.reward = reward;
-  g.action_out = action_out;
-  g.rootQ_out = rootQ_out;
-  QV_LAUNCH(k_backup, dim3(1), dim3(1024), 0, st, g);
   return hipGetLastError();
 }
 

@@ -1,6 +1,7 @@
 // qv_timing.hip -- optional per-kernel timing: while enabled, every kernel
 // launch of the library is bracketed by two hipEvents recorded on the launch
 // stream, and qv_timing_read sums the elapsed times by kernel name.
+#include <cstdio>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -13,6 +14,7 @@ namespace qv {
 namespace {
 struct Rec {
   const char *name;
+  int tag;
   hipEvent_t a, b;
 };
 std::mutex g_mu;
@@ -32,7 +34,8 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
-TimingScope::TimingScope(const char *name, hipStream_t st) : name_(name), st_(st), ev_(nullptr) {
+TimingScope::TimingScope(const char *name, hipStream_t st, int tag)
+    : name_(name), st_(st), ev_(nullptr), tag_(tag) {
   std::lock_guard<std::mutex> g(g_mu);
   if (!g_on) return;
   ev_ = take_event();
@@ -45,7 +48,7 @@ TimingScope::~TimingScope() {
   hipEvent_t e = take_event();
   if (!e) return;
   if (hipEventRecord(e, st_) != hipSuccess) return;
-  g_recs.push_back({name_, (hipEvent_t)ev_, e});
+  g_recs.push_back({name_, tag_, (hipEvent_t)ev_, e});
 }
 
 }  // namespace qv
@@ -73,12 +76,17 @@ int32_t qv_timing_read(qv_kernel_time *out, int32_t max_entries, int32_t *n_out)
     float ms = 0.f;
     if (hipEventSynchronize(r.b) != hipSuccess) return QV_ERR_HIP;
     if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return QV_ERR_HIP;
+    char nm[sizeof out[0].name];
+    if (r.tag >= 0)
+      std::snprintf(nm, sizeof nm, "%s@L%d", r.name, r.tag);
+    else
+      std::snprintf(nm, sizeof nm, "%s", r.name);
     int32_t i = 0;
-    while (i < n && std::strncmp(out[i].name, r.name, sizeof out[i].name) != 0) ++i;
+    while (i < n && std::strncmp(out[i].name, nm, sizeof out[i].name) != 0) ++i;
     if (i == n) {
       if (n == max_entries) continue;
       std::memset(&out[n], 0, sizeof out[n]);
-      std::strncpy(out[n].name, r.name, sizeof out[n].name - 1);
+      std::strncpy(out[n].name, nm, sizeof out[n].name - 1);
       ++n;
     }
     out[i].launches += 1;

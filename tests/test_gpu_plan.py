@@ -36,6 +36,8 @@ def _run(prob, Q32, flags=0, D=None, n=None):
 
 
 def _check(prob, Q32, flags=0, beliefs=True):
+    if prob.D == 0:
+        beliefs = False
     pl, act, rq = _run(prob, Q32, flags)
     g = pl.tree(beliefs=beliefs)
     res = oracle.plan(prob, Q32, dump_beliefs=beliefs)
@@ -47,28 +49,34 @@ def _check(prob, Q32, flags=0, beliefs=True):
     return rep
 
 
-@pytest.mark.parametrize("seed", range(24))
-def test_plan_matches_oracle_small_grid(seed):
-    _say(f"plan 10x10 4 actions D=2 n=2 seed={seed}")
+PATHS = {"node": 0, "banded": B.QV_PLAN_TILED}
+
+
+@pytest.mark.parametrize("path", list(PATHS))
+@pytest.mark.parametrize("seed", range(16))
+def test_plan_matches_oracle_small_grid(seed, path):
+    _say(f"plan 10x10 4 actions D=2 n=2 seed={seed} path={path}")
     prob = wl.make_small(seed=seed)
-    rep = _check(prob, _q32(prob))
+    rep = _check(prob, _q32(prob), flags=PATHS[path])
     assert rep.nodes > 1
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("seed", range(2))
-def test_plan_matches_oracle_rect_grid(seed):
+def test_plan_matches_oracle_rect_grid(seed, path):
     """64x64 rectangles, 8 actions, 32 landmarks, depth 3, 4 samples."""
-    _say(f"plan 64x64 8 actions L=32 D=3 n=4 seed={seed}")
+    _say(f"plan 64x64 8 actions L=32 D=3 n=4 seed={seed} path={path}")
     prob = wl.make_rect(seed=seed)
-    rep = _check(prob, _q32(prob))
+    rep = _check(prob, _q32(prob), flags=PATHS[path])
     assert rep.nodes > 100
     assert len(rep.excused) <= 3
 
 
+@pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("case", ["depth0", "depth1", "n1", "ragged", "corridor", "goal_in_belief",
-                                  "landmark_obs", "deep"])
-def test_plan_edge_cases(case):
-    _say(f"plan edge case {case}")
+                                  "landmark_obs", "deep", "nine_actions", "many_samples"])
+def test_plan_edge_cases(case, path):
+    _say(f"plan edge case {case} path={path}")
     if case == "depth0":
         prob = wl.make_small(seed=3, D=0)
     elif case == "depth1":
@@ -76,8 +84,8 @@ def test_plan_edge_cases(case):
     elif case == "n1":
         prob = wl.make_small(seed=5, D=3, n=1)
     elif case == "ragged":
-        # 50 x 100: bands of 81 rows, the second band ragged
-        prob = wl.make_small(seed=6, W=50, H=100, D=2, n=2)
+        # 50 x 97: bands of 20 rows, the last one 17 rows
+        prob = wl.make_small(seed=6, W=50, H=97, D=2, n=2)
     elif case == "corridor":
         prob = wl.make_small(seed=7, W=40, H=1, frac=0.0, D=2, n=3)
     elif case == "goal_in_belief":
@@ -88,9 +96,18 @@ def test_plan_edge_cases(case):
     elif case == "landmark_obs":
         prob = wl.make_rect(seed=9, side=12, n_landmarks=20, D=2, n=3)
         prob.lm_p = 0.6
+    elif case == "nine_actions":
+        # the 8-neighbour set plus "stay" (A = 9, the action set of Sec. V)
+        prob = wl.make_rect(seed=14, side=16, n_landmarks=4, D=2, n=2)
+        stay = np.zeros((1, 9), np.float32)
+        stay[0, 4] = 1.0
+        prob.slip = np.concatenate([prob.slip, stay])
+        prob.R = wl.reward_step_goal(prob.occ, prob.W, prob.H, prob.slip, prob.goal)
+    elif case == "many_samples":
+        prob = wl.make_small(seed=15, W=12, H=9, D=2, n=16)
     else:
         prob = wl.make_small(seed=10, W=6, H=5, D=4, n=1)
-    _check(prob, _q32(prob))
+    _check(prob, _q32(prob), flags=PATHS[path])
 
 
 def test_plan_store_leaves_matches_fused_scoring():
@@ -110,11 +127,12 @@ def test_plan_store_leaves_matches_fused_scoring():
     parity.compare_tree(prob, t2, res["dump"])
 
 
-def test_plan_is_bitwise_deterministic():
-    _say("plan determinism 64x64")
+@pytest.mark.parametrize("path", list(PATHS))
+def test_plan_is_bitwise_deterministic(path):
+    _say(f"plan determinism 64x64 path={path}")
     prob = wl.make_rect(seed=12)
     Q32 = _q32(prob)
-    p1, a1, q1 = _run(prob, Q32)
+    p1, a1, q1 = _run(prob, Q32, flags=PATHS[path])
     t1 = p1.tree(beliefs=True)
     p1.plan(torch.as_tensor(Q32.reshape(-1)).cuda())
     t2 = p1.tree(beliefs=True)
