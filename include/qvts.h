@@ -172,6 +172,34 @@ typedef struct qv_tree_layout {
 int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
                        qv_tree_layout *out /* host */);
 
+/* ---- differentiable filter -----------------------------------------------
+ * Negative log-likelihood of logged runs under the Bayes filter of Sec. III,
+ * and its gradient with respect to the slip logits theta (T'(a,.) =
+ * softmax(theta[a*9 .. a*9+8])) and the wall-bit flip logits phi (flip_j =
+ * 1/(1+exp(-phi_j))).  For run i with start belief b_0 (b0, [S], or [ntraj*S]
+ * when b0_per_traj != 0), actions acts[i*T+t-1] and observations
+ * obs[i*T+t-1], t = 1..T:
+ *   c_t = T_{a_t}^T b_{t-1},  eta_t = sum_s O(z_t|s) c_t(s),
+ *   b_t = O(z_t|.) c_t / eta_t,  nll_out[i] = -sum_t log eta_t.
+ * g_slip [A*9] and g_flip [4] receive d(sum_i nll_i)/d(theta, phi); pass
+ * NULL for both to skip the reverse sweep.  The model's own slip and flip
+ * fields are not used; its map, landmarks and goal are.  Beliefs are stored
+ * every ckpt_every steps and each segment is recomputed for the reverse
+ * sweep, so workspace grows with T/ckpt_every + ckpt_every beliefs per
+ * concurrent run, not with T.  theta, phi, b0, acts, obs, nll_out, g_* are
+ * device arrays.  Grids need (W+2)*(H+2) + W*H + 256*A floats of LDS (at
+ * most 150 KiB, e.g. 128 x 128 with 8 actions); else QV_ERR_UNSUPPORTED.  check != 0 makes the
+ * call synchronous and reports an out-of-range action or observation
+ * (QV_ERR_INVALID_ARG; that run's nll is NaN) or a zero-probability
+ * observation (QV_ERR_ZERO_LIKELIHOOD). */
+size_t qv_filter_workspace_bytes(const qv_model *m, int32_t ntraj, int32_t T,
+                                 int32_t ckpt_every);
+int32_t qv_filter_nll_grad(const qv_model *m, const float *theta, const float *phi,
+                           int32_t ntraj, int32_t T, const float *b0, int32_t b0_per_traj,
+                           const int32_t *acts, const int32_t *obs, int32_t ckpt_every,
+                           float *nll_out, float *g_slip, float *g_flip, int32_t check,
+                           void *ws, size_t ws_bytes, void *stream);
+
 /* ---- kernel timing (benchmarking aid) ----------------------------------
  * While enabled, each kernel the library launches is bracketed by two
  * hipEvents recorded on its launch stream.  qv_timing_read (after the

@@ -611,7 +611,9 @@ double qvo_leaf_score(const qvo_model *m, const double *Q, const double *b) {
  *   ubar_t = (lambda_t - <lambda_t, b_t> - 1) / eta_t,
  *   cbar_t = O(z_t|.) * ubar_t,  dNLL/dO(z_t|s) += c_t(s) ubar_t(s),
  *   lambda_{t-1} = T_{a_t} cbar_t,  dNLL/dT'(a_t,k) += sum_s b_{t-1}(s) cbar_t(dest(s,k)).
- * The model's own slip and flip fields are ignored.  nll[i] per trajectory;
+ * The model's own slip and flip fields are ignored; its landmarks enter the
+ * likelihood as in the planner (their report probability is not a
+ * parameter).  nll[i] per trajectory;
  * g_theta, g_phi are sums over trajectories.  All beliefs are stored. */
 int qvo_filter_nll_grad(const qvo_model *m0, const double *theta,
                         const double *phi, int ntraj, int T, const double *b0,
@@ -629,7 +631,6 @@ int qvo_filter_nll_grad(const qvo_model *m0, const double *theta,
   for (int j = 0; j < 4; j++) flip[j] = 1.0 / (1.0 + exp(-phi[j]));
   m.slip = slip;
   m.flip = flip;
-  m.L = 0;
   int *lm = qvo_landmark_map(&m);
   double *bs = (double *)malloc(sizeof(double) * (size_t)S * (size_t)(T + 1));
   double *eta = (double *)malloc(sizeof(double) * (size_t)(T + 1));
@@ -668,12 +669,14 @@ int qvo_filter_nll_grad(const qvo_model *m0, const double *theta,
         double ubar = (lam[s] - lb - 1.0) / eta[t];
         double o = qvo_obs(&m, lm, z, s);
         cbar[s] = o * ubar;
-        /* dO(z|s)/dflip_j: the product over the other bits times +1 on a
-         * misread bit, -1 on a correct one */
+        /* dO(z|s)/dflip_j: the landmark factor times the product over the
+         * other bits, times +1 on a misread bit, -1 on a correct one */
         double go = c[s] * ubar;
         if (go != 0.0) {
+          double lmf = lm[s] == 0 ? ((z >> 4) == 0 ? 1.0 : 0.0)
+                                  : ((z >> 4) == 0 ? 1.0 - m.lm_p : ((z >> 4) == lm[s] ? m.lm_p : 0.0));
           for (int j = 0; j < 4; j++) {
-            double rest = 1.0;
+            double rest = lmf;
             for (int jj = 0; jj < 4; jj++) {
               if (jj == j) continue;
               int rd = (z >> jj) & 1;

@@ -38,6 +38,7 @@ EXPORTS = [
     "qv_vi_workspace_bytes", "qv_value_iterate",
     "qv_plan_workspace_bytes", "qv_plan_step", "qv_plan_layout",
     "qv_timing_enable", "qv_timing_read",
+    "qv_filter_workspace_bytes", "qv_filter_nll_grad",
 ]
 
 
@@ -112,6 +113,11 @@ def lib():
         L.qv_plan_layout.argtypes = [mp, C.c_int32, C.c_int32, C.c_int32,
                                      C.POINTER(qv_tree_layout)]
         L.qv_plan_layout.restype = C.c_int32
+        L.qv_filter_workspace_bytes.argtypes = [mp, C.c_int32, C.c_int32, C.c_int32]
+        L.qv_filter_workspace_bytes.restype = C.c_size_t
+        L.qv_filter_nll_grad.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, vp, C.c_int32, vp, vp,
+                                         C.c_int32, vp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
+        L.qv_filter_nll_grad.restype = C.c_int32
         L.qv_timing_enable.argtypes = [C.c_int32]
         L.qv_timing_enable.restype = C.c_int32
         L.qv_timing_read.argtypes = [C.POINTER(qv_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
@@ -186,6 +192,20 @@ def qv_plan_step(model, Q, b0, D, n, seed, query_id, flags, action_out, rootQ_ou
                                   C.c_uint32(int(query_id) & (2 ** 32 - 1)), int(flags),
                                   _ptr(action_out), _ptr(rootQ_out), _ptr(ws), _nbytes(ws),
                                   _stream(stream)))
+
+
+def qv_filter_workspace_bytes(model, ntraj: int, T: int, ckpt_every: int) -> int:
+    return int(lib().qv_filter_workspace_bytes(C.byref(model.c), int(ntraj), int(T),
+                                               int(ckpt_every)))
+
+
+def qv_filter_nll_grad(model, theta, phi, ntraj, T, b0, b0_per_traj, acts, obs, ckpt_every,
+                       nll_out, g_slip, g_flip, check, ws, stream=None) -> int:
+    return int(lib().qv_filter_nll_grad(C.byref(model.c), _ptr(theta), _ptr(phi), int(ntraj),
+                                        int(T), _ptr(b0), int(b0_per_traj), _ptr(acts),
+                                        _ptr(obs), int(ckpt_every), _ptr(nll_out), _ptr(g_slip),
+                                        _ptr(g_flip), int(check), _ptr(ws), _nbytes(ws),
+                                        _stream(stream)))
 
 
 def qv_timing_enable(on: bool) -> int:

@@ -1,6 +1,7 @@
 // qv_api.hip -- the extern "C" entry points of libqvts: host-side checks of
 // the problem statement (the tuple of Sec. II with the grid world of
 // Sec. V), workspace layouts, and dispatch to the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -253,6 +254,43 @@ int32_t qv_plan_step(const qv_model *m, const float *Q, const float *b0, int32_t
   if (!ws_ok(ws, ws_bytes, L.pub.total_bytes)) return QV_ERR_WORKSPACE;
   return hip_status(launch_plan(m, Q, b0, D, n, seed, query_id, flags, action_out, rootQ_out,
                                 (char *)ws, L, (hipStream_t)stream));
+}
+
+size_t qv_filter_workspace_bytes(const qv_model *m, int32_t ntraj, int32_t T,
+                                 int32_t ckpt_every) {
+  if (check_model(m) != QV_OK || ntraj < 0 || T < 1 || ckpt_every < 1 || !filter_supported(m))
+    return 0;
+  return filter_ws(m, ntraj, T, std::min(ckpt_every, T), filter_groups(ntraj));
+}
+
+int32_t qv_filter_nll_grad(const qv_model *m, const float *theta, const float *phi,
+                           int32_t ntraj, int32_t T, const float *b0, int32_t b0_per_traj,
+                           const int32_t *acts, const int32_t *obs, int32_t ckpt_every,
+                           float *nll_out, float *g_slip, float *g_flip, int32_t check,
+                           void *ws, size_t ws_bytes, void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (ntraj < 0 || T < 1 || ckpt_every < 1) return QV_ERR_INVALID_ARG;
+  if (!theta || !phi || !b0 || !acts || !obs || !nll_out) return QV_ERR_INVALID_ARG;
+  if ((g_slip == nullptr) != (g_flip == nullptr)) return QV_ERR_INVALID_ARG;
+  if (!filter_supported(m)) return QV_ERR_UNSUPPORTED;
+  const int k = std::min(ckpt_every, T);
+  const int G = filter_groups(ntraj);
+  const size_t need = filter_ws(m, ntraj, T, k, G);
+  if (!ws_ok(ws, ws_bytes, need)) return QV_ERR_WORKSPACE;
+  hipStream_t hs = (hipStream_t)stream;
+  const DevModel dm = make_dev_model(m);
+  st = hip_status(launch_filter(dm, theta, phi, ntraj, T, b0, b0_per_traj, acts, obs, k, nll_out,
+                                g_slip, g_flip, (char *)ws, G, hs));
+  if (st != QV_OK || !check) return st;
+  int32_t herr = 0;
+  st = hip_status(hipMemcpyAsync(&herr, (char *)ws + need - 256, 4, hipMemcpyDeviceToHost, hs));
+  if (st != QV_OK) return st;
+  st = hip_status(hipStreamSynchronize(hs));
+  if (st != QV_OK) return st;
+  if (herr & 4) return QV_ERR_INVALID_ARG;
+  if (herr & 8) return QV_ERR_ZERO_LIKELIHOOD;
+  return QV_OK;
 }
 
 }  // extern "C"

@@ -97,10 +97,29 @@ __device__ __forceinline__ float u24(uint32_t r) {
 // ---------------------------------------------------------------------------
 // reductions (fixed order, hence bitwise reproducible)
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+// One step of a wavefront reduction on the DPP network: v plus the value of
+// the lane selected by CTRL, for the rows enabled in ROW_MASK (others add 0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+  const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xF, false);
+  return v + __int_as_float(s);
+}
+
+// Sum over the 64 lanes in a fixed order; the total lands in lane 63
+// (pairs, quads, half rows, rows, then rows broadcast into rows 1/3 and 2/3).
+__device__ __forceinline__ float wave_total_lane63(float v) {
+  v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xF>(v);   // row_mirror
+  v = dpp_add<0x142, 0xA>(v);   // row_bcast:15
+  v = dpp_add<0x143, 0xC>(v);   // row_bcast:31
   return v;
+}
+
+// Wavefront total, returned to every lane.
+__device__ __forceinline__ float wave_sum(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_total_lane63(v)), 63));
 }
 
 __device__ __forceinline__ int wave_min(int v) {

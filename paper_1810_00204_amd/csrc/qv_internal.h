@@ -84,6 +84,13 @@ size_t belief_update_ws(const qv_model *m, int batch);
 hipError_t run_value_iteration(const DevModel &dm, float tol, int max_sweeps, float *Q,
                                double *residual, int *sweeps, char *ws, hipStream_t st);
 size_t vi_ws(const qv_model *m, int max_sweeps);
+bool filter_supported(const qv_model *m);
+int filter_groups(int ntraj);
+size_t filter_ws(const qv_model *m, int ntraj, int T, int k, int G);
+hipError_t launch_filter(const DevModel &m, const float *theta, const float *phi, int ntraj,
+                         int T, const float *b0, int b0_per_traj, const int32_t *acts,
+                         const int32_t *obs, int k, float *nll, float *g_slip, float *g_flip,
+                         char *ws, int G, hipStream_t st);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

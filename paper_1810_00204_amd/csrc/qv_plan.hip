@@ -230,30 +230,23 @@ __device__ __forceinline__ int count_arrival(int32_t *ctr) {
   return __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Workgroup totals of 32 per-thread values through an LDS transpose: each
-// wave stores its 64 x 32 values (row pitch 33, so a column read touches 32
-// different banks), lane L sums column L & 31 over half the rows, the halves
-// combine with one shuffle, and the four waves combine in wave order.
-// scratch: [4][64*33 + 32] floats.  Thread i < 32 returns total i.
-constexpr int kTransPitch = 33;
-constexpr int kTransWave = kWave * kTransPitch + 32;
-__device__ __forceinline__ float block_sum32(const float (&v)[32], float *scratch) {
+// Workgroup totals of 32 per-thread values: each wavefront reduces every
+// value on the DPP network (total in lane 63), lane 63 stores its 32 totals,
+// and thread i < 32 adds the four wavefronts' totals of value i in order.
+// red: [4][32] floats.  Ends with a barrier.
+__device__ __forceinline__ float block_sum32(float (&v)[32], float *red) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  float *rw = scratch + wave * kTransWave;
 #pragma unroll
-  for (int i = 0; i < 32; ++i) rw[lane * kTransPitch + i] = v[i];
-  __syncthreads();
-  const int col = lane & 31, h = lane >> 5;
-  float s = 0.f;
-#pragma unroll 8
-  for (int j = 0; j < 32; ++j) s += rw[(h * 32 + j) * kTransPitch + col];
-  s += __shfl_xor(s, 32, kWave);
-  if (lane < 32) rw[kWave * kTransPitch + lane] = s;
+  for (int i = 0; i < 32; ++i) v[i] = wave_total_lane63(v[i]);
+  if (lane == kWave - 1) {
+#pragma unroll
+    for (int i = 0; i < 32; ++i) red[wave * 32 + i] = v[i];
+  }
   __syncthreads();
   float out = 0.f;
   if (threadIdx.x < 32) {
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) out += scratch[w * kTransWave + kWave * kTransPitch + threadIdx.x];
+    for (int w = 0; w < kBlock / kWave; ++w) out += red[w * 32 + threadIdx.x];
   }
   __syncthreads();
   return out;
@@ -826,9 +819,10 @@ template <int APAD, bool LEAF>
 __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ float s_stay[256];
-  __shared__ float s_red[kBlock / kWave];
+  __shared__ float s_red[kBlock / kWave * 32];
   __shared__ float s_H[17];
   __shared__ DrawOut s_draw;
+  __shared__ float s_tab[QV_MAX_SAMPLES * 16];     // O_w(zw_r | w) / P(z_r)
   __shared__ float s_leaf[(QV_MAX_SAMPLES + 8) * 16];
   __shared__ int s_last;
   const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2;
@@ -845,20 +839,17 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     return;
   }
   float *bpl = smem;                      // [S] predicted belief b'
-  float *X = smem + ((S + 3) & ~3);       // band + bins, then scratch
+  float *X = smem + ((S + 3) & ~3);       // band, then bins, then scratch
   float *band = X;
-  float *hist = X + (H + 2) * BW;         // [16][kBlock] per-thread bins
   const float *b = lv.pbel + (size_t)p * S;
-  s_stay[threadIdx.x] = lv.staytab[a * 256 + threadIdx.x];
+  s_stay[tid] = lv.staytab[a * 256 + tid];
   load_band(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
-#pragma unroll
-  for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
   __syncthreads();
   const float rW = 1.0f / (float)W;
   const float *sl = &m.slip[a * 9];
-  const float *stay_a = s_stay;
   const float rho = m.lm_p;
-  float h0 = 0.f, racc = 0.f;
+  // b'(x) for every cell (slip stencil) and R(b,a) = sum_x R(x,a) b(x)
+  float racc = 0.f;
   for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
     uint32_t sg[kCellBatch];
     float bt[kCellBatch], rr[kCellBatch];
@@ -874,11 +865,32 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     for (int j = 0; j < kCellBatch; ++j) {
       const int t = t0 + j * kBlock;
       if (t >= S) break;
-      // R(b,a) = sum_x R(x,a) b(x) (Sec. III)
       racc = fmaf(bt[j], rr[j], racc);
       const int ly = fdiv(t, W, rW), lx = t - ly * W;
-      const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
-      bpl[t] = bp;
+      bpl[t] = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt[j]);
+    }
+  }
+  racc = wave_sum(racc);
+  if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = racc;
+  __syncthreads();
+  // histogram of b' by true wall reading (per-thread bins in the dead band
+  // region; landmark cells weighted by their "no landmark" factor)
+  float *hist = X;                        // [16][kBlock]
+#pragma unroll
+  for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+  float h0 = 0.f;
+  for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
+    uint32_t sg[kCellBatch];
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int t = t0 + j * kBlock;
+      sg[j] = t < S ? lv.sig[t] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int t = t0 + j * kBlock;
+      if (t >= S) break;
+      const float bp = bpl[t];
       const uint32_t lm = sig_lm(sg[j]);
       const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
       const uint32_t w = sig_wall(sg[j]);
@@ -889,8 +901,6 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     }
   }
   hist[tid] = h0;
-  racc = wave_sum(racc);
-  if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = racc;
   __syncthreads();
   {
     const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
@@ -903,8 +913,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
   }
   __syncthreads();
-  // observation draws by wave 0; the band and bins are dead, X takes the
-  // landmark terms
+  // observation draws by wave 0; X now takes the landmark terms
   if (tid < kWave) {
     if (tid == 16) lv.reward[p * A + a] = s_H[16];
     uint32_t *lw = (uint32_t *)X;
@@ -920,11 +929,17 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   }
   __syncthreads();
   const int U = s_draw.U;
+  // per drawn z: O_w(zw | w) / P(z|b,a) for the 16 wall readings
+  if (tid < U * 16) {
+    const int r = tid >> 4, w = tid & 15;
+    s_tab[tid] = wall_lik(m.flip, (uint32_t)(s_draw.z[r] & 15), (uint32_t)w) * s_draw.inv[r];
+  }
+  __syncthreads();
   if (!LEAF) {
     // Phi(b,a,z)(x') = O(z|x') b'(x') / P(z|b,a) for each drawn z
     for (int r = 0; r < U; ++r) {
-      const uint32_t zw = (uint32_t)(s_draw.z[r] & 15), zl = (uint32_t)(s_draw.z[r] >> 4);
-      const float inv = s_draw.inv[r];
+      const uint32_t zl = (uint32_t)(s_draw.z[r] >> 4);
+      const float *tab = s_tab + r * 16;
       float *out = lv.cbel + (size_t)(cb + r) * S;
       for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
         uint32_t sg[kCellBatch];
@@ -937,8 +952,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
         for (int j = 0; j < kCellBatch; ++j) {
           const int t = t0 + j * kBlock;
           if (t < S)
-            out[t] = wall_lik(m.flip, zw, sig_wall(sg[j])) * lm_lik(rho, zl, sig_lm(sg[j])) *
-                     bpl[t] * inv;
+            out[t] = tab[sig_wall(sg[j])] * lm_lik(rho, zl, sig_lm(sg[j])) * bpl[t];
         }
       }
     }
@@ -946,17 +960,10 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   }
   // leaves: sum_x Phi(b,a,z)(x) Q(x,a') for every drawn z and every a'
   constexpr int G = 32 / APAD;
-  float *red = X;
   for (int r0 = 0; r0 < U; r0 += G) {
-    uint32_t zw[G], zl[G];
-    float inv[G];
+    uint32_t zl[G];
 #pragma unroll
-    for (int r = 0; r < G; ++r) {
-      const bool ok = r0 + r < U;
-      zw[r] = ok ? (uint32_t)(s_draw.z[r0 + r] & 15) : 0u;
-      zl[r] = ok ? (uint32_t)(s_draw.z[r0 + r] >> 4) : 0u;
-      inv[r] = ok ? s_draw.inv[r0 + r] : 0.f;
-    }
+    for (int r = 0; r < G; ++r) zl[r] = r0 + r < U ? (uint32_t)(s_draw.z[r0 + r] >> 4) : 0u;
     float acc[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) acc[i] = 0.f;
@@ -978,14 +985,14 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
 #pragma unroll
         for (int r = 0; r < G; ++r) {
           if (r0 + r < U) {
-            const float v = wall_lik(m.flip, zw[r], w) * lm_lik(rho, zl[r], lm) * bp * inv[r];
+            const float v = s_tab[(r0 + r) * 16 + w] * lm_lik(rho, zl[r], lm) * bp;
 #pragma unroll
             for (int c = 0; c < APAD; ++c) acc[r * APAD + c] = fmaf(v, q[j][c], acc[r * APAD + c]);
           }
         }
       }
     }
-    const float tot = block_sum32(acc, red);
+    const float tot = block_sum32(acc, s_red);
     if (tid < 32) s_leaf[(r0 + tid / APAD) * APAD + (tid % APAD)] = tot;
   }
   __syncthreads();
@@ -1123,13 +1130,13 @@ __global__ __launch_bounds__(1024) void k_backup(TreeArgs g) {
 // ---------------------------------------------------------------------------
 static size_t band_bytes(int W, int TH) { return (size_t)(TH + 2) * (W + 2) * sizeof(float); }
 
-// LDS of k_node: b' of the whole grid, then the largest of band + bins,
-// reduction scratch, backup scratch and landmark terms.
+// Dynamic LDS of k_node: b' of the whole grid, then the largest of the band,
+// the per-thread bins, the landmark terms and the backup scratch.
 constexpr size_t kSmallLdsMax = 64 * 1024;
 static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
   const size_t S = (size_t)W * H;
-  size_t x = (size_t)(H + 2) * (W + 2) + 16 * kBlock;
-  x = std::max<size_t>(x, (size_t)(kBlock / kWave) * kTransWave);
+  size_t x = (size_t)(H + 2) * (W + 2);
+  x = std::max<size_t>(x, (size_t)16 * kBlock);
   x = std::max<size_t>(x, (size_t)A * n + A);
   x = std::max<size_t>(x, (size_t)2 * L);
   return (((S + 3) & ~(size_t)3) + x) * sizeof(float);
@@ -1183,7 +1190,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
   const size_t lds_band = band_bytes(m.W, TH);
   const size_t lds_stats = lds_band + 16 * kBlock * sizeof(float);
   const size_t lds_leaf =
-      lds_band + std::max<size_t>((size_t)(kBlock / kWave) * kTransWave,
+      lds_band + std::max<size_t>((size_t)(kBlock / kWave) * 32,
                                   (size_t)K + A + (size_t)K * A) * sizeof(float);
   const int q_vec = (A == 4 || A == 8) && ((uintptr_t)Q % 16 == 0);
   const size_t lds_small = small_lds_bytes(m.W, m.H, A, n, m.L);

@@ -355,11 +355,12 @@ class TrajectorySet:
     obs: np.ndarray                 # int32 [ntraj, T]
 
 
-def _simulate(rng, occ, W, H, slip, flip, s0, acts):
-    """Draw a state path and wall-bit observations from the generative model
-    of Sec. V: the slip outcome k ~ slip[a], the move succeeds when its
-    target is inside the grid and free, each wall bit is read correctly with
-    probability 1 - flip[j]."""
+def _simulate(rng, occ, W, H, slip, flip, s0, acts, lm_id=None, lm_p=0.0):
+    """Draw a state path and observations from the generative model of
+    Sec. V: the slip outcome k ~ slip[a], the move succeeds when its target
+    is inside the grid and free, each wall bit is read correctly with
+    probability 1 - flip[j]; on a cell with landmark id l > 0 the landmark
+    channel reports l with probability lm_p, else 0 (z = zw + 16 zl)."""
     T = acts.shape[0]
     obs = np.zeros(T, dtype=np.int32)
     s = s0
@@ -381,7 +382,10 @@ def _simulate(rng, occ, W, H, slip, flip, s0, acts):
             if rng.random() < flip[j]:
                 bit ^= 1
             zw |= bit << j
-        obs[t] = zw
+        zl = 0
+        if lm_id is not None and lm_id[s] > 0 and rng.random() < lm_p:
+            zl = int(lm_id[s])
+        obs[t] = zw + 16 * zl
     return obs
 
 
@@ -393,13 +397,16 @@ def _softmax_rows(x):
 
 def make_trajectories(seed: int = 0, side: int = 128, frac: float = 0.15,
                       ntraj: int = 1024, T: int = 50,
-                      cfg_index: int = 3) -> TrajectorySet:
+                      cfg_index: int = 3, n_landmarks: int = 0,
+                      lm_p: float = 0.9) -> TrajectorySet:
     """Logged runs for filter calibration: a side x side grid with exactly
     round(frac*S) blocked cells, 8 actions with 9-outcome slip given by true
     logits log(p + 0.01) + N(0, 0.1^2) around the 8-neighbour slip table p,
     true flip probabilities U[0.05, 0.2] per wall bit, actions uniform, start
     state drawn from the uniform belief over free cells.  The evaluation
-    point is the truth plus N(0, 0.5^2) noise on every logit."""
+    point is the truth plus N(0, 0.5^2) noise on every logit.  With
+    n_landmarks > 0, that many distinct free cells carry landmarks with
+    ids 1..n_landmarks, seen with probability lm_p."""
     rng = _rng(cfg_index, seed)
     W = H = side
     occ = occ_exact_count(rng, W, H, frac)
@@ -410,17 +417,23 @@ def make_trajectories(seed: int = 0, side: int = 128, frac: float = 0.15,
     phi_true = np.log(f_true / (1.0 - f_true))
     slip_true = _softmax_rows(theta_true)
     acts = rng.integers(0, 8, size=(ntraj, T)).astype(np.int32)
+    lm_cell = np.zeros(0, dtype=np.int32)
+    lm_id = None
+    if n_landmarks > 0:
+        lm_cell = np.sort(rng.choice(free, size=n_landmarks, replace=False)).astype(np.int32)
+        lm_id = np.zeros(W * H, dtype=np.int32)
+        lm_id[lm_cell] = np.arange(1, n_landmarks + 1)
     obs = np.zeros((ntraj, T), dtype=np.int32)
     for i in range(ntraj):
         s0 = int(free[rng.integers(0, free.size)])
-        obs[i] = _simulate(rng, occ, W, H, slip_true, f_true, s0, acts[i])
+        obs[i] = _simulate(rng, occ, W, H, slip_true, f_true, s0, acts[i], lm_id, lm_p)
     theta = theta_true + rng.normal(0.0, 0.5, size=theta_true.shape)
     phi = phi_true + rng.normal(0.0, 0.5, size=4)
     b0 = belief_uniform_cells(W * H, free)
     prob = Problem(name=f"filter{W}x{H}-8act-{ntraj}x{T}", W=W, H=H,
                    occ=occ, slip=slip_true.astype(np.float32),
                    flip=f_true.astype(np.float32),
-                   lm_cell=np.zeros(0, dtype=np.int32), lm_p=0.9,
+                   lm_cell=lm_cell, lm_p=lm_p,
                    R=np.zeros((W * H, 8), dtype=np.float32), goal=-1,
                    gamma=0.95, b0=b0)
     return TrajectorySet(problem=prob,

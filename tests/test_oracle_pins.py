@@ -550,9 +550,14 @@ def test_filter_nll_equals_path_enumeration():
         assert abs(-np.log(tot) - nll[i]) < 1e-12
 
 
-def test_filter_gradient_matches_central_differences():
+@pytest.mark.parametrize("landmarks", [False, True])
+def test_filter_gradient_matches_central_differences(landmarks):
     ts = _filter_case(side=5, ntraj=3, T=6, seed=2)
     prob = ts.problem
+    if landmarks:
+        # landmark cells scale the "no landmark" reading by 1 - lm_p
+        prob.lm_cell = np.flatnonzero(prob.occ == 0)[::3].astype(np.int32)
+        prob.lm_p = 0.7
     th = ts.theta.astype(np.float64)
     ph = ts.phi.astype(np.float64)
     nll, gt, gp = oracle.filter_nll_grad(prob, th, ph, ts.acts, ts.obs)
