@@ -15,10 +15,12 @@ Prints one JSON line: belief-state updates/s (value), plans/s, V-node
 expansions/s, the roofline of the dominant kernel (HIP events around its
 launches inside the timed region), the per-kernel breakdown, the value
 iteration, and the FP64 CPU oracle timed on a bounded sample of the same
-workload.
+workload.  Beside the headline: 256 uneven queries planned in one batched
+call against the same queries planned one by one ("batch"), one evaluation
+of the filter likelihood and its adjoint on 1024 logged runs ("filter"), and
+planning on a 512 x 512 grid ("large").
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -44,15 +46,128 @@ def parse():
                     help="force the banded multi-pass kernels (QV_PLAN_TILED)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 512 MiB device copy (PMC byte-count calibration)")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="skip the batch, filter and large-grid measurements")
+    ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--filter-steps", type=int, default=5)
+    ap.add_argument("--large-steps", type=int, default=10)
     return ap.parse_args()
 
 
+def gpu_q(B, torch, prob, dev):
+    """Q-MDP table from the library's value iteration (tol 1e-6 relative)."""
+    m = B.DeviceModel(prob, dev)
+    Q = torch.empty(m.S * m.A, dtype=torch.float32, device=dev)
+    ws = torch.empty(B.qv_vi_workspace_bytes(m, 10000), dtype=torch.uint8, device=dev)
+    st, _, sweeps = B.qv_value_iterate(m, 1e-6, 10000, Q, ws)
+    B.check(st, "qv_value_iterate")
+    return Q, sweeps
+
+
+def level_counts(tree, D):
+    lf = tree["level_first"]
+    return [int(tree["valid"][lf[d]:lf[d + 1]].sum()) for d in range(D + 1)]
+
+
+def bench_batch(args, B, wl, torch, dev):
+    """256 independent queries (sides 32..256, 10-30% blocked, N/E/S/W,
+    wall bits, depth 2-3, 3 samples): one batched call (persistent launches,
+    HIP graph per level, autotuned shape) against the same 256 queries
+    planned one qv_plan_step call after another."""
+    from paper_1810_00204_amd.planner import BatchPlanner, Planner
+    probs = wl.make_batch(seed=0)
+    Qs = [gpu_q(B, torch, p, dev)[0] for p in probs]
+    seed = 1810
+    bp = BatchPlanner(probs, Qs, device=dev, n=3, flags=B.QV_BATCH_GRAPH)
+    tune_ms = bp.autotune(seed, reps=2)
+    tc, ch = bp.shape()
+    bp.plan(seed)
+    counts = [level_counts(bp.tree(q), p.D) for q, p in enumerate(probs)]
+    upd = sum(sum(c[1:]) * p.S for c, p in zip(counts, probs))
+    for _ in range(2):
+        bp.plan(seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        bp.plan(seed)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.batch_steps
+    # the plain per-query form: each query on its own (auto kernel choice)
+    pls = [Planner(p, device=dev) for p in probs]
+    for q, pl in enumerate(pls):
+        pl.plan(Qs[q], seed=seed, query_id=q)
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for q, pl in enumerate(pls):
+            pl.plan(Qs[q], seed=seed, query_id=q)
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    nq = len(probs)
+    return {"workload": "256 queries, sides U{32..256}, 10-30% blocked, 4 actions, wall bits, "
+                        "D U{2,3}, n 3",
+            "queries": nq, "mean_cells": sum(p.S for p in probs) / nq,
+            "depth3_queries": sum(1 for p in probs if p.D == 3),
+            "ms_per_batch": t_batch * 1e3, "plans_per_s": nq / t_batch,
+            "belief_updates_per_s": upd / t_batch,
+            "sequential_ms_per_batch": t_seq * 1e3, "sequential_plans_per_s": nq / t_seq,
+            "speedup_vs_sequential": t_seq / t_batch,
+            "shape": {"tile_cells": tc, "chunk": ch, "autotune_ms_per_batch": tune_ms},
+            "graph": True}
+
+
+def bench_filter(args, B, wl, torch, dev):
+    """One evaluation = NLL and adjoint gradient of 1024 logged runs of 50
+    steps on 128 x 128 (8 actions, 9 slip outcomes), checkpoints every 10."""
+    from paper_1810_00204_amd.filter import FilterProblem
+    ts = wl.make_trajectories(seed=0)
+    fp = FilterProblem(ts.problem, ts.acts, ts.obs, device=dev, ckpt_every=10)
+    th = torch.as_tensor(ts.theta)
+    ph = torch.as_tensor(ts.phi)
+    fp.run(th, ph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.filter_steps):
+        fp.run(th, ph, check=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.filter_steps
+    ntraj, T = ts.acts.shape
+    S = ts.problem.W * ts.problem.H
+    return {"workload": f"{ntraj} runs x {T} steps, {ts.problem.W}x{ts.problem.H}, 8 actions, "
+                        "checkpoint every 10",
+            "ms_per_eval": dt * 1e3, "evals_per_s": 1.0 / dt,
+            "filter_updates_per_s": ntraj * T * S / dt,
+            "note": "one evaluation = forward filter, segment recomputation and adjoint"}
+
+
+def bench_large(args, B, wl, torch, dev):
+    """512 x 512 rectangles and corridors (25% blocked), 8 actions, 256
+    landmarks, depth 3, 3 samples, 4-patch start belief."""
+    from paper_1810_00204_amd.planner import Planner
+    prob = wl.make_large(seed=0)
+    pl = Planner(prob, device=dev)
+    t0 = time.perf_counter()
+    Q, res, sweeps = pl.value_iterate(tol=1e-6, max_sweeps=10000)
+    torch.cuda.synchronize()
+    vi_ms = (time.perf_counter() - t0) * 1e3
+    pl.plan(Q)
+    counts = level_counts(pl.tree(beliefs=False), prob.D)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.large_steps):
+        pl.plan(Q)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.large_steps
+    upd = sum(counts[1:]) * prob.S
+    return {"workload": prob.name, "ms_per_plan": dt * 1e3, "plans_per_s": 1.0 / dt,
+            "belief_updates_per_s": upd / dt, "nodes_per_level": counts,
+            "value_iteration": {"sweeps": sweeps, "residual": res, "ms": vi_ms}}
+
+
 def source_hash():
-    h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_1810_00204_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        h.update(open(os.path.join(d, f), "rb").read())
-    return h.hexdigest()[:16]
+    from paper_1810_00204_amd.build import source_hash as h
+    return h()
 
 
 def kernel_work(name, prob, counts):
@@ -219,6 +334,10 @@ def main():
         "value_iteration": {"sweeps": sweeps, "residual": res, "ms": vi_ms,
                             "sweeps_per_s": sweeps / (vi_ms * 1e-3)},
     }
+    if not args.only_headline:
+        line["batch"] = bench_batch(args, B, wl, torch, dev)
+        line["filter"] = bench_filter(args, B, wl, torch, dev)
+        line["large"] = bench_large(args, B, wl, torch, dev)
     if not args.no_cpu_baseline:
         Q32 = Q.cpu().numpy().reshape(prob.S, prob.A)
         line["cpu_baseline"] = cpu_baseline(prob, Q32, seeds[:4])

@@ -172,6 +172,61 @@ typedef struct qv_tree_layout {
 int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
                        qv_tree_layout *out /* host */);
 
+/* ---- batched planning ------------------------------------------------------
+ * Many independent planning steps (Alg. 1 inner loop, as qv_plan_step), each
+ * with its own grid, depth and Q table, expanded together: per tree level one
+ * persistent launch forms the statistics and observation draws of every
+ * Q-node of every query and a second one writes the child beliefs or, at a
+ * query's last level, scores its leaves and completes its backup.  Both take
+ * (query, parent slot, band, action) items from a work counter in device
+ * memory.  Query q draws with query_id = q; with the default shape its
+ * results equal qv_plan_step(models[q], Q[q], b0[q], depths[q], n, seed, q,
+ * QV_PLAN_TILED, ...) bit for bit.
+ *
+ * qv_batch_create checks the models (as qv_plan_step), copies the qv_model
+ * structs (not the device arrays they point to: occ, lm_cell and R must stay
+ * valid and unchanged while the batch is used) and fixes the work shape to
+ * bands of about 1024 cells (QVTS_TILE_CELLS overrides), one item per visit
+ * to the queue.  depths[q] in 1..QV_MAX_DEPTH.  With QV_BATCH_GRAPH the
+ * launches of each level are captured once into a HIP graph (on a stream of
+ * the batch's own) and replayed on the caller's stream; a new workspace
+ * address or shape recaptures.  The handle is host memory plus a small
+ * pinned buffer; it is not safe for concurrent use from several threads.
+ *
+ * qv_batch_workspace_bytes: bytes for every candidate shape (so a shape
+ * change never needs a larger workspace).
+ * qv_batch_plan: Q[q] and b0[q] are host arrays of nq DEVICE pointers (Q[q]:
+ * [S_q*A_q] FP32, b0[q]: [S_q] FP32); actions: device int32 [nq]; rootQ:
+ * device FP32 [nq*QV_MAX_ACTIONS]: row q holds query q's root Q-values,
+ * entries a >= A_q are 0.
+ * Asynchronous on stream; the first call on a workspace uploads the query
+ * descriptors and waits for that upload.
+ * qv_batch_set_shape / qv_batch_get_shape: bands of about tile_cells cells
+ * (whole rows), chunk (1..64) items taken per visit to the queue.
+ * qv_batch_autotune: runs every candidate shape (tile_cells 256..4096,
+ * chunk 1, 2, 4) reps times after one warm-up, keeps the fastest and returns
+ * its time per batch in *best_ms_out (may be NULL); synchronous.  Results of
+ * different shapes differ only in the rounding of the band sums.
+ * qv_batch_layout: query q's tree records (qv_tree_layout) and the byte
+ * offset of its region in the workspace. */
+typedef struct qv_batch qv_batch;
+#define QV_BATCH_GRAPH 1
+int32_t qv_batch_create(int32_t nq, const qv_model *models /* host [nq] */,
+                        const int32_t *depths /* host [nq] */, int32_t n, int32_t flags,
+                        qv_batch **out);
+int32_t qv_batch_destroy(qv_batch *b);
+size_t qv_batch_workspace_bytes(const qv_batch *b);
+int32_t qv_batch_set_shape(qv_batch *b, int32_t tile_cells, int32_t chunk);
+int32_t qv_batch_get_shape(const qv_batch *b, int32_t *tile_cells, int32_t *chunk);
+int32_t qv_batch_plan(qv_batch *b, const float *const *Q, const float *const *b0,
+                      uint64_t seed, int32_t *actions, float *rootQ, void *ws,
+                      size_t ws_bytes, void *stream);
+int32_t qv_batch_autotune(qv_batch *b, const float *const *Q, const float *const *b0,
+                          uint64_t seed, int32_t *actions, float *rootQ, int32_t reps,
+                          void *ws, size_t ws_bytes, void *stream, float *best_ms_out);
+int32_t qv_batch_layout(const qv_batch *b, int32_t q, qv_tree_layout *out /* host */,
+                        size_t *offset_out /* host */);
+
 /* ---- differentiable filter -----------------------------------------------
  * Negative log-likelihood of logged runs under the Bayes filter of Sec. III,
  * and its gradient with respect to the slip logits theta (T'(a,.) =
@@ -187,7 +242,8 @@ int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
  * every ckpt_every steps and each segment is recomputed for the reverse
  * sweep, so workspace grows with T/ckpt_every + ckpt_every beliefs per
  * concurrent run, not with T.  theta, phi, b0, acts, obs, nll_out, g_* are
- * device arrays.  Grids need (W+2)*(H+2) + W*H + 256*A floats of LDS (at
+ * device arrays (acts, obs and nll_out may be NULL when ntraj = 0; the
+ * gradients are then 0).  Grids need (W+2)*(H+2) + W*H + 256*A floats of LDS (at
  * most 150 KiB, e.g. 128 x 128 with 8 actions); else QV_ERR_UNSUPPORTED.  check != 0 makes the
  * call synchronous and reports an out-of-range action or observation
  * (QV_ERR_INVALID_ARG; that run's nll is NaN) or a zero-probability

@@ -30,6 +30,7 @@ QV_MAX_DEPTH = 6
 QV_MAX_SAMPLES = 16
 QV_PLAN_STORE_LEAVES = 1
 QV_PLAN_TILED = 2
+QV_BATCH_GRAPH = 1
 
 # every function the header declares
 EXPORTS = [
@@ -39,6 +40,8 @@ EXPORTS = [
     "qv_plan_workspace_bytes", "qv_plan_step", "qv_plan_layout",
     "qv_timing_enable", "qv_timing_read",
     "qv_filter_workspace_bytes", "qv_filter_nll_grad",
+    "qv_batch_create", "qv_batch_destroy", "qv_batch_workspace_bytes", "qv_batch_set_shape",
+    "qv_batch_get_shape", "qv_batch_plan", "qv_batch_autotune", "qv_batch_layout",
 ]
 
 
@@ -118,6 +121,26 @@ def lib():
         L.qv_filter_nll_grad.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, vp, C.c_int32, vp, vp,
                                          C.c_int32, vp, vp, vp, C.c_int32, vp, C.c_size_t, vp]
         L.qv_filter_nll_grad.restype = C.c_int32
+        pp = C.POINTER(C.c_void_p)
+        L.qv_batch_create.argtypes = [C.c_int32, mp, C.POINTER(C.c_int32), C.c_int32, C.c_int32,
+                                      C.POINTER(C.c_void_p)]
+        L.qv_batch_create.restype = C.c_int32
+        L.qv_batch_destroy.argtypes = [vp]
+        L.qv_batch_destroy.restype = C.c_int32
+        L.qv_batch_workspace_bytes.argtypes = [vp]
+        L.qv_batch_workspace_bytes.restype = C.c_size_t
+        L.qv_batch_set_shape.argtypes = [vp, C.c_int32, C.c_int32]
+        L.qv_batch_set_shape.restype = C.c_int32
+        L.qv_batch_get_shape.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.qv_batch_get_shape.restype = C.c_int32
+        L.qv_batch_plan.argtypes = [vp, pp, pp, C.c_uint64, vp, vp, vp, C.c_size_t, vp]
+        L.qv_batch_plan.restype = C.c_int32
+        L.qv_batch_autotune.argtypes = [vp, pp, pp, C.c_uint64, vp, vp, C.c_int32, vp,
+                                        C.c_size_t, vp, C.POINTER(C.c_float)]
+        L.qv_batch_autotune.restype = C.c_int32
+        L.qv_batch_layout.argtypes = [vp, C.c_int32, C.POINTER(qv_tree_layout),
+                                      C.POINTER(C.c_size_t)]
+        L.qv_batch_layout.restype = C.c_int32
         L.qv_timing_enable.argtypes = [C.c_int32]
         L.qv_timing_enable.restype = C.c_int32
         L.qv_timing_read.argtypes = [C.POINTER(qv_kernel_time), C.c_int32, C.POINTER(C.c_int32)]
@@ -206,6 +229,64 @@ def qv_filter_nll_grad(model, theta, phi, ntraj, T, b0, b0_per_traj, acts, obs, 
                                         _ptr(obs), int(ckpt_every), _ptr(nll_out), _ptr(g_slip),
                                         _ptr(g_flip), int(check), _ptr(ws), _nbytes(ws),
                                         _stream(stream)))
+
+
+def _ptr_array(ts):
+    arr = (C.c_void_p * max(len(ts), 1))()
+    for i, t in enumerate(ts):
+        arr[i] = _ptr(t)
+    return arr
+
+
+def qv_batch_create(models, depths, n: int, flags: int = 0):
+    """Returns (status, handle); models: list of DeviceModel."""
+    nq = len(models)
+    cm = (qv_model * max(nq, 1))(*[m.c for m in models])
+    dp = (C.c_int32 * max(nq, 1))(*[int(d) for d in depths])
+    h = C.c_void_p()
+    st = lib().qv_batch_create(int(nq), cm, dp, int(n), int(flags), C.byref(h))
+    return int(st), h
+
+
+def qv_batch_destroy(h) -> int:
+    return int(lib().qv_batch_destroy(h))
+
+
+def qv_batch_workspace_bytes(h) -> int:
+    return int(lib().qv_batch_workspace_bytes(h))
+
+
+def qv_batch_set_shape(h, tile_cells: int, chunk: int) -> int:
+    return int(lib().qv_batch_set_shape(h, int(tile_cells), int(chunk)))
+
+
+def qv_batch_get_shape(h):
+    tc, ch = C.c_int32(0), C.c_int32(0)
+    st = lib().qv_batch_get_shape(h, C.byref(tc), C.byref(ch))
+    return int(st), int(tc.value), int(ch.value)
+
+
+def qv_batch_plan(h, Qs, b0s, seed, actions, rootQ, ws, stream=None) -> int:
+    return int(lib().qv_batch_plan(h, _ptr_array(Qs), _ptr_array(b0s),
+                                   C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(actions),
+                                   _ptr(rootQ), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_batch_autotune(h, Qs, b0s, seed, actions, rootQ, reps, ws, stream=None):
+    """Returns (status, best milliseconds per batch)."""
+    ms = C.c_float(0.0)
+    st = lib().qv_batch_autotune(h, _ptr_array(Qs), _ptr_array(b0s),
+                                 C.c_uint64(int(seed) & (2 ** 64 - 1)), _ptr(actions),
+                                 _ptr(rootQ), int(reps), _ptr(ws), _nbytes(ws), _stream(stream),
+                                 C.byref(ms))
+    return int(st), float(ms.value)
+
+
+def qv_batch_layout(h, q: int):
+    out = qv_tree_layout()
+    off = C.c_size_t(0)
+    st = lib().qv_batch_layout(h, int(q), C.byref(out), C.byref(off))
+    return int(st), out, int(off.value)
 
 
 def qv_timing_enable(on: bool) -> int:

@@ -26,6 +26,18 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
+def source_hash() -> str:
+    """Hash of every file under csrc/ (kernels, headers): measurements taken
+    on one build are tagged with it."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(HERE, "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     tmp = LIB + ".tmp"

@@ -12,7 +12,7 @@ namespace qv {
 
 static thread_local int32_t g_last_hip = 0;
 
-static int32_t hip_status(hipError_t e) {
+int32_t hip_status(hipError_t e) {
   if (e == hipSuccess) return QV_OK;
   g_last_hip = (int32_t)e;
   return QV_ERR_HIP;
@@ -51,7 +51,7 @@ DevModel make_dev_model(const qv_model *m) {
   return d;
 }
 
-static int32_t check_model(const qv_model *m) {
+int32_t check_model(const qv_model *m) {
   if (!m) return QV_ERR_INVALID_ARG;
   if (m->W < 1 || m->H < 1 || m->W > QV_MAX_SIDE || m->H > QV_MAX_SIDE) return QV_ERR_INVALID_ARG;
   if (m->A < 1 || m->A > QV_MAX_ACTIONS) return QV_ERR_INVALID_ARG;
@@ -75,14 +75,14 @@ static int32_t check_model(const qv_model *m) {
   return QV_OK;
 }
 
-static bool ws_ok(const void *ws, size_t have, size_t need) {
+bool ws_ok(const void *ws, size_t have, size_t need) {
   if (need == 0) return true;
   return ws && have >= need && ((uintptr_t)ws % QV_WORKSPACE_ALIGN) == 0;
 }
 
 // Workspace of a planning query.  Returns false when the tree does not fit
 // this build's index ranges.
-static bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L) {
+bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L, int th) {
   std::memset(L, 0, sizeof *L);
   qv_tree_layout &T = L->pub;
   const long long S = (long long)m->W * m->H;
@@ -92,7 +92,7 @@ static bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLay
   T.K = K;
   T.A = A;
   T.S = (int32_t)S;
-  T.tile_rows = tile_rows(m->W, m->H);
+  T.tile_rows = th > 0 ? std::min(th, m->H) : tile_rows(m->W, m->H);
   T.tiles = (m->H + T.tile_rows - 1) / T.tile_rows;
   long long tot = 0, lv = 1;
   for (int d = 0; d <= D; ++d) {
@@ -271,7 +271,8 @@ int32_t qv_filter_nll_grad(const qv_model *m, const float *theta, const float *p
   int32_t st = check_model(m);
   if (st != QV_OK) return st;
   if (ntraj < 0 || T < 1 || ckpt_every < 1) return QV_ERR_INVALID_ARG;
-  if (!theta || !phi || !b0 || !acts || !obs || !nll_out) return QV_ERR_INVALID_ARG;
+  if (!theta || !phi || !b0) return QV_ERR_INVALID_ARG;
+  if (ntraj > 0 && (!acts || !obs || !nll_out)) return QV_ERR_INVALID_ARG;
   if ((g_slip == nullptr) != (g_flip == nullptr)) return QV_ERR_INVALID_ARG;
   if (!filter_supported(m)) return QV_ERR_UNSUPPORTED;
   const int k = std::min(ckpt_every, T);

@@ -67,9 +67,72 @@ struct TreeArgs {
   float *rootQ_out;
 };
 
+// Seeds of the map-signature pass of one query (see k_prep_sig).
+struct PrepExtra {
+  int32_t *valid, *z, *count;  // root records (nullptr: none)
+  float *pz;
+  int32_t *zero;               // counters cleared every call
+  long long nzero;
+  uint32_t *lm_wall;           // [L] wall reading of each landmark cell (or null)
+};
+
+// ---------------------------------------------------------------------------
+// batched planning
+// ---------------------------------------------------------------------------
+// One query of a batch, resident in device memory for the life of a shape.
+struct BatchQuery {
+  DevModel m;
+  TreeArgs tr;                     // action_out/rootQ_out: the batch's own slots
+  LevelArgs lv[QV_MAX_DEPTH];      // per level; the per-call fields are bound on use
+  PrepExtra px;
+  uint32_t *sig;
+  float *staytab;
+  int32_t *err;
+  int D;
+};
+
+// The per-call inputs of one query.
+struct BatchCall {
+  const float *b0, *Q;
+  uint32_t key0, key1, qid;
+  int q_vec;
+};
+
+// One persistent launch over the items of all queries at level d.
+struct BatchLevel {
+  const BatchQuery *q;
+  const BatchCall *call;
+  const int32_t *base;   // [nq+1]: first item of each query at this level
+  int32_t *queue;        // work counter of this launch (cleared by the prep pass)
+  int nq, d, total, chunk;
+};
+
+// Prep pass over all queries: base[q] is the first 256-thread block of query q.
+struct BatchPrep {
+  const BatchQuery *q;
+  const int32_t *base, *lm_base;   // [nq+1] blocks of the cell and landmark passes
+  int32_t *queue;
+  int nq, nqueue;
+};
+
 int tile_rows(int W, int H);
-void plan_layout(const qv_model *m, int D, int n, int flags, PlanLayout *L);
 DevModel make_dev_model(const qv_model *m);
+int32_t check_model(const qv_model *m);
+bool ws_ok(const void *ws, size_t have, size_t need);
+int32_t hip_status(hipError_t e);
+// Plan workspace layout with bands of th rows (th <= 0: the default).
+bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L, int th = 0);
+size_t band_lds_bytes(int W, int TH);
+size_t leaf_lds_bytes(int W, int TH, int K, int A);
+
+// batch launchers
+hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks, hipStream_t st,
+                             bool timed);
+hipError_t launch_batch_level(const BatchLevel &bl, int phase, int apad, size_t lds, int grid,
+                              hipStream_t st, bool timed);
+int batch_level_occupancy(int phase, int apad, size_t lds);
+hipError_t launch_batch_out(int nq, const int32_t *act_in, const float *rq_in, int32_t *act_out,
+                            float *rq_out, hipStream_t st);
 
 // launchers (return hipError_t)
 hipError_t launch_plan(const qv_model *m, const float *Q, const float *b0, int D, int n,

@@ -29,17 +29,10 @@ namespace qv {
 // ---------------------------------------------------------------------------
 // map signature, stay table, counters
 // ---------------------------------------------------------------------------
-struct PrepExtra {
-  int32_t *valid, *z, *count;  // root records (nullptr: none)
-  float *pz;
-  int32_t *zero;               // counters cleared every call
-  long long nzero;
-  uint32_t *lm_wall;           // [L] wall reading of each landmark cell (or null)
-};
-
-__global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *err,
-                           PrepExtra x) {
-  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// Thread g of the prep pass of one query: clears the error word, writes the
+// root records and the counters, the stay table and the signature of cell g.
+__device__ void prep_sig_one(const DevModel &m, uint32_t *sig, float *staytab, int32_t *err,
+                             const PrepExtra &x, long long g) {
   const int s = (int)g;
   if (g == 0) {
     err[0] = 0;
@@ -83,8 +76,14 @@ __global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *e
   sig[s] = v | (w << 10);
 }
 
-__global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32_t *lm_wall) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *err,
+                           PrepExtra x) {
+  prep_sig_one(m, sig, staytab, err, x, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Landmark l of one query: its id goes into the signature of its cell.
+__device__ void prep_landmark_one(const DevModel &m, uint32_t *sig, int32_t *err,
+                                  uint32_t *lm_wall, int l) {
   if (l >= m.L) return;
   const int c = m.lm_cell[l];
   if (c < 0 || c >= m.S) {
@@ -101,6 +100,10 @@ __global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32
     cur = prev;
   }
   atomicOr(err, 2);
+}
+
+__global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32_t *lm_wall) {
+  prep_landmark_one(m, sig, err, lm_wall, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 static void prep_launch(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
@@ -432,28 +435,48 @@ __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int 
   sample_draws(m, lv, p, a, hs, lw, lvv, nullptr);
 }
 
-// Decodes blockIdx.x = (p * tiles + tile) * A + a.
+// Work item idx = (p * tiles + tile) * A + a of a level.
 struct Item {
   int p, tile, a;
 };
-__device__ __forceinline__ Item decode_item(int tiles, int A) {
+__device__ __forceinline__ Item decode_item(int idx, int tiles, int A) {
   Item it;
-  const int pt = blockIdx.x / A;
-  it.a = blockIdx.x - pt * A;
+  const int pt = idx / A;
+  it.a = idx - pt * A;
   it.p = pt / tiles;
   it.tile = pt - it.p * tiles;
   return it;
 }
 
+// Static LDS of the banded item functions.
+struct BandShared {
+  float stay[256];            // stay probability of action a by neighbour pattern
+  float red[kBlock / kWave];
+  int last;
+};
+
+// The slip row of action a and the flip probabilities, copied to registers.
+struct ActTables {
+  float sl[9];
+  float fl[4];
+};
+__device__ __forceinline__ ActTables act_tables(const DevModel &m, int a) {
+  ActTables t;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) t.sl[k] = m.slip[a * 9 + k];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t.fl[j] = m.flip[j];
+  return t;
+}
+
 // ---------------------------------------------------------------------------
 // k_stats: per (parent slot, band, action)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
-  extern __shared__ float smem[];
-  __shared__ float s_stay[256];
-  __shared__ float red[kBlock / kWave];
-  __shared__ int s_last;
-  const Item it = decode_item(lv.tiles, m.A);
+__device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, float *smem,
+                           BandShared &sh) {
+  float *s_stay = sh.stay;
+  float *red = sh.red;
+  int &s_last = sh.last;
   const int p = it.p, tile = it.tile, a = it.a;
   // children of an invalid parent are marked absent by its first band
   if (!lv.pvalid[p]) {
@@ -480,9 +503,12 @@ __global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
   __syncthreads();
   const int ncell = th * W;
   const float rW = 1.0f / (float)W;
-  const float *sl = &m.slip[a * 9];
+  const ActTables at = act_tables(m, a);
+  const float *sl = at.sl;
   const float *stay_a = s_stay;
   const float rho = m.lm_p;
+  const int L = m.L;
+  const float *Rt = m.R;
   float h0 = 0.f, racc = 0.f;
   const int t00 = y0 * W;
   for (int i0 = tid; i0 < ncell; i0 += kCellBatch * kBlock) {
@@ -495,7 +521,7 @@ __global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
       const int t = t00 + (ok ? i : 0);
       sg[j] = ok ? lv.sig[t] : 0u;
       bt[j] = ok ? b[t] : 0.f;
-      rr[j] = ok ? m.R[(size_t)t * A + a] : 0.f;
+      rr[j] = ok ? Rt[(size_t)t * A + a] : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < kCellBatch; ++j) {
@@ -507,9 +533,9 @@ __global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
       const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
       const uint32_t lm = sig_lm(sg[j]);
       float contrib = bp;
-      if (lm && lm <= (uint32_t)m.L) {
+      if (lm && lm <= (uint32_t)L) {
         contrib = bp * (1.f - rho);
-        st_coherent(lv.lmv + ((size_t)p * A + a) * m.L + lm - 1, bp);
+        st_coherent(lv.lmv + ((size_t)p * A + a) * L + lm - 1, bp);
       }
       const uint32_t w = sig_wall(sg[j]);
       if (w == 0u)
@@ -547,13 +573,18 @@ __global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
   if (tid == 0) lv.ctr[p * A + a] = 0;
 }
 
+__global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ BandShared sh;
+  stats_item(m, lv, decode_item(blockIdx.x, lv.tiles, m.A), smem, sh);
+}
+
 // ---------------------------------------------------------------------------
 // k_update: per (parent slot, band, action); writes Phi(b,a,z) per child
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
-  extern __shared__ float smem[];
-  __shared__ float s_stay[256];
-  const Item it = decode_item(lv.tiles, m.A);
+__device__ void update_item(const DevModel &m, const LevelArgs &lv, Item it, float *smem,
+                            BandShared &sh) {
+  float *s_stay = sh.stay;
   const int p = it.p, tile = it.tile, a = it.a;
   if (!lv.pvalid[p]) return;
   const int cb = p * lv.K + a * lv.n;
@@ -581,7 +612,9 @@ __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
   __syncthreads();
   const int ncell = th * W;
   const float rW = 1.0f / (float)W;
-  const float *sl = &m.slip[a * 9];
+  const ActTables at = act_tables(m, a);
+  const float *sl = at.sl;
+  const float rho = m.lm_p;
   const float *stay_a = s_stay;
   const int t00 = y0 * W;
   for (int i0 = threadIdx.x; i0 < ncell; i0 += kCellBatch * kBlock) {
@@ -605,13 +638,19 @@ __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
 #pragma unroll
       for (int r = 0; r < QV_MAX_SAMPLES; ++r) {
         if (r < U) {
-          const float o = wall_lik(m.flip, (uint32_t)(zr[r] & 15), w) *
-                          lm_lik(m.lm_p, (uint32_t)(zr[r] >> 4), lm);
+          const float o = wall_lik(at.fl, (uint32_t)(zr[r] & 15), w) *
+                          lm_lik(rho, (uint32_t)(zr[r] >> 4), lm);
           lv.cbel[(size_t)(cb + r) * S + t] = o * bp * inv[r];
         }
       }
     }
   }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ BandShared sh;
+  update_item(m, lv, decode_item(blockIdx.x, lv.tiles, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -689,12 +728,11 @@ __device__ void climb_wg(const TreeArgs &t, int d, long long slot, float *sh, in
 // belief value is formed as in k_update and dotted with Q(.,a') at once
 // ---------------------------------------------------------------------------
 template <int APAD>
-__global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeArgs tr) {
+__device__ void leaf_item(const DevModel &m, const LevelArgs &lv, const TreeArgs &tr, Item it,
+                          float *smem, BandShared &sh) {
   constexpr int G = 32 / APAD;            // children per accumulation group
-  extern __shared__ float smem[];
-  __shared__ float s_stay[256];
-  __shared__ int s_last;
-  const Item it = decode_item(lv.tiles, m.A);
+  float *s_stay = sh.stay;
+  int &s_last = sh.last;
   const int p = it.p, tile = it.tile, a = it.a;
   if (!lv.pvalid[p]) return;
   const int W = m.W, BW = W + 2, A = m.A, S = m.S;
@@ -712,7 +750,9 @@ __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeA
     __syncthreads();
     const int ncell = th * W;
     const float rW = 1.0f / (float)W;
-    const float *sl = &m.slip[a * 9];
+    const ActTables at = act_tables(m, a);
+    const float *sl = at.sl;
+    const float rho = m.lm_p;
     const float *stay_a = s_stay;
     for (int r0 = 0; r0 < U; r0 += G) {
       int zr[G];
@@ -753,8 +793,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeA
 #pragma unroll
           for (int r = 0; r < G; ++r) {
             if (r0 + r < U) {
-              const float o = wall_lik(m.flip, (uint32_t)(zr[r] & 15), w) *
-                              lm_lik(m.lm_p, (uint32_t)(zr[r] >> 4), lm);
+              const float o = wall_lik(at.fl, (uint32_t)(zr[r] & 15), w) *
+                              lm_lik(rho, (uint32_t)(zr[r] >> 4), lm);
               const float v = o * bp * inv[r];
 #pragma unroll
               for (int c = 0; c < APAD; ++c)
@@ -805,6 +845,13 @@ __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeA
   __syncthreads();
   backup_node_wg(tr, lv.d, p, red);
   climb_wg(tr, lv.d, p, red, &s_last);
+}
+
+template <int APAD>
+__global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeArgs tr) {
+  extern __shared__ float smem[];
+  __shared__ BandShared sh;
+  leaf_item<APAD>(m, lv, tr, decode_item(blockIdx.x, lv.tiles, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,6 +1176,12 @@ __global__ __launch_bounds__(1024) void k_backup(TreeArgs g) {
 // host side
 // ---------------------------------------------------------------------------
 static size_t band_bytes(int W, int TH) { return (size_t)(TH + 2) * (W + 2) * sizeof(float); }
+size_t band_lds_bytes(int W, int TH) { return band_bytes(W, TH); }
+// k_leaf: the band, then the block_sum32 scratch or the backup scratch
+size_t leaf_lds_bytes(int W, int TH, int K, int A) {
+  return band_bytes(W, TH) + std::max<size_t>((size_t)(kBlock / kWave) * 32,
+                                              (size_t)K + A + (size_t)K * A) * sizeof(float);
+}
 
 // Dynamic LDS of k_node: b' of the whole grid, then the largest of the band,
 // the per-thread bins, the landmark terms and the backup scratch.
@@ -1189,9 +1242,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
 
   const size_t lds_band = band_bytes(m.W, TH);
   const size_t lds_stats = lds_band + 16 * kBlock * sizeof(float);
-  const size_t lds_leaf =
-      lds_band + std::max<size_t>((size_t)(kBlock / kWave) * 32,
-                                  (size_t)K + A + (size_t)K * A) * sizeof(float);
+  const size_t lds_leaf = leaf_lds_bytes(m.W, TH, K, A);
   const int q_vec = (A == 4 || A == 8) && ((uintptr_t)Q % 16 == 0);
   const size_t lds_small = small_lds_bytes(m.W, m.H, A, n, m.L);
   const bool small = !(flags & QV_PLAN_TILED) && lds_small <= kSmallLdsMax;
@@ -1260,6 +1311,153 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
               D == 0 ? qvalue : (float *)nullptr);
     QV_LAUNCH(k_backup, dim3(1), dim3(1024), 0, st, tr);
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched planning: the same item functions, fed from a device work queue
+// that spans every query of the batch
+// ---------------------------------------------------------------------------
+
+// Query owning item i: the last q with base[q] <= i (base[nq] = total).
+__device__ __forceinline__ int find_query(const int32_t *base, int nq, int i) {
+  int lo = 0, hi = nq;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (base[mid] <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ LevelArgs bind_level(const BatchQuery &bq, const BatchCall &c, int d) {
+  LevelArgs lv = bq.lv[d];
+  if (d == 0) lv.pbel = c.b0;
+  lv.Q = c.Q;
+  lv.q_vec = c.q_vec;
+  lv.key0 = c.key0;
+  lv.key1 = c.key1;
+  lv.qid = c.qid;
+  return lv;
+}
+
+__global__ void k_prep_batch(BatchPrep bp) {
+  const int q = find_query(bp.base, bp.nq, blockIdx.x);
+  const BatchQuery &bq = bp.q[q];
+  const long long g = (long long)(blockIdx.x - bp.base[q]) * blockDim.x + threadIdx.x;
+  prep_sig_one(bq.m, bq.sig, bq.staytab, bq.err, bq.px, g);
+  if (g < QV_MAX_ACTIONS) bq.tr.rootQ_out[g] = 0.f;   // entries a >= A stay 0
+  if (blockIdx.x == 0 && threadIdx.x < bp.nqueue) bp.queue[threadIdx.x] = 0;
+}
+
+__global__ void k_prep_landmarks_batch(BatchPrep bp) {
+  const int q = find_query(bp.lm_base, bp.nq, blockIdx.x);
+  const BatchQuery &bq = bp.q[q];
+  const int l = (blockIdx.x - bp.lm_base[q]) * blockDim.x + threadIdx.x;
+  prep_landmark_one(bq.m, bq.sig, bq.err, bq.px.lm_wall, l);
+}
+
+// PHASE 0: statistics and draws of every Q-node of level d (k_stats);
+// PHASE 1: child beliefs (k_update) or, at a query's last level, leaf scoring
+// and backup (k_leaf).  Workgroups take `chunk` items at a time from the
+// queue until it runs dry; every workgroup leaves after one failed take.
+template <int PHASE, int APAD>
+__global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
+  extern __shared__ float smem[];
+  __shared__ BandShared sh;
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(bl.queue, bl.chunk);
+    __syncthreads();
+    const int i0 = s_item;
+    if (i0 >= bl.total) break;
+    const int i1 = min(i0 + bl.chunk, bl.total);
+    for (int i = i0; i < i1; ++i) {
+      const int q = __builtin_amdgcn_readfirstlane(find_query(bl.base, bl.nq, i));
+      const BatchQuery &bq = bl.q[q];
+      const LevelArgs lv = bind_level(bq, bl.call[q], bl.d);
+      const Item it = decode_item(i - bl.base[q], lv.tiles, bq.m.A);
+      if (PHASE == 0)
+        stats_item(bq.m, lv, it, smem, sh);
+      else if (bl.d + 1 < bq.D)
+        update_item(bq.m, lv, it, smem, sh);
+      else
+        leaf_item<APAD>(bq.m, lv, bq.tr, it, smem, sh);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_batch_out(int nq, const int32_t *act_in, const float *rq_in, int32_t *act_out,
+                            float *rq_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nq) act_out[i] = act_in[i];
+  if (i < nq * QV_MAX_ACTIONS) rq_out[i] = rq_in[i];
+}
+
+#define QV_LAUNCH_T(timed, tag, kernel, grid, block, lds, st, ...)             \
+  do {                                                                      \
+    if (timed) {                                                            \
+      QV_LAUNCH_L(tag, kernel, grid, block, lds, st, __VA_ARGS__);          \
+    } else {                                                                \
+      hipLaunchKernelGGL(kernel, grid, block, lds, st, __VA_ARGS__);        \
+    }                                                                       \
+  } while (0)
+
+hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks, hipStream_t st,
+                             bool timed) {
+  QV_LAUNCH_T(timed, 0, k_prep_batch, dim3(cell_blocks), dim3(256), 0, st, bp);
+  if (lm_blocks > 0)
+    QV_LAUNCH_T(timed, 0, k_prep_landmarks_batch, dim3(lm_blocks), dim3(256), 0, st, bp);
+  return hipGetLastError();
+}
+
+template <int PHASE, int APAD>
+static const void *level_kernel() {
+  return (const void *)k_level_batch<PHASE, APAD>;
+}
+
+static const void *batch_kernel_ptr(int phase, int apad) {
+  if (phase == 0) return level_kernel<0, 4>();
+  if (apad <= 4) return level_kernel<1, 4>();
+  if (apad <= 8) return level_kernel<1, 8>();
+  return level_kernel<1, 16>();
+}
+
+int batch_level_occupancy(int phase, int apad, size_t lds) {
+  const void *k = batch_kernel_ptr(phase, apad);
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, lds) != hipSuccess) return 0;
+  return nb;
+}
+
+hipError_t launch_batch_level(const BatchLevel &bl, int phase, int apad, size_t lds, int grid,
+                              hipStream_t st, bool timed) {
+  if (grid <= 0) return hipSuccess;
+  const int d = bl.d;
+  if (phase == 0) {
+    QV_LAUNCH_T(timed, d, (k_level_batch<0, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
+  } else if (apad <= 4) {
+    QV_LAUNCH_T(timed, d, (k_level_batch<1, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
+  } else if (apad <= 8) {
+    QV_LAUNCH_T(timed, d, (k_level_batch<1, 8>), dim3(grid), dim3(kBlock), lds, st, bl);
+  } else {
+    QV_LAUNCH_T(timed, d, (k_level_batch<1, 16>), dim3(grid), dim3(kBlock), lds, st, bl);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_out(int nq, const int32_t *act_in, const float *rq_in, int32_t *act_out,
+                            float *rq_out, hipStream_t st) {
+  const int n = nq * QV_MAX_ACTIONS;
+  if (n == 0) return hipSuccess;
+  QV_LAUNCH(k_batch_out, dim3((n + 255) / 256), dim3(256), 0, st, nq, act_in, rq_in, act_out,
+            rq_out);
   return hipGetLastError();
 }
 

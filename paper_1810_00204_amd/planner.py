@@ -51,32 +51,8 @@ class Planner:
     # -- tree records -----------------------------------------------------
     def tree(self, beliefs: bool = True) -> dict:
         """Copies the tree records out of the workspace (after a sync)."""
-        torch = self.torch
-        torch.cuda.synchronize()
-        L = self.layout
-        tot = int(L.level_first[L.D + 1])
-        A, S = L.A, L.S
-        raw = self.ws
-
-        def arr(off, count, dt):
-            nbytes = count * np.dtype(dt).itemsize
-            return raw[off:off + nbytes].cpu().numpy().view(dt).copy()
-
-        out = dict(valid=arr(L.valid, tot, np.int32), z=arr(L.z, tot, np.int32),
-                   count=arr(L.count, tot, np.int32), pz=arr(L.pz, tot, np.float32),
-                   value=arr(L.value, tot, np.float32),
-                   qvalue=arr(L.qvalue, tot * A, np.float32),
-                   reward=arr(L.reward, tot * A, np.float32),
-                   level_first=[int(L.level_first[d]) for d in range(L.D + 2)],
-                   level_slots=[int(L.level_slots[d]) for d in range(L.D + 1)],
-                   tiles=int(L.tiles), tile_rows=int(L.tile_rows))
-        if beliefs:
-            out["beliefs"] = {}
-            for d in range(1, L.D + 1):
-                off = int(L.belief_offset[d])
-                if off:
-                    out["beliefs"][d] = arr(off, int(L.level_slots[d]) * S, np.float32).reshape(-1, S)
-        return out
+        self.torch.cuda.synchronize()
+        return read_tree(self.ws, self.layout, beliefs)
 
     def belief_of(self, d: int, slot: int):
         """One stored belief of level d as a float32 numpy array."""
@@ -87,6 +63,95 @@ class Planner:
         S = L.S
         start = off + slot * S * 4
         return self.ws[start:start + S * 4].cpu().numpy().view(np.float32).copy()
+
+
+def read_tree(raw, L, beliefs: bool = True) -> dict:
+    """Tree records described by layout L from the uint8 device tensor raw
+    (a workspace, or the slice of one that holds a batch query)."""
+    tot = int(L.level_first[L.D + 1])
+    A, S = L.A, L.S
+
+    def arr(off, count, dt):
+        nbytes = count * np.dtype(dt).itemsize
+        return raw[off:off + nbytes].cpu().numpy().view(dt).copy()
+
+    out = dict(valid=arr(L.valid, tot, np.int32), z=arr(L.z, tot, np.int32),
+               count=arr(L.count, tot, np.int32), pz=arr(L.pz, tot, np.float32),
+               value=arr(L.value, tot, np.float32),
+               qvalue=arr(L.qvalue, tot * A, np.float32),
+               reward=arr(L.reward, tot * A, np.float32),
+               level_first=[int(L.level_first[d]) for d in range(L.D + 2)],
+               level_slots=[int(L.level_slots[d]) for d in range(L.D + 1)],
+               tiles=int(L.tiles), tile_rows=int(L.tile_rows))
+    if beliefs:
+        out["beliefs"] = {}
+        for d in range(1, L.D + 1):
+            off = int(L.belief_offset[d])
+            if off:
+                out["beliefs"][d] = arr(off, int(L.level_slots[d]) * S, np.float32).reshape(-1, S)
+    return out
+
+
+class BatchPlanner:
+    """Many planning queries planned together (qv_batch_*): the problems'
+    device arrays, their Q tables and start beliefs, one workspace."""
+
+    def __init__(self, probs, Qs, device="cuda", n=None, flags: int = 0, b0s=None):
+        import torch
+        self.torch = torch
+        self.probs = probs
+        self.device = device
+        self.n = probs[0].n if n is None else n
+        self.models = [B.DeviceModel(p, device) for p in probs]
+        self.Qs = [torch.as_tensor(np.ascontiguousarray(q, np.float32).reshape(-1)).to(device)
+                   if not hasattr(q, "data_ptr") else q for q in Qs]
+        b0s = [p.b0 for p in probs] if b0s is None else b0s
+        self.b0s = [torch.as_tensor(np.ascontiguousarray(b, np.float32)).to(device)
+                    if not hasattr(b, "data_ptr") else b for b in b0s]
+        st, self.h = B.qv_batch_create(self.models, [p.D for p in probs], self.n, flags)
+        B.check(st, "qv_batch_create")
+        nb = B.qv_batch_workspace_bytes(self.h)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        nq = len(probs)
+        self.actions = torch.zeros(nq, dtype=torch.int32, device=device)
+        self.rootQ = torch.zeros(nq * B.QV_MAX_ACTIONS, dtype=torch.float32, device=device)
+
+    def close(self):
+        if self.h is not None and self.h.value:
+            B.check(B.qv_batch_destroy(self.h), "qv_batch_destroy")
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_shape(self, tile_cells: int, chunk: int):
+        B.check(B.qv_batch_set_shape(self.h, tile_cells, chunk), "qv_batch_set_shape")
+
+    def shape(self):
+        st, tc, ch = B.qv_batch_get_shape(self.h)
+        B.check(st, "qv_batch_get_shape")
+        return tc, ch
+
+    def plan(self, seed: int, stream=None):
+        st = B.qv_batch_plan(self.h, self.Qs, self.b0s, seed, self.actions, self.rootQ,
+                             self.ws, stream)
+        B.check(st, "qv_batch_plan")
+        return self.actions, self.rootQ.view(-1, B.QV_MAX_ACTIONS)
+
+    def autotune(self, seed: int, reps: int = 3, stream=None) -> float:
+        st, ms = B.qv_batch_autotune(self.h, self.Qs, self.b0s, seed, self.actions, self.rootQ,
+                                     reps, self.ws, stream)
+        B.check(st, "qv_batch_autotune")
+        return ms
+
+    def tree(self, q: int, beliefs: bool = False) -> dict:
+        self.torch.cuda.synchronize()
+        st, L, off = B.qv_batch_layout(self.h, q)
+        B.check(st, "qv_batch_layout")
+        return read_tree(self.ws[off:off + int(L.total_bytes)], L, beliefs)
 
 
 def belief_update(m: B.DeviceModel, b, a, z, check: bool = True, stream=None):

@@ -1,0 +1,153 @@
+"""Short text summaries of rocprofv3 output for profiles/.
+
+  python -m paper_1810_00204_amd.rocprof_summary stats <kernel_stats.csv> \\
+      --cmd "<the rocprofv3 command>" --out profiles/<kernel>_<workload>.md
+
+writes the per-kernel duration table (calls, total, average, share);
+
+  python -m paper_1810_00204_amd.rocprof_summary traffic \\
+      --fetch <FETCH_SIZE counter_collection.csv> --write <WRITE_SIZE ...csv> \\
+      --copy-bytes 536870912 --workload rect64 --cmd-fetch "..." --cmd-write "..." \\
+      --out profiles/traffic_rect64.json
+
+turns the two counter passes into HBM bytes per launch of each planning
+kernel, per tree level.  Both counters read in KiB per dispatch; each is
+scaled by what it reads for a plain device copy of --copy-bytes bytes (the
+largest copy dispatch of the run), so the result is in bytes actually
+moved.  Levels are told apart by grid size, from the tree shape of the
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+BLOCK = 256   # threads per workgroup of the planning kernels
+
+
+def short_name(full: str) -> str:
+    """'void qv::k_node<8, true>(qv::DevModel, ...)' -> 'k_node<8, true>'."""
+    s = full.strip()
+    if s.startswith("void "):
+        s = s[5:]
+    depth = 0
+    for i, ch in enumerate(s):
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            s = s[:i]
+            break
+    return re.sub(r"^qv::", "", s)
+
+
+def level_grids(workload: str):
+    """{(kernel family, grid threads): level} for the planning kernels."""
+    from paper_1810_00204_amd import workloads as wl
+    prob = {"rect64": lambda: wl.make_rect(seed=0),
+            "large512": lambda: wl.make_large(seed=0),
+            "small10": lambda: wl.make_small(seed=0)}[workload]()
+    A, K, D = prob.A, prob.A * prob.n, prob.D
+    th = max(1, min(prob.H, 1024 // prob.W))
+    tiles = (prob.H + th - 1) // th
+    out = {}
+    for d in range(D):
+        slots = K ** d
+        out[("k_node", slots * A * BLOCK)] = d
+        for fam in ("k_stats", "k_update", "k_leaf"):
+            out[(fam, slots * tiles * A * BLOCK)] = d
+    return out
+
+
+def family(name: str) -> str:
+    return name.split("<", 1)[0]
+
+
+def cmd_stats(args):
+    rows = list(csv.DictReader(open(args.csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# rocprofv3 kernel statistics: {args.title}", "",
+             "Command (from the repository root on the GPU host):", "",
+             "```", args.cmd, "```", "",
+             "| kernel | calls | total ms | average us | share |",
+             "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:args.top]:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | "
+                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{100.0 * float(r['TotalDurationNs']) / tot:.1f}% |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter(path, copy_bytes):
+    rows = list(csv.DictReader(open(path)))
+    copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+    if not copies:
+        raise SystemExit(f"{path}: no device copy dispatch to calibrate against")
+    ref_kib = max(copies)
+    scale = copy_bytes / ref_kib   # bytes per counter unit
+    per = collections.defaultdict(list)
+    for r in rows:
+        per[(short_name(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    return per, scale, ref_kib
+
+
+def cmd_traffic(args):
+    from paper_1810_00204_amd.build import source_hash
+    grids = level_grids(args.workload)
+    fetch, fs, fref = _counter(args.fetch, args.copy_bytes)
+    write, ws, wref = _counter(args.write, args.copy_bytes)
+    kern = {}
+    for (name, grid), vals in fetch.items():
+        lvl = grids.get((family(name), grid))
+        if lvl is None:
+            continue
+        key = f"{name}@L{lvl}"
+        wv = write.get((name, grid), [0.0])
+        fb = fs * sum(vals) / len(vals)
+        wb = ws * sum(wv) / len(wv)
+        kern[key] = {"fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                     "dispatches": len(vals)}
+    out = {"source_hash": source_hash(), "workload": args.workload,
+           "copy_bytes": args.copy_bytes,
+           "counter_reading_of_copy_kib": {"FETCH_SIZE": fref, "WRITE_SIZE": wref},
+           "bytes_per_counter_unit": {"FETCH_SIZE": fs, "WRITE_SIZE": ws},
+           "commands": {"FETCH_SIZE": args.cmd_fetch, "WRITE_SIZE": args.cmd_write},
+           "kernels": kern}
+    json.dump(out, open(args.out, "w"), indent=1)
+    print(json.dumps(out, indent=1))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="mode", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--cmd", required=True)
+    s.add_argument("--title", default="")
+    s.add_argument("--top", type=int, default=12)
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--copy-bytes", type=int, default=512 << 20)
+    t.add_argument("--workload", default="rect64")
+    t.add_argument("--cmd-fetch", required=True)
+    t.add_argument("--cmd-write", required=True)
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    {"stats": cmd_stats, "traffic": cmd_traffic}[a.mode](a)
+
+
+if __name__ == "__main__":
+    main()
