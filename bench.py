@@ -185,6 +185,12 @@ def kernel_work(name, prob, counts):
     stats = P * A * S * 3.0             # bin add, R(b,a) FMA
     child = C * S * 6.0                 # O product, normalisation
     score = C * S * 2.0 * A             # A FMAs against Q per leaf cell
+    # leaf scores from wall-reading histograms: per (parent, action, cell)
+    # R(b,a) (2), lambda b' (1), A FMAs with Q and the histogram add (1);
+    # per leaf child 16 A FMAs
+    hist_q = P * A * S * (2.0 + 2.0 * A + 2.0) + C * 32.0 * A
+    if "k_leaf_parent" in base:
+        return stencil + hist_q, P * S * 4.0, "alu"
     if "k_node" in base:
         if leaf:
             return stencil + stats + child + score, P * S * 4.0, "alu"
@@ -275,6 +281,9 @@ def main():
 
     # work done in the timed region
     upd = sum(sum(counts[s][1:]) for s in step_seeds) * prob.S
+    # the stricter count: posteriors written out (levels 1..D-1); leaf
+    # posteriors are scored through wall-reading histograms, not formed cell by cell
+    upd_stored = sum(sum(counts[s][1:prob.D]) for s in step_seeds) * prob.S
     exp = sum(sum(counts[s][:-1]) for s in step_seeds)
     kids = sum(sum(counts[s][1:]) for s in step_seeds)
 
@@ -325,9 +334,11 @@ def main():
                    "landmarks": prob.L, "depth": prob.D, "samples_per_action": prob.n,
                    "blocked_fraction": round(float(prob.occ.mean()), 4),
                    "draw_seeds": len(seeds), "parallelism": "single GPU",
-                   "kernels": "banded" if args.banded else "auto"},
+                   "kernels": "banded" if args.banded else "auto",
+                   "source_hash": source_hash()},
         "ms_per_step_with_kernel_events": wall_ev * 1e3 / K,
         "plans_per_s": K / wall, "v_node_expansions_per_s": exp / wall,
+        "stored_belief_updates_per_s": upd_stored / wall,
         "child_nodes_per_s": kids / wall,
         "hbm_frac_by_kernel": hbm_frac,
         "roofline": roof, "kernels": kern,

@@ -135,6 +135,17 @@ bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L,
   L->node_ctr_len = (size_t)tot;
   L->counters = take((L->stats_ctr_len + L->node_ctr_len) * 4);
   L->lm_wall = take((size_t)(m->L > 0 ? m->L : 1) * 4);
+  // the last level runs one workgroup per (parent, band of about 8192 cells)
+  L->leaf_rows = std::max(1, std::min(m->H, 8192 / m->W));
+  L->leaf_tiles = (m->H + L->leaf_rows - 1) / L->leaf_rows;
+  L->sort_cells = take((size_t)S * 4);
+  L->sort_chunk = take((size_t)L->leaf_tiles * (2 * kBlock + 17) * 4);
+  if (D > 0 && A <= 8 && L->leaf_tiles > 1) {
+    // band records sized for histograms of 8 actions, the widest a kernel
+    // uses for A <= 8 (a batch may pad a 4-action query to 8)
+    const size_t recn = (size_t)8 * 16 * 9 + 8;
+    L->leafrec = take((size_t)T.level_slots[D - 1] * L->leaf_tiles * recn * 4);
+  }
   L->err = take(256);
   T.total_bytes = off;
   return true;

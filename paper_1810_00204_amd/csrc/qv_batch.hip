@@ -29,21 +29,25 @@ int band_rows(int W, int H, int tile_cells) { return std::max(1, std::min(H, til
 using namespace qv;
 
 struct qv_batch {
-  int nq = 0, n = 0, flags = 0, dmax = 0, apad = 4;
+  int nq = 0, n = 0, flags = 0, dmax = 0;
+  // launches per level: phase 0 statistics, phase 1 children (or leaves of
+  // 9-action queries), phase 2 the per-parent last level
+  int apad[3] = {4, 4, 4};      // template widths of the three launches
   std::vector<qv_model> models;
   std::vector<int> D;
   int tile_cells = 0, chunk = 1;
   // layout of the current shape
   std::vector<PlanLayout> lay;
   std::vector<size_t> qoff;
-  size_t desc_off = 0, call_off = 0, base_off = 0, pbase_off = 0, lbase_off = 0, queue_off = 0,
-         act_off = 0, rq_off = 0, total = 0, ws_max = 0;
-  std::vector<int32_t> bases;   // [dmax][nq+1]
+  size_t desc_off = 0, call_off = 0, base_off = 0, pbase_off = 0, lbase_off = 0, sbase_off = 0,
+         queue_off = 0, act_off = 0, rq_off = 0, total = 0, ws_max = 0;
+  std::vector<int32_t> bases;   // [3 phases][dmax][nq+1]
   std::vector<int32_t> pbase;   // [nq+1] blocks of the prep pass
   std::vector<int32_t> lbase;   // [nq+1] blocks of the landmark pass
-  std::vector<int> totals;      // [dmax] items per level
-  size_t lds[2] = {0, 0};
-  int grid[2][QV_MAX_DEPTH] = {};
+  std::vector<int32_t> sbase;   // [nq+1] blocks of the leaf-band sort pass
+  std::vector<int> totals;      // [3][dmax] items per phase and level
+  size_t lds[3] = {0, 0, 0};
+  int grid[3][QV_MAX_DEPTH] = {};
   // device state
   char *bound_ws = nullptr;
   std::vector<BatchQuery> hq;
@@ -80,29 +84,44 @@ bool layout(qv_batch *b, int tile_cells, bool commit) {
   };
   const size_t desc_off = take((size_t)nq * sizeof(BatchQuery));
   const size_t call_off = take((size_t)nq * sizeof(BatchCall));
-  const size_t base_off = take((size_t)b->dmax * (nq + 1) * 4);
+  const size_t base_off = take((size_t)3 * b->dmax * (nq + 1) * 4);
   const size_t pbase_off = take((size_t)(nq + 1) * 4);
   const size_t lbase_off = take((size_t)(nq + 1) * 4);
-  const size_t queue_off = take((size_t)2 * QV_MAX_DEPTH * 4);
+  const size_t sbase_off = take((size_t)(nq + 1) * 4);
+  const size_t queue_off = take((size_t)3 * QV_MAX_DEPTH * 4);
   const size_t act_off = take((size_t)nq * 4);
   const size_t rq_off = take((size_t)nq * QV_MAX_ACTIONS * 4);
   std::vector<size_t> qoff(nq);
-  std::vector<int32_t> bases((size_t)b->dmax * (nq + 1), 0), pbase(nq + 1, 0), lbase(nq + 1, 0);
-  std::vector<long long> tot(b->dmax, 0);
-  long long pb = 0, lb = 0;
-  size_t lds0 = 0, lds1 = 0;
-  int apad = 4;
+  const size_t nb = (size_t)b->dmax * (nq + 1);
+  std::vector<int32_t> bases(3 * nb, 0), pbase(nq + 1, 0), lbase(nq + 1, 0), sbase(nq + 1, 0);
+  std::vector<long long> tot(3 * (size_t)b->dmax, 0);
+  long long pb = 0, lb = 0, sb = 0;
+  size_t lds0 = 0, lds1 = 0, lds2 = 0;
+  int apad1 = 4, apad2 = 4;
   for (int q = 0; q < nq; ++q) {
     const qv_model &m = b->models[q];
     const int th = band_rows(m.W, m.H, tile_cells);
     if (!plan_layout_impl(&m, b->D[q], b->n, 0, &lay[q], th)) return false;
     qoff[q] = take(lay[q].pub.total_bytes);
     const qv_tree_layout &T = lay[q].pub;
+    // the last level of a query with A <= 8 runs (parent, leaf band) items in
+    // phase 2; every other level runs (parent, band, action) items in phases 0, 1
+    const bool lp = m.A <= 8;
     for (int d = 0; d < b->dmax; ++d) {
-      bases[(size_t)d * (nq + 1) + q] = (int32_t)tot[d];
-      if (d < b->D[q]) tot[d] += T.level_slots[d] * T.tiles * m.A;
-      if (tot[d] > (1LL << 30)) return false;
+      for (int ph = 0; ph < 3; ++ph) {
+        bases[ph * nb + (size_t)d * (nq + 1) + q] = (int32_t)tot[ph * b->dmax + d];
+        long long items = 0;
+        const bool banded = d + 1 < b->D[q] || (d + 1 == b->D[q] && !lp);
+        if (ph < 2 && banded)
+          items = T.level_slots[d] * T.tiles * m.A;
+        else if (ph == 2 && d + 1 == b->D[q] && lp)
+          items = T.level_slots[d] * lay[q].leaf_tiles;
+        tot[ph * b->dmax + d] += items;
+        if (tot[ph * b->dmax + d] > (1LL << 30)) return false;
+      }
     }
+    sbase[q] = (int32_t)sb;
+    if (lp) sb += lay[q].leaf_tiles;
     const long long S = (long long)m.W * m.H;
     const long long nzero = (long long)(lay[q].stats_ctr_len + lay[q].node_ctr_len);
     const long long cells = std::max<long long>(std::max<long long>(S, m.A * 256LL), nzero);
@@ -112,13 +131,26 @@ bool layout(qv_batch *b, int tile_cells, bool commit) {
     lb += (m.L + 255) / 256;
     if (pb > (1LL << 30)) return false;
     lds0 = std::max(lds0, band_lds_bytes(m.W, th) + (size_t)16 * kBlock * 4);
+    if (lp) {
+      const int am = m.A <= 4 ? 4 : 8;
+      apad2 = std::max(apad2, am);
+    } else {
+      apad1 = 16;
+    }
     lds1 = std::max(lds1, leaf_lds_bytes(m.W, th, m.A * b->n, m.A));
-    apad = std::max(apad, m.A <= 4 ? 4 : (m.A <= 8 ? 8 : 16));
   }
-  for (int d = 0; d < b->dmax; ++d) bases[(size_t)d * (nq + 1) + nq] = (int32_t)tot[d];
+  // phase 2 runs at one histogram width for all its queries
+  for (int q = 0; q < nq; ++q)
+    if (b->models[q].A <= 8)
+      lds2 = std::max(lds2, leaf_parent_lds_bytes(b->models[q].W, lay[q].leaf_rows,
+                                                  b->models[q].L, apad2));
+  for (int ph = 0; ph < 3; ++ph)
+    for (int d = 0; d < b->dmax; ++d)
+      bases[ph * nb + (size_t)d * (nq + 1) + nq] = (int32_t)tot[ph * b->dmax + d];
   pbase[nq] = (int32_t)pb;
   lbase[nq] = (int32_t)lb;
-  if (lds0 > 150 * 1024 || lds1 > 150 * 1024) return false;
+  sbase[nq] = (int32_t)sb;
+  if (lds0 > 150 * 1024 || lds1 > 150 * 1024 || lds2 > 150 * 1024) return false;
   if (!commit) {
     b->ws_max = std::max(b->ws_max, off);
     return true;
@@ -130,6 +162,7 @@ bool layout(qv_batch *b, int tile_cells, bool commit) {
   b->base_off = base_off;
   b->pbase_off = pbase_off;
   b->lbase_off = lbase_off;
+  b->sbase_off = sbase_off;
   b->queue_off = queue_off;
   b->act_off = act_off;
   b->rq_off = rq_off;
@@ -137,11 +170,15 @@ bool layout(qv_batch *b, int tile_cells, bool commit) {
   b->bases = bases;
   b->pbase = pbase;
   b->lbase = lbase;
-  b->totals.assign(b->dmax, 0);
-  for (int d = 0; d < b->dmax; ++d) b->totals[d] = (int)tot[d];
+  b->sbase = sbase;
+  b->totals.assign(3 * (size_t)b->dmax, 0);
+  for (size_t i = 0; i < tot.size(); ++i) b->totals[i] = (int)tot[i];
   b->lds[0] = lds0;
   b->lds[1] = lds1;
-  b->apad = apad;
+  b->lds[2] = lds2;
+  b->apad[0] = 4;
+  b->apad[1] = apad1;
+  b->apad[2] = apad2;
   b->tile_cells = tile_cells;
   b->bound_ws = nullptr;
   drop_graphs(b);
@@ -155,11 +192,12 @@ bool size_grids(qv_batch *b) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return false;
-  for (int ph = 0; ph < 2; ++ph) {
-    const int occ = batch_level_occupancy(ph, b->apad, b->lds[ph]);
+  for (int ph = 0; ph < 3; ++ph) {
+    const int occ = batch_level_occupancy(ph, b->apad[ph], b->lds[ph]);
     if (occ <= 0) return false;
     for (int d = 0; d < b->dmax; ++d) {
-      const long long visits = ((long long)b->totals[d] + b->chunk - 1) / b->chunk;
+      const long long visits =
+          ((long long)b->totals[ph * b->dmax + d] + b->chunk - 1) / b->chunk;
       b->grid[ph][d] = (int)std::min<long long>(visits, (long long)cus * occ);
     }
   }
@@ -208,6 +246,7 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
     bq.err = (int32_t *)(qb + L.err);
     uint32_t *lm_wall = (uint32_t *)(qb + L.lm_wall);
     bq.px = {valid, zrec, cnt, pz, ctr, (long long)(L.stats_ctr_len + L.node_ctr_len), lm_wall};
+    bq.leaf_parent = A <= 8 ? 1 : 0;
     for (int d = 0; d < D; ++d) {
       LevelArgs &lv = bq.lv[d];
       lv.d = d;
@@ -231,6 +270,13 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
       lv.staytab = bq.staytab;
       lv.lm_wall = lm_wall;
       lv.ctr = ctr;
+      lv.sort_cells = (const int32_t *)(qb + L.sort_cells);
+      lv.sort_chunk = (const int32_t *)(qb + L.sort_chunk);
+      if (d + 1 == D && bq.leaf_parent) {
+        lv.TH = L.leaf_rows;
+        lv.tiles = L.leaf_tiles;
+        lv.part = (float *)(qb + L.leafrec);
+      }
     }
   }
   int32_t s;
@@ -246,6 +292,9 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
   s = hip_status(hipMemcpyAsync(ws + b->lbase_off, b->lbase.data(), b->lbase.size() * 4,
                                 hipMemcpyHostToDevice, st));
   if (s) return s;
+  s = hip_status(hipMemcpyAsync(ws + b->sbase_off, b->sbase.data(), b->sbase.size() * 4,
+                                hipMemcpyHostToDevice, st));
+  if (s) return s;
   s = hip_status(hipStreamSynchronize(st));
   if (s) return s;
   b->bound_ws = ws;
@@ -258,9 +307,10 @@ BatchPrep prep_args(const qv_batch *b, char *ws) {
   bp.q = (const BatchQuery *)(ws + b->desc_off);
   bp.base = (const int32_t *)(ws + b->pbase_off);
   bp.lm_base = (const int32_t *)(ws + b->lbase_off);
+  bp.sort_base = (const int32_t *)(ws + b->sbase_off);
   bp.queue = (int32_t *)(ws + b->queue_off);
   bp.nq = b->nq;
-  bp.nqueue = 2 * b->dmax;
+  bp.nqueue = 3 * b->dmax;
   return bp;
 }
 
@@ -268,11 +318,12 @@ BatchLevel level_args(const qv_batch *b, char *ws, int d, int phase) {
   BatchLevel bl;
   bl.q = (const BatchQuery *)(ws + b->desc_off);
   bl.call = (const BatchCall *)(ws + b->call_off);
-  bl.base = (const int32_t *)(ws + b->base_off) + (size_t)d * (b->nq + 1);
-  bl.queue = (int32_t *)(ws + b->queue_off) + 2 * d + phase;
+  bl.base = (const int32_t *)(ws + b->base_off) +
+            ((size_t)phase * b->dmax + d) * (b->nq + 1);
+  bl.queue = (int32_t *)(ws + b->queue_off) + 3 * d + phase;
   bl.nq = b->nq;
   bl.d = d;
-  bl.total = b->totals[d];
+  bl.total = b->totals[(size_t)phase * b->dmax + d];
   bl.chunk = b->chunk;
   return bl;
 }
@@ -281,12 +332,13 @@ BatchLevel level_args(const qv_batch *b, char *ws, int d, int phase) {
 hipError_t enqueue_level(const qv_batch *b, char *ws, int d, hipStream_t st, bool timed) {
   hipError_t e;
   if (d == 0) {
-    e = launch_batch_prep(prep_args(b, ws), b->pbase[b->nq], b->lbase[b->nq], st, timed);
+    e = launch_batch_prep(prep_args(b, ws), b->pbase[b->nq], b->lbase[b->nq], b->sbase[b->nq],
+                          st, timed);
     if (e != hipSuccess) return e;
   }
-  for (int ph = 0; ph < 2; ++ph) {
-    e = launch_batch_level(level_args(b, ws, d, ph), ph, b->apad, b->lds[ph], b->grid[ph][d], st,
-                           timed);
+  for (int ph = 0; ph < 3; ++ph) {
+    e = launch_batch_level(level_args(b, ws, d, ph), ph, b->apad[ph], b->lds[ph],
+                           b->grid[ph][d], st, timed);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -352,7 +404,9 @@ int32_t run(qv_batch *b, const float *const *Q, const float *const *b0, uint64_t
     c.key1 = (uint32_t)(seed >> 32);
     c.qid = (uint32_t)q;
     const int A = b->models[q].A;
-    c.q_vec = (A == 4 || A == 8) && A == b->apad && ((uintptr_t)Q[q] % 16 == 0);
+    // Q rows are read (by the leaf-parent items) as float4 when they are
+    // exactly as wide as the kernel's histograms
+    c.q_vec = (A == 4 || A == 8) && A == b->apad[2] && ((uintptr_t)Q[q] % 16 == 0);
   }
   s = hip_status(hipMemcpyAsync(ws + b->call_off, b->call_host, (size_t)b->nq * sizeof(BatchCall),
                                 hipMemcpyHostToDevice, st));

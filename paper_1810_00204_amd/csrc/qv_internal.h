@@ -28,6 +28,9 @@ struct PlanPtrs {
 struct PlanLayout {
   qv_tree_layout pub;
   size_t sig, staytab, part, lmv, leafpart, err, counters, lm_wall;
+  size_t sort_cells, sort_chunk;   // [S] and [leaf_tiles][2*kBlock + 17] int32
+  int leaf_rows, leaf_tiles;       // bands of the per-parent leaf level
+  size_t leafrec;                  // [slots_{D-1}][leaf_tiles][record] band records
   size_t part_slots;      // max slots of a non-leaf level
   size_t stats_ctr_len;   // int32 counters: bands done per (slot, action)
   size_t node_ctr_len;    // int32 counters: parts done per node
@@ -51,6 +54,8 @@ struct LevelArgs {
   const uint32_t *lm_wall;  // [L] true wall reading of each landmark cell
   int32_t *ctr;           // [nslots*A] bands finished per Q-node
   int q_vec;              // Q rows can be read as float4 (A = 4 or 8, aligned)
+  // free cells in true-wall-reading order and their chunks (see k_prep_sort)
+  const int32_t *sort_cells, *sort_chunk;
 };
 
 // Whole-tree view for the expectimax backup (Alg. 6/7).
@@ -89,6 +94,7 @@ struct BatchQuery {
   float *staytab;
   int32_t *err;
   int D;
+  int leaf_parent;                 // last level by (parent, band) items over all actions
 };
 
 // The per-call inputs of one query.
@@ -111,6 +117,7 @@ struct BatchLevel {
 struct BatchPrep {
   const BatchQuery *q;
   const int32_t *base, *lm_base;   // [nq+1] blocks of the cell and landmark passes
+  const int32_t *sort_base;        // [nq+1] blocks of the leaf-band sort pass
   int32_t *queue;
   int nq, nqueue;
 };
@@ -126,8 +133,9 @@ size_t band_lds_bytes(int W, int TH);
 size_t leaf_lds_bytes(int W, int TH, int K, int A);
 
 // batch launchers
-hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks, hipStream_t st,
-                             bool timed);
+hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks,
+                             int sort_blocks, hipStream_t st, bool timed);
+size_t leaf_parent_lds_bytes(int W, int TH, int L, int AM);
 hipError_t launch_batch_level(const BatchLevel &bl, int phase, int apad, size_t lds, int grid,
                               hipStream_t st, bool timed);
 int batch_level_occupancy(int phase, int apad, size_t lds);

@@ -106,6 +106,147 @@ __global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32
   prep_landmark_one(m, sig, err, lm_wall, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+// Sorted cell entries: bits 0..21 the cell index (S <= 2048 * 2048 = 2^22),
+// bits 22..29 the cell's 8-neighbour move pattern (signature bits 0..7),
+// bit 30 goal, bit 31 landmark.
+constexpr uint32_t kSortCell = 0x3FFFFFu;
+constexpr int kSortOutShift = 22;
+constexpr uint32_t kSortGoal = 1u << 30;
+constexpr uint32_t kSortLandmark = 1u << 31;
+
+// Free cells of one band of rows grouped by their true wall reading w
+// (stable: ascending cell index within a reading), for the leaf-level
+// wall-reading histograms.  The band's cells are [c_lo, c_hi); its ordered
+// list takes the same positions of `cells`, cut into at most kBlock chunks
+// of at most C cells, each holding one reading only: with
+// C = ceil(Sf / (kBlock - 16)) for the band's Sf free cells, the 16
+// readings need sum_w ceil(n_w / C) <= Sf / C + 16 <= kBlock chunks.
+//   cells[c_lo + k]             ordered free cells (packed entries, see above)
+//   chunk[2k], chunk[2k+1]      first and one-past-last position of chunk k
+//                               (equal for unused k)
+//   chunk[2 kBlock + w]         first chunk of reading w, w = 0..16
+// One workgroup per band; thread i first counts cells c_lo + [i R, (i+1) R).
+constexpr int kSortChunkInts = 2 * kBlock + 17;
+constexpr int kSortMaxCells = 16384;   // cells of one sorted band (leaf bands <= 8192)
+// per-cell summary kept in LDS while sorting: bits 0..7 move pattern, 8..11
+// wall reading, 12 free, 13 goal, 14 landmark
+__device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_t *cells,
+                          int32_t *chunk) {
+  __shared__ int cnt[16 * kBlock];   // [w][thread], then exclusive offsets
+  __shared__ uint16_t cs[kSortMaxCells];
+  __shared__ int wtot[kBlock / kWave];
+  __shared__ int s_start[17], s_pchunk[17], s_C;
+  const int tid = threadIdx.x;
+  const int S = c_hi - c_lo;
+  // the band's signatures, coalesced, eight loads in flight per thread
+  for (int i0 = tid; i0 < S; i0 += 8 * kBlock) {
+    uint32_t sg[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * kBlock;
+      sg[k] = i < S ? sig[c_lo + i] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int i = i0 + k * kBlock;
+      if (i < S) {
+        const uint32_t lm = sig_lm(sg[k]);
+        cs[i] = (uint16_t)(sig_out8(sg[k]) | (sig_wall(sg[k]) << 8) |
+                           ((sg[k] & kSigFree) ? 1u << 12 : 0u) |
+                           ((sg[k] & kSigGoal) ? 1u << 13 : 0u) |
+                           ((lm && lm <= (uint32_t)L) ? 1u << 14 : 0u));
+      }
+    }
+  }
+  __syncthreads();
+  const int R = (S + kBlock - 1) / kBlock;
+  const int c0 = min(S, tid * R), c1 = min(S, c0 + R);   // band-relative
+  int n[16];
+#pragma unroll
+  for (int w = 0; w < 16; ++w) n[w] = 0;
+  for (int t = c0; t < c1; ++t) {
+    const uint32_t c = cs[t];
+    const int w = (c & (1u << 12)) ? (int)((c >> 8) & 15u) : -1;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) n[k] += (w == k) ? 1 : 0;
+  }
+#pragma unroll
+  for (int w = 0; w < 16; ++w) cnt[w * kBlock + tid] = n[w];
+  __syncthreads();
+  // exclusive scan of cnt in (w, thread) order: thread i owns entries
+  // [16 i, 16 i + 16), then the 256 owner totals are scanned
+  int loc[16], sum = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    loc[k] = sum;
+    sum += cnt[16 * tid + k];
+  }
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  int inc = sum;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(inc, o, kWave);
+    if (lane >= o) inc += y;
+  }
+  if (lane == kWave - 1) wtot[wave] = inc;
+  __syncthreads();
+  int base = inc - sum;
+  for (int v = 0; v < wave; ++v) base += wtot[v];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) cnt[16 * tid + k] = base + loc[k];
+  __syncthreads();
+  if (tid == 0) {
+    int Sf = 0;
+    for (int v = 0; v < kBlock / kWave; ++v) Sf += wtot[v];
+    const int C = max(1, (Sf + (kBlock - 16) - 1) / (kBlock - 16));
+    int pc = 0;
+    for (int w = 0; w < 16; ++w) {
+      s_start[w] = cnt[w * kBlock];
+      s_pchunk[w] = pc;
+      const int nw = (w < 15 ? cnt[(w + 1) * kBlock] : Sf) - cnt[w * kBlock];
+      pc += (nw + C - 1) / C;
+    }
+    s_start[16] = Sf;
+    s_pchunk[16] = pc;
+    s_C = C;
+  }
+  // scatter: each thread walks its cells again in order
+  int o[16];
+#pragma unroll
+  for (int w = 0; w < 16; ++w) o[w] = cnt[w * kBlock + tid];
+  for (int t = c0; t < c1; ++t) {
+    const uint32_t c = cs[t];
+    if (!(c & (1u << 12))) continue;
+    const int w = (int)((c >> 8) & 15u);
+    int pos = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (w == k) pos = o[k]++;
+    cells[c_lo + pos] = (int32_t)((uint32_t)(c_lo + t) | ((c & 0xFFu) << kSortOutShift) |
+                                  ((c & (1u << 13)) ? kSortGoal : 0u) |
+                                  ((c & (1u << 14)) ? kSortLandmark : 0u));
+  }
+  __syncthreads();
+  // chunk k belongs to the reading w with pchunk[w] <= k < pchunk[w+1]
+  int w = 0;
+  while (w < 16 && s_pchunk[w + 1] <= tid) ++w;
+  int j0 = 0, j1 = 0;
+  if (w < 16) {
+    j0 = s_start[w] + (tid - s_pchunk[w]) * s_C;
+    j1 = min(j0 + s_C, s_start[w + 1]);
+  }
+  chunk[2 * tid] = c_lo + j0;
+  chunk[2 * tid + 1] = c_lo + j1;
+  if (tid <= 16) chunk[2 * kBlock + tid] = s_pchunk[tid];
+}
+
+// band = blockIdx.x: cells [band * TC, min(S, (band + 1) * TC))
+__global__ __launch_bounds__(kBlock) void k_prep_sort(int S, int TC, int L, const uint32_t *sig,
+                                                       int32_t *cells, int32_t *chunk) {
+  const int c_lo = blockIdx.x * TC;
+  sort_band(c_lo, min(S, c_lo + TC), L, sig, cells, chunk + (size_t)blockIdx.x * kSortChunkInts);
+}
+
 static void prep_launch(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
                         const PrepExtra &x, hipStream_t st) {
   const long long n = std::max<long long>(std::max(dm.S, dm.A * 256), x.nzero);
@@ -193,6 +334,8 @@ __device__ __forceinline__ float predict_cell_v(const float *band, int BW, int l
 
 constexpr int kCellBatch = 4;   // cells whose loads a thread issues together
 constexpr int kLeafBatch = 2;
+constexpr int kNodeBatch = 16;  // the same in k_node (bound by LDS, not registers)
+constexpr int kSortBatch = 8;   // cells of a leaf-histogram chunk loaded together
 
 // Q(t, .) padded to APAD entries; float4 loads when rows are APAD wide.
 template <int APAD>
@@ -418,10 +561,25 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
 __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int a, float *lds) {
   const int lane = threadIdx.x & (kWave - 1);
   const int idx = p * m.A + a;
+  // the 17 band sums: lane j adds bands j, j+64, ... (loads issued together),
+  // then each value is reduced across the wavefront in a fixed order
+  const float *pp = lv.part + (size_t)idx * lv.tiles * 17;
+  float v[17];
+#pragma unroll
+  for (int k = 0; k < 17; ++k) v[k] = 0.f;
+  for (int t = lane; t < lv.tiles; t += kWave) {
+    float x[17];
+#pragma unroll
+    for (int k = 0; k < 17; ++k) x[k] = ld_coherent(pp + (size_t)t * 17 + k);
+#pragma unroll
+    for (int k = 0; k < 17; ++k) v[k] += x[k];
+  }
   float hs = 0.f;
-  if (lane < 17) {
-    const float *pp = lv.part + (size_t)idx * lv.tiles * 17 + lane;
-    for (int t = 0; t < lv.tiles; ++t) hs += ld_coherent(pp + t * 17);
+#pragma unroll
+  for (int k = 0; k < 17; ++k) {
+    const float tot = __int_as_float(
+        __builtin_amdgcn_readlane(__float_as_int(wave_total_lane63(v[k])), 63));
+    if (lane == k) hs = tot;
   }
   if (lane == 16) lv.reward[idx] = hs;
   uint32_t *lw = (uint32_t *)lds;
@@ -433,6 +591,16 @@ __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int 
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   sample_draws(m, lv, p, a, hs, lw, lvv, nullptr);
+}
+
+// Workgroups go to the 8 XCDs in turn (workgroup id mod 8), each XCD with
+// its own L2.  This renumbering gives every XCD a contiguous range of
+// logical ids, so neighbouring items -- the actions of one parent, which
+// read the same parent belief -- meet in one L2.  A bijection on [0, n).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_local_id(int i, int n) {
+  const int q = n / kXcds, r = n - q * kXcds, x = i % kXcds;
+  return x * q + min(x, r) + i / kXcds;
 }
 
 // Work item idx = (p * tiles + tile) * A + a of a level.
@@ -576,7 +744,7 @@ __device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, floa
 __global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
-  stats_item(m, lv, decode_item(blockIdx.x, lv.tiles, m.A), smem, sh);
+  stats_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv.tiles, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -650,7 +818,7 @@ __device__ void update_item(const DevModel &m, const LevelArgs &lv, Item it, flo
 __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
-  update_item(m, lv, decode_item(blockIdx.x, lv.tiles, m.A), smem, sh);
+  update_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv.tiles, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -851,7 +1019,7 @@ template <int APAD>
 __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
-  leaf_item<APAD>(m, lv, tr, decode_item(blockIdx.x, lv.tiles, m.A), smem, sh);
+  leaf_item<APAD>(m, lv, tr, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv.tiles, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -871,9 +1039,11 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   __shared__ DrawOut s_draw;
   __shared__ float s_tab[QV_MAX_SAMPLES * 16];     // O_w(zw_r | w) / P(z_r)
   __shared__ float s_leaf[(QV_MAX_SAMPLES + 8) * 16];
+  __shared__ float s_HQ[LEAF ? 16 * (APAD + 1) : 1];
   __shared__ int s_last;
   const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2;
-  const int p = blockIdx.x / A, a = blockIdx.x - p * A;
+  const int bid = xcd_local_id(blockIdx.x, gridDim.x);
+  const int p = bid / A, a = bid - p * A;
   const int cb = p * lv.K + a * lv.n;
   const int tid = threadIdx.x;
   if (!lv.pvalid[p]) {
@@ -897,11 +1067,11 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   const float rho = m.lm_p;
   // b'(x) for every cell (slip stencil) and R(b,a) = sum_x R(x,a) b(x)
   float racc = 0.f;
-  for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
-    uint32_t sg[kCellBatch];
-    float bt[kCellBatch], rr[kCellBatch];
+  for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
+    uint32_t sg[kNodeBatch];
+    float bt[kNodeBatch], rr[kNodeBatch];
 #pragma unroll
-    for (int j = 0; j < kCellBatch; ++j) {
+    for (int j = 0; j < kNodeBatch; ++j) {
       const int t = t0 + j * kBlock;
       const bool ok = t < S;
       sg[j] = ok ? lv.sig[t] : 0u;
@@ -909,57 +1079,107 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
       rr[j] = ok ? m.R[(size_t)t * A + a] : 0.f;
     }
 #pragma unroll
-    for (int j = 0; j < kCellBatch; ++j) {
+    for (int j = 0; j < kNodeBatch; ++j) {
       const int t = t0 + j * kBlock;
-      if (t >= S) break;
-      racc = fmaf(bt[j], rr[j], racc);
-      const int ly = fdiv(t, W, rW), lx = t - ly * W;
-      bpl[t] = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt[j]);
+      if (t < S) {
+        racc = fmaf(bt[j], rr[j], racc);
+        const int ly = fdiv(t, W, rW), lx = t - ly * W;
+        bpl[t] = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt[j]);
+      }
     }
   }
   racc = wave_sum(racc);
   if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = racc;
   __syncthreads();
-  // histogram of b' by true wall reading (per-thread bins in the dead band
-  // region; landmark cells weighted by their "no landmark" factor)
-  float *hist = X;                        // [16][kBlock]
+  if (LEAF) {
+    // Every leaf child's score comes from histograms by true wall reading w:
+    //   HQ[w][c] = sum over free x with reading w of lambda(x) b'(x) Q(x,c),
+    //   HQ[w][APAD] = sum of lambda(x) b'(x)  (the histogram behind P(z)),
+    // lambda = 1 - rho on landmark cells, else 1.  Cells come in reading
+    // order; thread k sums chunk k (one reading), then the chunk partials of
+    // each reading are added in chunk order.
+    constexpr int NV = APAD + 1;
+    float *part = X;                      // [kBlock][NV]
+    const int j0 = lv.sort_chunk[2 * tid], j1 = lv.sort_chunk[2 * tid + 1];
+    float acc[NV];
 #pragma unroll
-  for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
-  float h0 = 0.f;
-  for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
-    uint32_t sg[kCellBatch];
+    for (int c = 0; c < NV; ++c) acc[c] = 0.f;
+    for (int j = j0; j < j1; j += kSortBatch) {
+      uint32_t e[kSortBatch];
+      float q[kSortBatch][APAD];
 #pragma unroll
-    for (int j = 0; j < kCellBatch; ++j) {
-      const int t = t0 + j * kBlock;
-      sg[j] = t < S ? lv.sig[t] : 0u;
+      for (int k = 0; k < kSortBatch; ++k) e[k] = j + k < j1 ? (uint32_t)lv.sort_cells[j + k] : 0u;
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) load_q_row<APAD>(lv, A, (int)(e[k] & kSortCell), q[k]);
+#pragma unroll
+      for (int k = 0; k < kSortBatch; ++k) {
+        if (j + k < j1) {
+          const float bp = bpl[e[k] & kSortCell];
+          const float v = (e[k] & kSortLandmark) ? bp * (1.f - rho) : bp;
+#pragma unroll
+          for (int c = 0; c < APAD; ++c) acc[c] = fmaf(v, q[k][c], acc[c]);
+          acc[APAD] += v;
+        }
+      }
     }
 #pragma unroll
-    for (int j = 0; j < kCellBatch; ++j) {
-      const int t = t0 + j * kBlock;
-      if (t >= S) break;
-      const float bp = bpl[t];
-      const uint32_t lm = sig_lm(sg[j]);
-      const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
-      const uint32_t w = sig_wall(sg[j]);
-      if (w == 0u)
-        h0 += contrib;
-      else
-        hist[w * kBlock + tid] += contrib;
+    for (int c = 0; c < NV; ++c) part[tid * NV + c] = acc[c];
+    __syncthreads();
+    const int32_t *pch = lv.sort_chunk + 2 * kBlock;
+    for (int i = tid; i < 16 * NV; i += kBlock) {
+      const int w = i / NV, c = i - w * NV;
+      float sum = 0.f;
+      for (int k = pch[w]; k < pch[w + 1]; ++k) sum += part[k * NV + c];
+      s_HQ[i] = sum;
     }
+    __syncthreads();
+    if (tid < 16) s_H[tid] = s_HQ[tid * NV + APAD];
+    if (tid == 16) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    __syncthreads();
   }
-  hist[tid] = h0;
-  __syncthreads();
-  {
-    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
-    float s = 0.f;
+  if (!LEAF) {
+    // histogram of b' by true wall reading (per-thread bins in the dead band
+    // region; landmark cells weighted by their "no landmark" factor)
+    float *hist = X;                        // [16][kBlock]
 #pragma unroll
-    for (int i = 0; i < 16; ++i) s += hb[i];
+    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+    float h0 = 0.f;
+    for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
+      uint32_t sg[kNodeBatch];
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-    if ((tid & 15) == 0) s_H[tid >> 4] = s;
-    if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+      for (int j = 0; j < kNodeBatch; ++j) {
+        const int t = t0 + j * kBlock;
+        sg[j] = t < S ? lv.sig[t] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < kNodeBatch; ++j) {
+        const int t = t0 + j * kBlock;
+        if (t < S) {
+          const float bp = bpl[t];
+          const uint32_t lm = sig_lm(sg[j]);
+          const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
+          const uint32_t w = sig_wall(sg[j]);
+          if (w == 0u)
+            h0 += contrib;
+          else
+            hist[w * kBlock + tid] += contrib;
+        }
+      }
+    }
+    hist[tid] = h0;
+    __syncthreads();
+    {
+      const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
+      float s = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s += hb[i];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+      if ((tid & 15) == 0) s_H[tid >> 4] = s;
+      if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
   // observation draws by wave 0; X now takes the landmark terms
   if (tid < kWave) {
     if (tid == 16) lv.reward[p * A + a] = s_H[16];
@@ -977,26 +1197,27 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   __syncthreads();
   const int U = s_draw.U;
   // per drawn z: O_w(zw | w) / P(z|b,a) for the 16 wall readings
-  if (tid < U * 16) {
+  if (!LEAF && tid < U * 16) {
     const int r = tid >> 4, w = tid & 15;
     s_tab[tid] = wall_lik(m.flip, (uint32_t)(s_draw.z[r] & 15), (uint32_t)w) * s_draw.inv[r];
   }
   __syncthreads();
   if (!LEAF) {
-    // Phi(b,a,z)(x') = O(z|x') b'(x') / P(z|b,a) for each drawn z
-    for (int r = 0; r < U; ++r) {
-      const uint32_t zl = (uint32_t)(s_draw.z[r] >> 4);
-      const float *tab = s_tab + r * 16;
-      float *out = lv.cbel + (size_t)(cb + r) * S;
-      for (int t0 = tid; t0 < S; t0 += kCellBatch * kBlock) {
-        uint32_t sg[kCellBatch];
+    // Phi(b,a,z)(x') = O(z|x') b'(x') / P(z|b,a) for each drawn z (the
+    // signatures of a batch of cells are loaded once for all children)
+    for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
+      uint32_t sg[kNodeBatch];
 #pragma unroll
-        for (int j = 0; j < kCellBatch; ++j) {
-          const int t = t0 + j * kBlock;
-          sg[j] = t < S ? lv.sig[t] : 0u;
-        }
+      for (int j = 0; j < kNodeBatch; ++j) {
+        const int t = t0 + j * kBlock;
+        sg[j] = t < S ? lv.sig[t] : 0u;
+      }
+      for (int r = 0; r < U; ++r) {
+        const uint32_t zl = (uint32_t)(s_draw.z[r] >> 4);
+        const float *tab = s_tab + r * 16;
+        float *out = lv.cbel + (size_t)(cb + r) * S;
 #pragma unroll
-        for (int j = 0; j < kCellBatch; ++j) {
+        for (int j = 0; j < kNodeBatch; ++j) {
           const int t = t0 + j * kBlock;
           if (t < S)
             out[t] = tab[sig_wall(sg[j])] * lm_lik(rho, zl, sig_lm(sg[j])) * bpl[t];
@@ -1005,42 +1226,31 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     }
     return;
   }
-  // leaves: sum_x Phi(b,a,z)(x) Q(x,a') for every drawn z and every a'
-  constexpr int G = 32 / APAD;
-  for (int r0 = 0; r0 < U; r0 += G) {
-    uint32_t zl[G];
+  // leaves (Alg. 5): sum_x Phi(b,a,z_r)(x) Q(x,c) for drawn z_r = zw + 16 zl
+  // and every action c, from the histograms:
+  //   zl = 0:  (1/P(z_r)) sum_w O_w(zw|w) HQ[w][c]
+  //   zl = l:  (1/P(z_r)) O_w(zw|w_l) rho b'(x_l) Q(x_l,c)   (x_l the cell of l)
+  // (X still holds the landmark walls and masses staged for the draws)
+  if (tid < U * APAD) {
+    constexpr int NV = APAD + 1;
+    const int r = tid / APAD, c = tid - r * APAD;
+    float v = 0.f;
+    if (c < A) {
+      const int z = s_draw.z[r];
+      const uint32_t zw = (uint32_t)(z & 15);
+      const int zl = z >> 4;
+      if (zl == 0) {
 #pragma unroll
-    for (int r = 0; r < G; ++r) zl[r] = r0 + r < U ? (uint32_t)(s_draw.z[r0 + r] >> 4) : 0u;
-    float acc[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) acc[i] = 0.f;
-    for (int t0 = tid; t0 < S; t0 += kLeafBatch * kBlock) {
-      uint32_t sg[kLeafBatch];
-      float q[kLeafBatch][APAD];
-#pragma unroll
-      for (int j = 0; j < kLeafBatch; ++j) {
-        const int t = t0 + j * kBlock;
-        sg[j] = t < S ? lv.sig[t] : 0u;
-        load_q_row<APAD>(lv, A, t < S ? t : 0, q[j]);
+        for (int w = 0; w < 16; ++w) v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), s_HQ[w * NV + c], v);
+      } else {
+        const uint32_t *lw = (const uint32_t *)X;
+        const float *lvv = X + m.L;
+        const int cell = m.lm_cell[zl - 1];
+        v = wall_lik(m.flip, zw, lw[zl - 1]) * rho * lvv[zl - 1] * lv.Q[(size_t)cell * A + c];
       }
-#pragma unroll
-      for (int j = 0; j < kLeafBatch; ++j) {
-        const int t = t0 + j * kBlock;
-        if (t >= S) break;
-        const float bp = bpl[t];
-        const uint32_t w = sig_wall(sg[j]), lm = sig_lm(sg[j]);
-#pragma unroll
-        for (int r = 0; r < G; ++r) {
-          if (r0 + r < U) {
-            const float v = s_tab[(r0 + r) * 16 + w] * lm_lik(rho, zl[r], lm) * bp;
-#pragma unroll
-            for (int c = 0; c < APAD; ++c) acc[r * APAD + c] = fmaf(v, q[j][c], acc[r * APAD + c]);
-          }
-        }
-      }
+      v *= s_draw.inv[r];
     }
-    const float tot = block_sum32(acc, s_red);
-    if (tid < 32) s_leaf[(r0 + tid / APAD) * APAD + (tid % APAD)] = tot;
+    s_leaf[r * APAD + c] = v;
   }
   __syncthreads();
   const long long g = tr.first[lv.d] + p;
@@ -1067,6 +1277,272 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   if (tid == 0) finish_node(tr, lv.d, g, sh + lv.K);
   __syncthreads();
   climb_wg(tr, lv.d, p, sh, &s_last);
+}
+
+// ---------------------------------------------------------------------------
+// k_leaf_parent: the last level with one workgroup per (parent slot, band of
+// rows) that handles every action of the parent.  A leaf child's score is
+// sum_x Phi(b,a,z)(x) Q(x,c) with Phi(b,a,z)(x) = O(z|x) b'_a(x) / P(z|b,a),
+// and O(z|x) depends on x only through its true wall reading w(x) and its
+// landmark, so every child of every action follows from
+//   HQ_a[w][c] = sum over free x with reading w of lambda(x) b'_a(x) Q(x,c),
+//   HQ_a[w][A'] = sum of lambda(x) b'_a(x)       (the histogram behind P(z)),
+// lambda = 1 - rho on landmark cells, else 1, plus the predicted mass b'_a on
+// each landmark cell.  The workgroup walks its band's free cells in wall-
+// reading order (k_prep_sort), forms b'_a(x) for every action from the one
+// 3x3 neighbourhood, and reads each Q and R row once for all actions.  With
+// several bands per parent, the band records are summed in band order by the
+// last band to finish; then the wavefronts draw the observations of the
+// actions in parallel, and the workgroup forms the leaf and Q-node values,
+// the node value and the backup towards the root.
+// ---------------------------------------------------------------------------
+constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
+
+struct LeafParentShared {
+  float slip[8 * 9];                    // slip table, when staged in LDS
+  DrawOut draw[8];
+  float leaf[8 * QV_MAX_SAMPLES * 8];   // [a][r][c] child scores
+  float rb[8];                          // R(b,a)
+  float qn[8];                          // Q-node values
+  float red[kBlock / kWave][8];
+  int last;
+};
+
+// Floats of dynamic LDS: the band (or the landmark tables staged after the
+// pass), the stay tables, the chunk partials and the histograms.
+__host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM) {
+  const size_t band = (size_t)(TH + 2) * (W + 2);
+  const size_t lmk = (size_t)5 * L;
+  return (band > lmk ? band : lmk) + (size_t)AM * 256 + (size_t)kBlock * (AM + 1) +
+         (size_t)AM * 16 * (AM + 1);
+}
+
+// SLIP_LDS: read the slip table from LDS (for a model in device memory, whose
+// table would otherwise sit in vector registers).
+template <int AM, bool SLIP_LDS>
+__device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const TreeArgs &tr,
+                                 int p, int band, float *smem, LeafParentShared &sh) {
+  constexpr int NV = AM + 1;
+  constexpr int RECN = AM * 16 * NV + AM;   // band record: HQ, then R(b,a)
+  const int A = m.A, W = m.W, BW = W + 2, S = m.S, L = m.L;
+  const int K = lv.K, n = lv.n;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  if (!lv.pvalid[p]) {
+    // children of an absent parent are absent; the parent takes no part in
+    // any backup
+    if (band == 0)
+      for (int i = tid; i < K; i += kBlock) {
+        const int c = p * K + i;
+        lv.cvalid[c] = 0;
+        lv.cz[c] = -1;
+        lv.ccount[c] = 0;
+        lv.cpz[c] = 0.f;
+      }
+    return;
+  }
+  const int TH = lv.TH, y0 = band * TH, th = min(TH, m.H - y0);
+  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)5 * L;
+  float *X = smem;                                  // band, later landmark tables
+  float *stay = smem + (bandf > lmkf ? bandf : lmkf);   // [A][256]
+  float *part = stay + AM * 256;                    // [kBlock][NV], later backup scratch
+  float *HQ = part + kBlock * NV;                   // [AM][16][NV]
+  const float *b = lv.pbel + (size_t)p * S;
+  for (int i = tid; i < A * 256; i += kBlock) stay[i] = lv.staytab[i];
+  if (SLIP_LDS && tid < A * 9) sh.slip[tid] = m.slip[tid];
+  load_band(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
+  __syncthreads();
+  const float *slip = SLIP_LDS ? sh.slip : m.slip;   // kernel argument: read as scalars
+  const float rho = m.lm_p;
+  const float rW = 1.0f / (float)W;
+  const float *Rt = m.R;
+  float acc[AM][NV], racc[AM];
+#pragma unroll
+  for (int a = 0; a < AM; ++a) {
+    racc[a] = 0.f;
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[a][c] = 0.f;
+  }
+  const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
+  const int j0 = ch[2 * tid], j1 = ch[2 * tid + 1];
+  for (int j = j0; j < j1; j += kLeafParentBatch) {
+    uint32_t e[kLeafParentBatch];
+    float q[kLeafParentBatch][AM], rr[kLeafParentBatch][AM], bg[kLeafParentBatch];
+#pragma unroll
+    for (int k = 0; k < kLeafParentBatch; ++k)
+      e[k] = j + k < j1 ? (uint32_t)lv.sort_cells[j + k] : 0u;
+#pragma unroll
+    for (int k = 0; k < kLeafParentBatch; ++k) {
+      const int t = (int)(e[k] & kSortCell);
+      load_q_row<AM>(lv, A, t, q[k]);
+#pragma unroll
+      for (int a = 0; a < AM; ++a) rr[k][a] = a < A ? Rt[(size_t)t * A + a] : 0.f;
+      bg[k] = (e[k] & kSortGoal) ? b[t] : 0.f;   // the goal keeps its own mass
+    }
+#pragma unroll
+    for (int k = 0; k < kLeafParentBatch; ++k) {
+      if (j + k < j1) {
+        const int t = (int)(e[k] & kSortCell);
+        const int gy = fdiv(t, W, rW);
+        const float *c = X + (gy - y0 + 1) * BW + (t - gy * W) + 1;
+        const float n0 = c[-BW - 1], n1 = c[-BW], n2 = c[-BW + 1], n3 = c[-1], n5 = c[1],
+                    n6 = c[BW - 1], n7 = c[BW], n8 = c[BW + 1];
+        const bool goal = (e[k] & kSortGoal) != 0;
+        const float self = goal ? bg[k] : c[0];
+        const uint32_t o8 = (e[k] >> kSortOutShift) & 0xFFu;
+        const bool lmk = (e[k] & kSortLandmark) != 0;
+        const float lam = lmk ? 1.f - rho : 1.f;
+        uint32_t lid = 0;
+        if (lmk) lid = sig_lm(lv.sig[t]);
+#pragma unroll
+        for (int a = 0; a < AM; ++a) {
+          if (a < A) {
+            // b'_a(x): the slip stencil in gather form (as stencil())
+            const float *sl = slip + a * 9;
+            float v = sl[8] * n0;
+            v = fmaf(sl[7], n1, v);
+            v = fmaf(sl[6], n2, v);
+            v = fmaf(sl[5], n3, v);
+            v = fmaf(sl[3], n5, v);
+            v = fmaf(sl[2], n6, v);
+            v = fmaf(sl[1], n7, v);
+            v = fmaf(sl[0], n8, v);
+            v = fmaf(goal ? 1.f : stay[a * 256 + o8], self, v);
+            // R(b,a) = sum_x R(x,a) b(x)
+            racc[a] = fmaf(self, rr[k][a], racc[a]);
+            if (lmk) st_coherent(lv.lmv + ((size_t)p * A + a) * L + lid - 1, v);
+            v *= lam;
+#pragma unroll
+            for (int cc = 0; cc < AM; ++cc) acc[a][cc] = fmaf(v, q[k][cc], acc[a][cc]);
+            acc[a][AM] += v;
+          }
+        }
+      }
+    }
+  }
+  // per action: chunk partials -> histograms by wall reading (chunk order)
+  const int32_t *pch = ch + 2 * kBlock;
+#pragma unroll
+  for (int a = 0; a < AM; ++a) {
+    if (a < A) {
+#pragma unroll
+      for (int c = 0; c < NV; ++c) part[tid * NV + c] = acc[a][c];
+      __syncthreads();
+      for (int i = tid; i < 16 * NV; i += kBlock) {
+        const int w = i / NV, c = i - w * NV;
+        float sum = 0.f;
+        for (int k = pch[w]; k < pch[w + 1]; ++k) sum += part[k * NV + c];
+        HQ[a * 16 * NV + i] = sum;
+      }
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < AM; ++a) {
+    const float tot = wave_total_lane63(racc[a]);
+    if (lane == kWave - 1) sh.red[wave][a] = tot;
+  }
+  __syncthreads();
+  if (tid < A) sh.rb[tid] = (sh.red[0][tid] + sh.red[1][tid]) + (sh.red[2][tid] + sh.red[3][tid]);
+  __syncthreads();
+  if (lv.tiles > 1) {
+    // band record out; the last band of the parent sums all records in band order
+    float *rec = lv.part + ((size_t)p * lv.tiles + band) * RECN;
+    for (int i = tid; i < RECN; i += kBlock) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
+    wait_mem();
+    __syncthreads();
+    if (tid == 0) sh.last = (count_arrival(&lv.ctr[p]) == lv.tiles - 1);
+    __syncthreads();
+    if (!sh.last) return;
+    const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
+    for (int i = tid; i < RECN; i += kBlock) {
+      float sum = 0.f;
+      int t0 = 0;
+      for (; t0 + 4 <= lv.tiles; t0 += 4) {
+        float x[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = ld_coherent(rec0 + (size_t)(t0 + k) * RECN + i);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) sum += x[k];
+      }
+      for (; t0 < lv.tiles; ++t0) sum += ld_coherent(rec0 + (size_t)t0 * RECN + i);
+      if (i < AM * 16 * NV)
+        HQ[i] = sum;
+      else
+        sh.rb[i - AM * 16 * NV] = sum;
+    }
+    if (tid == 0) lv.ctr[p] = 0;
+    __syncthreads();
+  }
+  // observation draws: wavefront w takes actions w, w + 4, ...
+  uint32_t *lw = (uint32_t *)X;
+  for (int l = tid; l < L; l += kBlock) lw[l] = lv.lm_wall[l];
+  wait_mem();
+  __syncthreads();
+  float *lvv = X + L + wave * L;
+  for (int a = wave; a < A; a += kBlock / kWave) {
+    for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    float hs = 0.f;
+    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
+    if (lane == 16) {
+      hs = sh.rb[a];
+      lv.reward[p * A + a] = hs;
+    }
+    sample_draws(m, lv, p, a, hs, lw, lvv, &sh.draw[a]);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // leaf values (Alg. 5) of every drawn child of every action:
+  //   zl = 0: (1/P(z)) sum_w O_w(zw|w) HQ_a[w][c];  zl = l: (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) Q(x_l,c)
+  for (int i = tid; i < A * n * AM; i += kBlock) {
+    const int a = i / (n * AM), r = (i / AM) - a * n, c = i - (i / AM) * AM;
+    float v = 0.f;
+    if (c < A && r < sh.draw[a].U) {
+      const int z = sh.draw[a].z[r];
+      const uint32_t zw = (uint32_t)(z & 15);
+      const int zl = z >> 4;
+      if (zl == 0) {
+#pragma unroll
+        for (int w = 0; w < 16; ++w)
+          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
+      } else {
+        const int cell = m.lm_cell[zl - 1];
+        v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
+            ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * lv.Q[(size_t)cell * A + c];
+      }
+      v *= sh.draw[a].inv[r];
+    }
+    sh.leaf[i] = v;
+  }
+  __syncthreads();
+  // Q-node values (Alg. 6), the node value, then the backup towards the root
+  const long long g = tr.first[lv.d] + p;
+  if (tid < A) {
+    const int a = tid;
+    float qv = sh.rb[a];
+    const long long lf = tr.first[lv.d + 1] + (long long)p * K + (long long)a * n;
+    for (int r = 0; r < sh.draw[a].U; ++r) {
+      float best = -INFINITY;
+      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(a * n + r) * AM + c]);
+      tr.value[lf + r] = best;
+      qv += tr.gamma * ((float)sh.draw[a].count[r] / (float)n) * best;
+    }
+    tr.qvalue[g * A + a] = qv;
+    sh.qn[a] = qv;
+  }
+  __syncthreads();
+  if (tid == 0) finish_node(tr, lv.d, g, sh.qn);
+  __syncthreads();
+  climb_wg(tr, lv.d, p, part, &sh.last);
+}
+
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_leaf_parent(DevModel m, LevelArgs lv, TreeArgs tr) {
+  extern __shared__ float smem[];
+  __shared__ LeafParentShared sh;
+  const int p = blockIdx.x / lv.tiles, band = blockIdx.x - p * lv.tiles;
+  leaf_parent_item<AM, false>(m, lv, tr, p, band, smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1190,6 +1666,7 @@ static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
   const size_t S = (size_t)W * H;
   size_t x = (size_t)(H + 2) * (W + 2);
   x = std::max<size_t>(x, (size_t)16 * kBlock);
+  x = std::max<size_t>(x, (size_t)(16 + 1) * kBlock);   // leaf chunk partials, A <= 16
   x = std::max<size_t>(x, (size_t)A * n + A);
   x = std::max<size_t>(x, (size_t)2 * L);
   return (((S + 3) & ~(size_t)3) + x) * sizeof(float);
@@ -1246,6 +1723,27 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
   const int q_vec = (A == 4 || A == 8) && ((uintptr_t)Q % 16 == 0);
   const size_t lds_small = small_lds_bytes(m.W, m.H, A, n, m.L);
   const bool small = !(flags & QV_PLAN_TILED) && lds_small <= kSmallLdsMax;
+  int32_t *sort_cells = (int32_t *)(ws + L.sort_cells);
+  int32_t *sort_chunk = (int32_t *)(ws + L.sort_chunk);
+  // the last level: one workgroup per (parent, band) over all actions (A <= 8),
+  // else one per Q-node (k_node) or per (band, action) (k_stats + k_leaf)
+  const bool leaf_parent = !store_leaves && D > 0 && A <= 8;
+  const int AM = A <= 4 ? 4 : 8;
+  const size_t lds_lp =
+      leaf_parent_lds_floats(m.W, L.leaf_rows, m.L, AM) * sizeof(float);
+  if ((leaf_parent && (long long)L.leaf_rows * m.W > kSortMaxCells) ||
+      (!leaf_parent && small && !store_leaves && D > 0 && m.S > kSortMaxCells))
+    return hipErrorInvalidValue;   // cannot happen: leaf bands hold <= 8192 cells
+  if (leaf_parent) {
+    QV_LAUNCH(k_prep_sort, dim3(L.leaf_tiles), dim3(kBlock), 0, st, m.S, L.leaf_rows * m.W, m.L,
+              sig, sort_cells, sort_chunk);
+    const void *kf = AM == 4 ? (const void *)k_leaf_parent<4> : (const void *)k_leaf_parent<8>;
+    hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_lp);
+    if (e != hipSuccess) return e;
+  } else if (small && !store_leaves && D > 0) {
+    QV_LAUNCH(k_prep_sort, dim3(1), dim3(kBlock), 0, st, m.S, m.S, m.L, sig, sort_cells,
+              sort_chunk);
+  }
   for (int d = 0; d < D; ++d) {
     LevelArgs lv;
     lv.d = d;
@@ -1275,6 +1773,19 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.lm_wall = lm_wall;
     lv.ctr = ctr;
     lv.q_vec = q_vec;
+    lv.sort_cells = sort_cells;
+    lv.sort_chunk = sort_chunk;
+    if (last && leaf_parent) {
+      lv.TH = L.leaf_rows;
+      lv.tiles = L.leaf_tiles;
+      lv.part = (float *)(ws + L.leafrec);
+      const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
+      if (AM == 4)
+        QV_LAUNCH_L(d, k_leaf_parent<4>, dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+      else
+        QV_LAUNCH_L(d, k_leaf_parent<8>, dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+      continue;
+    }
     if (small) {
       const unsigned nq = (unsigned)((long long)lv.nslots * A);
       if (!last || store_leaves) {
@@ -1332,14 +1843,29 @@ __device__ __forceinline__ int find_query(const int32_t *base, int nq, int i) {
   return lo;
 }
 
+// A copy of a descriptor read from device memory, declared uniform word by
+// word so that it lives in scalar registers (the compiler cannot prove the
+// memory unchanged under the kernel's own stores, so it would load it per lane).
+template <typename T>
+__device__ __forceinline__ T uniform_copy(const T &src) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized descriptor");
+  T out;
+  const int *in = reinterpret_cast<const int *>(&src);
+  int *o = reinterpret_cast<int *>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) o[i] = __builtin_amdgcn_readfirstlane(in[i]);
+  return out;
+}
+
 __device__ __forceinline__ LevelArgs bind_level(const BatchQuery &bq, const BatchCall &c, int d) {
-  LevelArgs lv = bq.lv[d];
-  if (d == 0) lv.pbel = c.b0;
-  lv.Q = c.Q;
-  lv.q_vec = c.q_vec;
-  lv.key0 = c.key0;
-  lv.key1 = c.key1;
-  lv.qid = c.qid;
+  LevelArgs lv = uniform_copy(bq.lv[d]);
+  const BatchCall cu = uniform_copy(c);
+  lv.Q = cu.Q;
+  lv.q_vec = cu.q_vec;
+  lv.key0 = cu.key0;
+  lv.key1 = cu.key1;
+  lv.qid = cu.qid;
+  if (d == 0) lv.pbel = cu.b0;
   return lv;
 }
 
@@ -1352,6 +1878,17 @@ __global__ void k_prep_batch(BatchPrep bp) {
   if (blockIdx.x == 0 && threadIdx.x < bp.nqueue) bp.queue[threadIdx.x] = 0;
 }
 
+// leaf-band sort of the queries whose last level runs k_leaf_parent items
+__global__ __launch_bounds__(kBlock) void k_prep_sort_batch(BatchPrep bp) {
+  const int q = find_query(bp.sort_base, bp.nq, blockIdx.x);
+  const BatchQuery &bq = bp.q[q];
+  const LevelArgs &lv = bq.lv[bq.D - 1];
+  const int band = blockIdx.x - bp.sort_base[q];
+  const int TC = lv.TH * bq.m.W, c_lo = band * TC;
+  sort_band(c_lo, min(bq.m.S, c_lo + TC), bq.m.L, bq.sig, (int32_t *)lv.sort_cells,
+            (int32_t *)lv.sort_chunk + (size_t)band * kSortChunkInts);
+}
+
 __global__ void k_prep_landmarks_batch(BatchPrep bp) {
   const int q = find_query(bp.lm_base, bp.nq, blockIdx.x);
   const BatchQuery &bq = bp.q[q];
@@ -1359,14 +1896,17 @@ __global__ void k_prep_landmarks_batch(BatchPrep bp) {
   prep_landmark_one(bq.m, bq.sig, bq.err, bq.px.lm_wall, l);
 }
 
-// PHASE 0: statistics and draws of every Q-node of level d (k_stats);
-// PHASE 1: child beliefs (k_update) or, at a query's last level, leaf scoring
-// and backup (k_leaf).  Workgroups take `chunk` items at a time from the
+// PHASE 0: statistics and draws of the Q-nodes of level d (k_stats);
+// PHASE 1: child beliefs (k_update) or, at the last level of a query with
+// 9 actions, leaf scoring and backup (k_leaf);
+// PHASE 2: the last level of a query with at most 8 actions, per (parent,
+// band) over all actions (k_leaf_parent).  Workgroups take `chunk` items at a time from the
 // queue until it runs dry; every workgroup leaves after one failed take.
 template <int PHASE, int APAD>
 __global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
+  __shared__ LeafParentShared shl;   // phase 2 only
   __shared__ int s_item;
   for (;;) {
     __syncthreads();
@@ -1380,12 +1920,18 @@ __global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
       const BatchQuery &bq = bl.q[q];
       const LevelArgs lv = bind_level(bq, bl.call[q], bl.d);
       const Item it = decode_item(i - bl.base[q], lv.tiles, bq.m.A);
-      if (PHASE == 0)
+      if constexpr (PHASE == 0) {
         stats_item(bq.m, lv, it, smem, sh);
-      else if (bl.d + 1 < bq.D)
-        update_item(bq.m, lv, it, smem, sh);
-      else
-        leaf_item<APAD>(bq.m, lv, bq.tr, it, smem, sh);
+      } else if constexpr (PHASE == 1) {
+        if (bl.d + 1 < bq.D)
+          update_item(bq.m, lv, it, smem, sh);
+        else
+          leaf_item<APAD>(bq.m, lv, bq.tr, it, smem, sh);
+      } else {
+        const int local = i - bl.base[q];
+        leaf_parent_item<APAD, true>(bq.m, lv, bq.tr, local / lv.tiles, local % lv.tiles, smem,
+                                     shl);
+      }
       __syncthreads();
     }
   }
@@ -1407,12 +1953,18 @@ __global__ void k_batch_out(int nq, const int32_t *act_in, const float *rq_in, i
     }                                                                       \
   } while (0)
 
-hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks, hipStream_t st,
-                             bool timed) {
+hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks,
+                             int sort_blocks, hipStream_t st, bool timed) {
   QV_LAUNCH_T(timed, 0, k_prep_batch, dim3(cell_blocks), dim3(256), 0, st, bp);
   if (lm_blocks > 0)
     QV_LAUNCH_T(timed, 0, k_prep_landmarks_batch, dim3(lm_blocks), dim3(256), 0, st, bp);
+  if (sort_blocks > 0)
+    QV_LAUNCH_T(timed, 0, k_prep_sort_batch, dim3(sort_blocks), dim3(kBlock), 0, st, bp);
   return hipGetLastError();
+}
+
+size_t leaf_parent_lds_bytes(int W, int TH, int L, int AM) {
+  return leaf_parent_lds_floats(W, TH, L, AM) * sizeof(float);
 }
 
 template <int PHASE, int APAD>
@@ -1422,6 +1974,7 @@ static const void *level_kernel() {
 
 static const void *batch_kernel_ptr(int phase, int apad) {
   if (phase == 0) return level_kernel<0, 4>();
+  if (phase == 2) return apad <= 4 ? level_kernel<2, 4>() : level_kernel<2, 8>();
   if (apad <= 4) return level_kernel<1, 4>();
   if (apad <= 8) return level_kernel<1, 8>();
   return level_kernel<1, 16>();
@@ -1442,6 +1995,10 @@ hipError_t launch_batch_level(const BatchLevel &bl, int phase, int apad, size_t 
   const int d = bl.d;
   if (phase == 0) {
     QV_LAUNCH_T(timed, d, (k_level_batch<0, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
+  } else if (phase == 2 && apad <= 4) {
+    QV_LAUNCH_T(timed, d, (k_level_batch<2, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
+  } else if (phase == 2) {
+    QV_LAUNCH_T(timed, d, (k_level_batch<2, 8>), dim3(grid), dim3(kBlock), lds, st, bl);
   } else if (apad <= 4) {
     QV_LAUNCH_T(timed, d, (k_level_batch<1, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
   } else if (apad <= 8) {

@@ -59,12 +59,15 @@ def level_grids(workload: str):
     A, K, D = prob.A, prob.A * prob.n, prob.D
     th = max(1, min(prob.H, 1024 // prob.W))
     tiles = (prob.H + th - 1) // th
+    leaf_rows = max(1, min(prob.H, 8192 // prob.W))
+    leaf_tiles = (prob.H + leaf_rows - 1) // leaf_rows
     out = {}
     for d in range(D):
         slots = K ** d
         out[("k_node", slots * A * BLOCK)] = d
         for fam in ("k_stats", "k_update", "k_leaf"):
             out[(fam, slots * tiles * A * BLOCK)] = d
+    out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * BLOCK)] = D - 1
     return out
 
 

@@ -120,8 +120,10 @@ def test_plan_store_leaves_matches_fused_scoring():
     assert a1 == a2
     for k in ("valid", "z", "count"):
         assert np.array_equal(t1[k], t2[k])
-    np.testing.assert_allclose(t1["value"][t1["valid"] == 1], t2["value"][t2["valid"] == 1],
-                               rtol=1e-6, atol=1e-5)
+    # the fused path scores leaves from wall-reading histograms, the stored
+    # path cell by cell: the same sums in another order
+    v1, v2 = t1["value"][t1["valid"] == 1], t2["value"][t2["valid"] == 1]
+    assert np.all(np.abs(v1 - v2) <= parity.REL * np.maximum(1.0, np.abs(v2)))
     # the stored leaves match the oracle's leaf beliefs
     res = oracle.plan(prob, Q32, dump_beliefs=True)
     parity.compare_tree(prob, t2, res["dump"])
