@@ -275,16 +275,17 @@ hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_
 // start belief) they are zeroed here as well.  Loads are issued in batches
 // so that each thread has several in flight.
 constexpr int kBandBatch = 8;
+template <int BATCH = kBandBatch>
 __device__ __forceinline__ void load_band(const DevModel &m, const uint32_t *sig,
                                           const float *b, int y0, int th, float *band,
                                           int BW, bool mask) {
   const int n = (th + 2) * BW;
   const float rBW = 1.0f / (float)BW;
-  for (int i0 = threadIdx.x; i0 < n; i0 += kBandBatch * kBlock) {
-    int cell[kBandBatch];
-    float v[kBandBatch];
+  for (int i0 = threadIdx.x; i0 < n; i0 += BATCH * kBlock) {
+    int cell[BATCH];
+    float v[BATCH];
 #pragma unroll
-    for (int j = 0; j < kBandBatch; ++j) {
+    for (int j = 0; j < BATCH; ++j) {
       const int i = i0 + j * kBlock;
       const int r = fdiv(i, BW, rBW);
       const int gy = y0 - 1 + r, gx = i - r * BW - 1;
@@ -294,11 +295,11 @@ __device__ __forceinline__ void load_band(const DevModel &m, const uint32_t *sig
     }
     if (mask) {
 #pragma unroll
-      for (int j = 0; j < kBandBatch; ++j)
+      for (int j = 0; j < BATCH; ++j)
         if (cell[j] >= 0 && !(sig[cell[j]] & kSigFree)) v[j] = 0.f;
     }
 #pragma unroll
-    for (int j = 0; j < kBandBatch; ++j) {
+    for (int j = 0; j < BATCH; ++j) {
       const int i = i0 + j * kBlock;
       if (i < n) band[i] = v[j];
     }
@@ -402,17 +403,16 @@ __device__ __forceinline__ float block_sum32(float (&v)[32], float *red) {
 // observation draws of one Q-node, by one wavefront
 // ---------------------------------------------------------------------------
 struct ObsSource {
-  float p0;                 // lane zw < 16: P(zw, no landmark)
+  const float *p0;          // LDS [16]: P(zw, no landmark)
   const uint32_t *lw;       // LDS [L]: wall reading of landmark l+1
   const float *lv;          // LDS [L]: predicted mass on landmark l+1
   int L;
 };
 
-// P(z|b,a) for z = zw + 16 zl.  Called by every lane of the wavefront (it
-// reads lane zw's no-landmark value with a shuffle).
+// P(z|b,a) for z = zw + 16 zl.
 __device__ __forceinline__ float obs_prob(const DevModel &m, const ObsSource &src, int z) {
   const int zw = z & 15, zl = z >> 4;
-  const float from_p0 = __shfl(src.p0, zw, kWave);
+  const float from_p0 = src.p0[zw];
   if (zl == 0) return from_p0;
   if (zl > src.L) return 0.f;
   const uint32_t w = src.lw[zl - 1];
@@ -435,21 +435,26 @@ struct DrawOut {
 // Philox uniforms, and writes one child record per distinct z (ascending)
 // with its frequency (Alg. 3/4).  One full wavefront; out (LDS) optional.
 __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
-                             const uint32_t *lw, const float *lvv, DrawOut *out) {
+                             const uint32_t *lw, const float *lvv, float *p0tab, DrawOut *out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = lv.n;
   const int cb = p * lv.K + a * n;
-  // P(zw, no landmark) = sum_w O_w(zw|w) H[w]; landmark cells entered H with
-  // their "no landmark" factor already
+  // P(zw, no landmark) = sum_w O_w(zw|w) H[w] (landmark cells entered H with
+  // their "no landmark" factor already), published in the LDS table p0tab
+  float p0 = 0.f;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) {
+    const float hw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hs), w));
+    p0 = fmaf(wall_lik(m.flip, (uint32_t)(lane & 15), (uint32_t)w), hw, p0);
+  }
+  if (lane < 16) p0tab[lane] = p0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
   ObsSource src;
-  src.p0 = 0.f;
+  src.p0 = p0tab;
   src.lw = lw;
   src.lv = lvv;
   src.L = m.L;
-  for (int w = 0; w < 16; ++w) {
-    const float hw = __shfl(hs, w, kWave);
-    src.p0 = fmaf(wall_lik(m.flip, (uint32_t)(lane & 15), (uint32_t)w), hw, src.p0);
-  }
   // running totals over z in ascending order: lane j owns z in [j*CH, (j+1)*CH)
   const int Z = 16 * (m.L + 1);
   const int CH = (Z + kWave - 1) / kWave;
@@ -462,8 +467,9 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
   // exclusive prefix of the lane totals, summed in lane order, so the running
   // totals are non-decreasing across lanes and the last one is the total P
   float exc = 0.f, P = 0.f;
+#pragma unroll 4
   for (int i = 0; i < kWave; ++i) {
-    const float s = __shfl(loc, i, kWave);
+    const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(loc), i));
     if (i == lane) exc = P;
     P += s;
   }
@@ -590,7 +596,7 @@ __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int 
   }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  sample_draws(m, lv, p, a, hs, lw, lvv, nullptr);
+  sample_draws(m, lv, p, a, hs, lw, lvv, lds + 2 * m.L, nullptr);
 }
 
 // Workgroups go to the 8 XCDs in turn (workgroup id mod 8), each XCD with
@@ -1060,7 +1066,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   float *band = X;
   const float *b = lv.pbel + (size_t)p * S;
   s_stay[tid] = lv.staytab[a * 256 + tid];
-  load_band(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
+  load_band<24>(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
   __syncthreads();
   const float rW = 1.0f / (float)W;
   const float *sl = &m.slip[a * 9];
@@ -1192,7 +1198,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     }
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
-    sample_draws(m, lv, p, a, tid < 17 ? s_H[tid] : 0.f, lw, lvv, &s_draw);
+    sample_draws(m, lv, p, a, tid < 17 ? s_H[tid] : 0.f, lw, lvv, X + 2 * m.L, &s_draw);
   }
   __syncthreads();
   const int U = s_draw.U;
@@ -1296,7 +1302,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
 // actions in parallel, and the workgroup forms the leaf and Q-node values,
 // the node value and the backup towards the root.
 // ---------------------------------------------------------------------------
-constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
+constexpr int kLeafParentBatch = 4;   // sorted cells whose loads go out together
 
 struct LeafParentShared {
   float slip[8 * 9];                    // slip table, when staged in LDS
@@ -1308,13 +1314,15 @@ struct LeafParentShared {
   int last;
 };
 
-// Floats of dynamic LDS: the band (or the landmark tables staged after the
-// pass), the stay tables, the chunk partials and the histograms.
+// Floats of dynamic LDS: one region that holds in turn the band, the chunk
+// partials and the landmark tables; then the stay tables and the histograms.
 __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM) {
   const size_t band = (size_t)(TH + 2) * (W + 2);
-  const size_t lmk = (size_t)5 * L;
-  return (band > lmk ? band : lmk) + (size_t)AM * 256 + (size_t)kBlock * (AM + 1) +
-         (size_t)AM * 16 * (AM + 1);
+  const size_t lmk = (size_t)5 * L + 16 * (kBlock / kWave);   // landmark tables, P(zw) tables
+  const size_t part = (size_t)kBlock * 2 * (AM + 1);         // chunk partials, two actions
+  size_t x = band > lmk ? band : lmk;
+  x = x > part ? x : part;
+  return x + (size_t)AM * 256 + (size_t)AM * 16 * (AM + 1);
 }
 
 // SLIP_LDS: read the slip table from LDS (for a model in device memory, whose
@@ -1341,42 +1349,86 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     return;
   }
   const int TH = lv.TH, y0 = band * TH, th = min(TH, m.H - y0);
-  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)5 * L;
-  float *X = smem;                                  // band, later landmark tables
-  float *stay = smem + (bandf > lmkf ? bandf : lmkf);   // [A][256]
-  float *part = stay + AM * 256;                    // [kBlock][NV], later backup scratch
-  float *HQ = part + kBlock * NV;                   // [AM][16][NV]
+  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)5 * L + 16 * (kBlock / kWave);
+  const size_t partf = (size_t)kBlock * 2 * NV;
+  const size_t xf = bandf > lmkf ? (bandf > partf ? bandf : partf) : (lmkf > partf ? lmkf : partf);
+  float *X = smem;             // band, then the chunk partials, then the landmark tables
+  float *part = X;             // [kBlock][2 NV], later the backup scratch
+  float *stay = smem + xf;     // [A][256]
+  float *HQ = stay + AM * 256;   // [AM][16][NV]
   const float *b = lv.pbel + (size_t)p * S;
   for (int i = tid; i < A * 256; i += kBlock) stay[i] = lv.staytab[i];
   if (SLIP_LDS && tid < A * 9) sh.slip[tid] = m.slip[tid];
-  load_band(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
+  load_band<24>(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
   __syncthreads();
   const float *slip = SLIP_LDS ? sh.slip : m.slip;   // kernel argument: read as scalars
   const float rho = m.lm_p;
   const float rW = 1.0f / (float)W;
-  const float *Rt = m.R;
-  float acc[AM][NV], racc[AM];
+  // R(b,a) = sum_x R(x,a) b(x) over the band's own rows, in cell order
+  // (coalesced rows of R; the goal's own mass is read from b)
+  float racc[AM];
 #pragma unroll
-  for (int a = 0; a < AM; ++a) {
-    racc[a] = 0.f;
+  for (int a = 0; a < AM; ++a) racc[a] = 0.f;
+  {
+    const float *Rt = m.R;
+    const bool r_vec = (A == AM) && ((reinterpret_cast<uintptr_t>(Rt) & 15u) == 0);
+    const int ncell = th * W, t00 = y0 * W;
+    for (int i0 = tid; i0 < ncell; i0 += 4 * kBlock) {
+      float r4[4][AM], bb[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = i0 + k * kBlock;
+        const int t = t00 + (i < ncell ? i : 0);
+        if (r_vec) {
+          const float4 *row = reinterpret_cast<const float4 *>(Rt + (size_t)t * AM);
+#pragma unroll
+          for (int c4 = 0; c4 < AM / 4; ++c4) {
+            const float4 v4 = row[c4];
+            r4[k][4 * c4] = v4.x;
+            r4[k][4 * c4 + 1] = v4.y;
+            r4[k][4 * c4 + 2] = v4.z;
+            r4[k][4 * c4 + 3] = v4.w;
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a < AM; ++a) r4[k][a] = a < A ? Rt[(size_t)t * A + a] : 0.f;
+        }
+        const int ly = fdiv(i, W, rW);
+        bb[k] = (i < ncell) ? ((t == m.goal) ? b[t] : X[(ly + 1) * BW + (i - ly * W) + 1]) : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int a = 0; a < AM; ++a) racc[a] = fmaf(bb[k], r4[k][a], racc[a]);
+    }
+  }
+  float acc[AM][NV];
+#pragma unroll
+  for (int a = 0; a < AM; ++a)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[a][c] = 0.f;
-  }
   const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
   const int j0 = ch[2 * tid], j1 = ch[2 * tid + 1];
+  // the chunk in batches: the next batch's entries load while this batch's
+  // Q rows are in flight
+  uint32_t en[kLeafParentBatch];
+#pragma unroll
+  for (int k = 0; k < kLeafParentBatch; ++k)
+    en[k] = j0 + k < j1 ? (uint32_t)lv.sort_cells[j0 + k] : 0u;
   for (int j = j0; j < j1; j += kLeafParentBatch) {
     uint32_t e[kLeafParentBatch];
-    float q[kLeafParentBatch][AM], rr[kLeafParentBatch][AM], bg[kLeafParentBatch];
-#pragma unroll
-    for (int k = 0; k < kLeafParentBatch; ++k)
-      e[k] = j + k < j1 ? (uint32_t)lv.sort_cells[j + k] : 0u;
+    float q[kLeafParentBatch][AM], bg[kLeafParentBatch];
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
+      e[k] = en[k];
       const int t = (int)(e[k] & kSortCell);
       load_q_row<AM>(lv, A, t, q[k]);
-#pragma unroll
-      for (int a = 0; a < AM; ++a) rr[k][a] = a < A ? Rt[(size_t)t * A + a] : 0.f;
       bg[k] = (e[k] & kSortGoal) ? b[t] : 0.f;   // the goal keeps its own mass
+    }
+#pragma unroll
+    for (int k = 0; k < kLeafParentBatch; ++k) {
+      const int jn = j + kLeafParentBatch + k;
+      en[k] = jn < j1 ? (uint32_t)lv.sort_cells[jn] : 0u;
     }
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
@@ -1407,8 +1459,6 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
             v = fmaf(sl[1], n7, v);
             v = fmaf(sl[0], n8, v);
             v = fmaf(goal ? 1.f : stay[a * 256 + o8], self, v);
-            // R(b,a) = sum_x R(x,a) b(x)
-            racc[a] = fmaf(self, rr[k][a], racc[a]);
             if (lmk) st_coherent(lv.lmv + ((size_t)p * A + a) * L + lid - 1, v);
             v *= lam;
 #pragma unroll
@@ -1419,19 +1469,43 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
       }
     }
   }
-  // per action: chunk partials -> histograms by wall reading (chunk order)
+  // chunk partials -> histograms by wall reading.  The chunks of reading w
+  // are [pch[w], pch[w+1]); their partials are added by a fixed binary tree
+  // over the position within that range (8 steps), two actions per round.
   const int32_t *pch = ch + 2 * kBlock;
+  int my_lo = 0, my_n = 0;
+  {
+    int w = 0;
+    while (w < 16 && pch[w + 1] <= tid) ++w;
+    if (w < 16) {
+      my_lo = pch[w];
+      my_n = pch[w + 1] - pch[w];
+    }
+  }
+  constexpr int G = 2, GW = G * NV;   // actions per round, floats per thread
+  __syncthreads();                    // the band is read no more: part takes its place
 #pragma unroll
-  for (int a = 0; a < AM; ++a) {
-    if (a < A) {
+  for (int a0 = 0; a0 < AM; a0 += G) {
+    if (a0 < A) {
 #pragma unroll
-      for (int c = 0; c < NV; ++c) part[tid * NV + c] = acc[a][c];
+      for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int c = 0; c < NV; ++c) part[tid * GW + g * NV + c] = acc[a0 + g][c];
       __syncthreads();
-      for (int i = tid; i < 16 * NV; i += kBlock) {
-        const int w = i / NV, c = i - w * NV;
-        float sum = 0.f;
-        for (int k = pch[w]; k < pch[w + 1]; ++k) sum += part[k * NV + c];
-        HQ[a * 16 * NV + i] = sum;
+      const int r = tid - my_lo;
+#pragma unroll
+      for (int st = 1; st < kBlock; st <<= 1) {
+        if (my_n > 0 && (r & (2 * st - 1)) == 0 && r + st < my_n) {
+#pragma unroll
+          for (int i = 0; i < GW; ++i) part[tid * GW + i] += part[(tid + st) * GW + i];
+        }
+        __syncthreads();
+      }
+      for (int i = tid; i < 16 * GW; i += kBlock) {
+        const int w = i / GW, gi = i - w * GW;
+        const int g = gi / NV, c = gi - g * NV;
+        if (a0 + g < AM)
+          HQ[((a0 + g) * 16 + w) * NV + c] = pch[w + 1] > pch[w] ? part[pch[w] * GW + gi] : 0.f;
       }
       __syncthreads();
     }
@@ -1489,7 +1563,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
       hs = sh.rb[a];
       lv.reward[p * A + a] = hs;
     }
-    sample_draws(m, lv, p, a, hs, lw, lvv, &sh.draw[a]);
+    sample_draws(m, lv, p, a, hs, lw, lvv, X + 5 * L + 16 * wave, &sh.draw[a]);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
@@ -1668,7 +1742,7 @@ static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
   x = std::max<size_t>(x, (size_t)16 * kBlock);
   x = std::max<size_t>(x, (size_t)(16 + 1) * kBlock);   // leaf chunk partials, A <= 16
   x = std::max<size_t>(x, (size_t)A * n + A);
-  x = std::max<size_t>(x, (size_t)2 * L);
+  x = std::max<size_t>(x, (size_t)2 * L + 16);
   return (((S + 3) & ~(size_t)3) + x) * sizeof(float);
 }
 
