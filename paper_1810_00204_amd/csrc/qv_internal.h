@@ -56,6 +56,7 @@ struct LevelArgs {
   int q_vec;              // Q rows can be read as float4 (A = 4 or 8, aligned)
   // free cells in true-wall-reading order and their chunks (see k_prep_sort)
   const int32_t *sort_cells, *sort_chunk;
+  int sort_bands, sort_tc;   // bands sorted by extra workgroups of this launch (0: none)
 };
 
 // Whole-tree view for the expectimax backup (Alg. 6/7).

@@ -407,17 +407,18 @@ struct ObsSource {
   const uint32_t *lw;       // LDS [L]: wall reading of landmark l+1
   const float *lv;          // LDS [L]: predicted mass on landmark l+1
   int L;
+  float fl[4], lmp;         // flip probabilities and landmark rate, in registers
 };
 
 // P(z|b,a) for z = zw + 16 zl.
-__device__ __forceinline__ float obs_prob(const DevModel &m, const ObsSource &src, int z) {
+__device__ __forceinline__ float obs_prob(const ObsSource &src, int z) {
   const int zw = z & 15, zl = z >> 4;
   const float from_p0 = src.p0[zw];
   if (zl == 0) return from_p0;
   if (zl > src.L) return 0.f;
   const uint32_t w = src.lw[zl - 1];
   if (w > 15u) return 0.f;
-  return wall_lik(m.flip, (uint32_t)zw, w) * m.lm_p * src.lv[zl - 1];
+  return wall_lik(src.fl, (uint32_t)zw, w) * src.lmp * src.lv[zl - 1];
 }
 
 // Copy of the drawn children kept in LDS for the rest of a workgroup.
@@ -439,29 +440,35 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
   const int lane = threadIdx.x & (kWave - 1);
   const int n = lv.n;
   const int cb = p * lv.K + a * n;
+  // the model's sensor scalars, once, as uniform registers (the model may sit
+  // in device memory)
+  ObsSource src;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+    src.fl[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.flip[j])));
+  src.lmp = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.lm_p)));
+  src.L = __builtin_amdgcn_readfirstlane(m.L);
+  src.p0 = p0tab;
+  src.lw = lw;
+  src.lv = lvv;
   // P(zw, no landmark) = sum_w O_w(zw|w) H[w] (landmark cells entered H with
   // their "no landmark" factor already), published in the LDS table p0tab
   float p0 = 0.f;
 #pragma unroll
   for (int w = 0; w < 16; ++w) {
     const float hw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hs), w));
-    p0 = fmaf(wall_lik(m.flip, (uint32_t)(lane & 15), (uint32_t)w), hw, p0);
+    p0 = fmaf(wall_lik(src.fl, (uint32_t)(lane & 15), (uint32_t)w), hw, p0);
   }
   if (lane < 16) p0tab[lane] = p0;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  ObsSource src;
-  src.p0 = p0tab;
-  src.lw = lw;
-  src.lv = lvv;
-  src.L = m.L;
   // running totals over z in ascending order: lane j owns z in [j*CH, (j+1)*CH)
-  const int Z = 16 * (m.L + 1);
+  const int Z = 16 * (src.L + 1);
   const int CH = (Z + kWave - 1) / kWave;
   float loc = 0.f;
   for (int j = 0; j < CH; ++j) {
     const int z = lane * CH + j;
-    const float v = obs_prob(m, src, min(z, Z - 1));
+    const float v = obs_prob(src, min(z, Z - 1));
     loc += (z < Z) ? v : 0.f;
   }
   // exclusive prefix of the lane totals, summed in lane order, so the running
@@ -497,7 +504,7 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
   float run = 0.f;
   for (int j = 0; j < CH; ++j) {
     const int z = lane * CH + j;
-    float v = obs_prob(m, src, min(z, Z - 1));
+    float v = obs_prob(src, min(z, Z - 1));
     if (z >= Z) v = 0.f;
     run += v;
     const float F = exc + run;
@@ -520,7 +527,7 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
       int zz = wave_min(cand[k]);
       if (zz == kNone) zz = lastz;
       zk[k] = zz;
-      pk[k] = zz >= 0 ? obs_prob(m, src, zz) : 0.f;
+      pk[k] = zz >= 0 ? obs_prob(src, zz) : 0.f;
     }
   }
   if (lane == 0) {
@@ -1036,7 +1043,10 @@ __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeA
 // forms the Q-node value (LEAF = true; the last Q-node of a node completes
 // the node and climbs towards the root).
 // ---------------------------------------------------------------------------
-template <int APAD, bool LEAF>
+// SORT: the launch carries lv.sort_bands extra workgroups, placed after the
+// Q-node workgroups, that sort the leaf bands (as k_prep_sort) while the
+// first level runs.
+template <int APAD, bool LEAF, bool SORT = false>
 __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ float s_stay[256];
@@ -1048,7 +1058,17 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   __shared__ float s_HQ[LEAF ? 16 * (APAD + 1) : 1];
   __shared__ int s_last;
   const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2;
-  const int bid = xcd_local_id(blockIdx.x, gridDim.x);
+  int nodes = gridDim.x;
+  if constexpr (SORT) {
+    nodes -= lv.sort_bands;
+    if ((int)blockIdx.x >= nodes) {
+      const int band = blockIdx.x - nodes, c_lo = band * lv.sort_tc;
+      sort_band(c_lo, min(S, c_lo + lv.sort_tc), m.L, lv.sig, (int32_t *)lv.sort_cells,
+                (int32_t *)lv.sort_chunk + (size_t)band * kSortChunkInts);
+      return;
+    }
+  }
+  const int bid = xcd_local_id(blockIdx.x, nodes);
   const int p = bid / A, a = bid - p * A;
   const int cb = p * lv.K + a * lv.n;
   const int tid = threadIdx.x;
@@ -1808,9 +1828,19 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
   if ((leaf_parent && (long long)L.leaf_rows * m.W > kSortMaxCells) ||
       (!leaf_parent && small && !store_leaves && D > 0 && m.S > kSortMaxCells))
     return hipErrorInvalidValue;   // cannot happen: leaf bands hold <= 8192 cells
-  if (leaf_parent) {
+  // on the fused path with D >= 2 the level-0 launch sorts the leaf bands
+  const bool sort_in_l0 = leaf_parent && small && D >= 2;
+  if (sort_in_l0) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_node<8, false, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds_small);
+    if (e != hipSuccess) return e;
+  }
+  if (leaf_parent && !sort_in_l0) {
     QV_LAUNCH(k_prep_sort, dim3(L.leaf_tiles), dim3(kBlock), 0, st, m.S, L.leaf_rows * m.W, m.L,
               sig, sort_cells, sort_chunk);
+  }
+  if (leaf_parent) {
     const void *kf = AM == 4 ? (const void *)k_leaf_parent<4> : (const void *)k_leaf_parent<8>;
     hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_lp);
     if (e != hipSuccess) return e;
@@ -1849,6 +1879,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.q_vec = q_vec;
     lv.sort_cells = sort_cells;
     lv.sort_chunk = sort_chunk;
+    lv.sort_bands = 0;
+    lv.sort_tc = 0;
     if (last && leaf_parent) {
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
@@ -1862,7 +1894,12 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     }
     if (small) {
       const unsigned nq = (unsigned)((long long)lv.nslots * A);
-      if (!last || store_leaves) {
+      if (d == 0 && sort_in_l0) {
+        lv.sort_bands = L.leaf_tiles;
+        lv.sort_tc = L.leaf_rows * m.W;
+        QV_LAUNCH_L(d, (k_node<8, false, true>), dim3(nq + L.leaf_tiles), dim3(kBlock), lds_small,
+                    st, m, lv, tr);
+      } else if (!last || store_leaves) {
         QV_LAUNCH_L(d, (k_node<8, false>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
       } else if (A <= 4) {
         QV_LAUNCH_L(d, (k_node<4, true>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
