@@ -144,7 +144,8 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const int i = i0 + k * kBlock;
-      sg[k] = i < S ? sig[c_lo + i] : 0u;
+      const uint32_t sv = sig[c_lo + (i < S ? i : 0)];   // every lane loads, then masks
+      sg[k] = i < S ? sv : 0u;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -291,12 +292,19 @@ __device__ __forceinline__ void load_band(const DevModel &m, const uint32_t *sig
       const int gy = y0 - 1 + r, gx = i - r * BW - 1;
       const bool in = i < n && gy >= 0 && gy < m.H && gx >= 0 && gx < m.W;
       cell[j] = in ? gy * m.W + gx : -1;
-      v[j] = (in && cell[j] != m.goal) ? b[cell[j]] : 0.f;
+      // every lane loads (cell 0 for halo and padding lanes), so the loads of
+      // the batch go out together without a branch around each
+      // (bitwise conditions: a short-circuit one lets the compiler move the
+      // load under a branch)
+      const float bv = b[in ? cell[j] : 0];
+      v[j] = ((uint32_t)in & (uint32_t)(cell[j] != m.goal)) ? bv : 0.f;
     }
     if (mask) {
 #pragma unroll
-      for (int j = 0; j < BATCH; ++j)
-        if (cell[j] >= 0 && !(sig[cell[j]] & kSigFree)) v[j] = 0.f;
+      for (int j = 0; j < BATCH; ++j) {
+        const uint32_t sv = sig[cell[j] >= 0 ? cell[j] : 0];
+        v[j] = ((uint32_t)(cell[j] >= 0) & (sv ^ kSigFree) & kSigFree) ? 0.f : v[j];
+      }
     }
 #pragma unroll
     for (int j = 0; j < BATCH; ++j) {
@@ -338,10 +346,23 @@ constexpr int kLeafBatch = 2;
 constexpr int kNodeBatch = 16;  // the same in k_node (bound by LDS, not registers)
 constexpr int kSortBatch = 8;   // cells of a leaf-histogram chunk loaded together
 
+// k_node's dynamic LDS: b' [S], then X (the band; then chunk partials or the
+// landmark terms of the draws; then the backup scratch) of this many floats,
+// then (inner levels) 16 histogram bins per thread.
+__host__ __device__ inline size_t small_x_floats(int W, int H, int A, int n, int L) {
+  size_t x = (size_t)(H + 2) * (W + 2);
+  const size_t c[4] = {(size_t)(16 + 1) * kBlock,   // leaf chunk partials, A <= 16
+                       (size_t)A * n + A, (size_t)2 * L + 16, (size_t)16};
+  for (int i = 0; i < 4; ++i) x = x > c[i] ? x : c[i];
+  return x;
+}
+
 // Q(t, .) padded to APAD entries; float4 loads when rows are APAD wide.
-template <int APAD>
+// QV: 1 rows are read as float4 (A = APAD, 16-byte aligned), 0 element by
+// element, -1 as lv.q_vec says.
+template <int APAD, int QV = -1>
 __device__ __forceinline__ void load_q_row(const LevelArgs &lv, int A, int t, float (&q)[APAD]) {
-  if (APAD <= 8 && lv.q_vec) {
+  if (APAD <= 8 && (QV == 1 || (QV == -1 && lv.q_vec))) {
     const float4 *q4 = (const float4 *)(lv.Q + (size_t)t * APAD);
 #pragma unroll
     for (int c4 = 0; c4 < APAD / 4; ++c4) {
@@ -356,6 +377,22 @@ __device__ __forceinline__ void load_q_row(const LevelArgs &lv, int A, int t, fl
 #pragma unroll
     for (int c = 0; c < APAD; ++c) q[c] = (c < A) ? Qr[c] : 0.f;
   }
+}
+
+// Sum of x[k * stride] over lo <= k < hi in a fixed order: eight running
+// sums over k - lo mod 8, then added pairwise.
+__device__ __forceinline__ float range_sum(const float *x, int stride, int lo, int hi) {
+  float s[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] = 0.f;
+  int k = lo;
+  for (; k + 8 <= hi; k += 8)
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += x[(k + u) * stride];
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (k + u < hi) s[u] += x[(k + u) * stride];
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // Hand-off between workgroups of one launch.  Values another workgroup will
@@ -402,25 +439,6 @@ __device__ __forceinline__ float block_sum32(float (&v)[32], float *red) {
 // ---------------------------------------------------------------------------
 // observation draws of one Q-node, by one wavefront
 // ---------------------------------------------------------------------------
-struct ObsSource {
-  const float *p0;          // LDS [16]: P(zw, no landmark)
-  const uint32_t *lw;       // LDS [L]: wall reading of landmark l+1
-  const float *lv;          // LDS [L]: predicted mass on landmark l+1
-  int L;
-  float fl[4], lmp;         // flip probabilities and landmark rate, in registers
-};
-
-// P(z|b,a) for z = zw + 16 zl.
-__device__ __forceinline__ float obs_prob(const ObsSource &src, int z) {
-  const int zw = z & 15, zl = z >> 4;
-  const float from_p0 = src.p0[zw];
-  if (zl == 0) return from_p0;
-  if (zl > src.L) return 0.f;
-  const uint32_t w = src.lw[zl - 1];
-  if (w > 15u) return 0.f;
-  return wall_lik(src.fl, (uint32_t)zw, w) * src.lmp * src.lv[zl - 1];
-}
-
 // Copy of the drawn children kept in LDS for the rest of a workgroup.
 struct DrawOut {
   int z[QV_MAX_SAMPLES], count[QV_MAX_SAMPLES];
@@ -428,144 +446,185 @@ struct DrawOut {
   int U;
 };
 
+// The observations z = zw + 16 zl come in blocks of 16 (one block per zl, the
+// wall reading zw inside it).  Block 0 is "no landmark seen": P(zw, 0) from
+// the LDS table p0.  Block l >= 1 is landmark l: O_w(zw | w_l) rho b'(x_l),
+// zero when landmark l sits on a blocked cell (w_l > 15).
+__device__ __forceinline__ void obs_block(int blk, int L, const float (&fl)[4], float lmp,
+                                          const float *p0, const uint32_t *lw,
+                                          const float *lvv, float (&v)[16]) {
+  if (blk == 0) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = p0[i];
+    return;
+  }
+  uint32_t w = 16u;
+  float mass = 0.f;
+  if (blk <= L) {
+    w = lw[blk - 1];
+    mass = lvv[blk - 1];
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = w > 15u ? 0.f : wall_lik(fl, (uint32_t)i, w) * lmp * mass;
+}
+
+// Running totals of one page of 64 blocks: lane j holds block 64 g + j and
+// gets F[i], the total of P(z|b,a) over every z up to and including its
+// entry i.  Totals grow in z order: within a lane entry by entry, across lanes
+// in lane order, across pages from `base`, which the call advances to the
+// page's end.  lastpos: the lane's last z of positive mass so far.
+__device__ __forceinline__ void obs_page(int g, int L, const float (&fl)[4], float lmp,
+                                         const float *p0, const uint32_t *lw, const float *lvv,
+                                         float &base, float (&F)[16], int &lastpos) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int blk = g * kWave + lane;
+  float v[16];
+  obs_block(blk, L, fl, lmp, p0, lw, lvv, v);
+  float run = 0.f;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    run += v[i];
+    F[i] = run;
+    if (v[i] > 0.f) lastpos = blk * 16 + i;
+  }
+  // exclusive prefix of the lane totals in lane order, from base
+  const int nl = min(kWave, L + 1 - g * kWave);
+  float P = base, exc = base;
+  for (int i = 0; i < nl; ++i) {
+    const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(run), i));
+    if (i == lane) exc = P;
+    P += s;
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) F[i] = exc + F[i];
+  base = P;
+}
+
 // Observation draws of Q-node (slot p, action a) of level lv.d from its
 // statistics: lane w < 16 holds H[w], the predicted mass with true wall
 // reading w (landmark cells weighted by their "no landmark" factor); lw/lvv
 // (LDS) hold each landmark's wall reading and predicted mass.  Forms P(z|b,a)
 // over all z in ascending order, draws n observations by inverse CDF with
-// Philox uniforms, and writes one child record per distinct z (ascending)
-// with its frequency (Alg. 3/4).  One full wavefront; out (LDS) optional.
+// Philox uniforms (the first z whose running total exceeds u P), and writes
+// one child record per distinct z (ascending) with its frequency (Alg. 3/4).
+// One full wavefront; out (LDS) optional; p0tab: 16 floats of LDS.
 __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
                              const uint32_t *lw, const float *lvv, float *p0tab, DrawOut *out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = lv.n;
   const int cb = p * lv.K + a * n;
-  // the model's sensor scalars, once, as uniform registers (the model may sit
-  // in device memory)
-  ObsSource src;
+  // the model's sensor scalars, once, as uniform registers
+  float fl[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j)
-    src.fl[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.flip[j])));
-  src.lmp = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.lm_p)));
-  src.L = __builtin_amdgcn_readfirstlane(m.L);
-  src.p0 = p0tab;
-  src.lw = lw;
-  src.lv = lvv;
+    fl[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.flip[j])));
+  const float lmp = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.lm_p)));
+  const int L = __builtin_amdgcn_readfirstlane(m.L);
   // P(zw, no landmark) = sum_w O_w(zw|w) H[w] (landmark cells entered H with
   // their "no landmark" factor already), published in the LDS table p0tab
   float p0 = 0.f;
 #pragma unroll
   for (int w = 0; w < 16; ++w) {
     const float hw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hs), w));
-    p0 = fmaf(wall_lik(src.fl, (uint32_t)(lane & 15), (uint32_t)w), hw, p0);
+    p0 = fmaf(wall_lik(fl, (uint32_t)(lane & 15), (uint32_t)w), hw, p0);
   }
   if (lane < 16) p0tab[lane] = p0;
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  // running totals over z in ascending order: lane j owns z in [j*CH, (j+1)*CH)
-  const int Z = 16 * (src.L + 1);
-  const int CH = (Z + kWave - 1) / kWave;
-  float loc = 0.f;
-  for (int j = 0; j < CH; ++j) {
-    const int z = lane * CH + j;
-    const float v = obs_prob(src, min(z, Z - 1));
-    loc += (z < Z) ? v : 0.f;
-  }
-  // exclusive prefix of the lane totals, summed in lane order, so the running
-  // totals are non-decreasing across lanes and the last one is the total P
-  float exc = 0.f, P = 0.f;
-#pragma unroll 4
-  for (int i = 0; i < kWave; ++i) {
-    const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(loc), i));
-    if (i == lane) exc = P;
-    P += s;
-  }
-  // n uniforms: Philox counter (a*ceil(n/4) + k/4, slot, level, query), word k%4
-  float tgt[QV_MAX_SAMPLES];
-  const int ng = (n + 3) / 4;
-#pragma unroll
-  for (int g = 0; g < QV_MAX_SAMPLES / 4; ++g) {
-    if (g < ng) {
-      const uint4 r = philox4x32_10(
-          make_uint4((uint32_t)(a * ng + g), (uint32_t)p, (uint32_t)lv.d, lv.qid), lv.key0,
-          lv.key1);
-      tgt[4 * g + 0] = u24(r.x) * P;
-      tgt[4 * g + 1] = u24(r.y) * P;
-      tgt[4 * g + 2] = u24(r.z) * P;
-      tgt[4 * g + 3] = u24(r.w) * P;
-    }
-  }
-  // first z of positive mass whose running total exceeds the target
-  constexpr int kNone = 0x7fffffff;
-  int cand[QV_MAX_SAMPLES];
-#pragma unroll
-  for (int k = 0; k < QV_MAX_SAMPLES; ++k) cand[k] = kNone;
+  const int npg = (L + 1 + kWave - 1) / kWave;
+  // the total P(z|b,a); a single page keeps its running totals for the search
+  float F[16];
+  float base = 0.f;
   int lastpos = -1;
-  float run = 0.f;
-  for (int j = 0; j < CH; ++j) {
-    const int z = lane * CH + j;
-    float v = obs_prob(src, min(z, Z - 1));
-    if (z >= Z) v = 0.f;
-    run += v;
-    const float F = exc + run;
-    if (v > 0.f) {
-      lastpos = z;
+  for (int g = 0; g < npg; ++g) obs_page(g, L, fl, lmp, p0tab, lw, lvv, base, F, lastpos);
+  const float P = base;
+  // lane k < n: its uniform from the Philox counter (a*ceil(n/4) + k/4, slot,
+  // level, query), word k%4, and its target u P
+  float tgt = 0.f;
+  if (lane < n) {
+    const int ng = (n + 3) / 4;
+    const uint4 r = philox4x32_10(
+        make_uint4((uint32_t)(a * ng + (lane >> 2)), (uint32_t)p, (uint32_t)lv.d, lv.qid),
+        lv.key0, lv.key1);
+    const int q = lane & 3;
+    tgt = u24(q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w) * P;
+  }
+  // draw k: the first lane (block) whose last running total exceeds the
+  // target, then the first entry of that lane that does (totals only grow at
+  // entries of positive mass, so that z has positive mass); lane k keeps it
+  constexpr int kNone = 0x7fffffff;
+  int zsel = kNone;
+  uint32_t found = 0u;
+  const uint32_t all = (n >= 32) ? 0xFFFFFFFFu : ((1u << n) - 1u);
+  float base2 = 0.f;
+  int lp2 = -1;
+  for (int g = 0; g < npg && found != all; ++g) {
+    if (npg > 1) obs_page(g, L, fl, lmp, p0tab, lw, lvv, base2, F, lp2);
+    const bool live = g * kWave + lane <= L;
+    for (int k = 0; k < n; ++k) {
+      if ((found >> k) & 1u) continue;
+      const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tgt), k));
+      const unsigned long long hit = __ballot(live && F[15] > tk);
+      if (hit == 0ull) continue;
+      const int js = __ffsll((long long)hit) - 1;
+      int below = 0;
 #pragma unroll
-      for (int k = 0; k < QV_MAX_SAMPLES; ++k)
-        if (k < n && cand[k] == kNone && tgt[k] < F) cand[k] = z;
+      for (int i = 0; i < 16; ++i) below += (F[i] <= tk) ? 1 : 0;
+      const int c = __builtin_amdgcn_readlane(below, js);
+      if (lane == k) zsel = (g * kWave + js) * 16 + c;
+      found |= 1u << k;
     }
   }
-  // the last z of positive mass catches a target that rounding left beyond it
-  int lastz = lastpos;
+  if (found != all) {
+    // a target that rounding left at or beyond the total takes the last z of
+    // positive mass
+    int lastz = lastpos;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) lastz = max(lastz, __shfl_xor(lastz, o, kWave));
-  int zk[QV_MAX_SAMPLES];
-  float pk[QV_MAX_SAMPLES];
-#pragma unroll
-  for (int k = 0; k < QV_MAX_SAMPLES; ++k) {
-    if (k < n) {
-      int zz = wave_min(cand[k]);
-      if (zz == kNone) zz = lastz;
-      zk[k] = zz;
-      pk[k] = zz >= 0 ? obs_prob(src, zz) : 0.f;
+    for (int o = 32; o > 0; o >>= 1) lastz = max(lastz, __shfl_xor(lastz, o, kWave));
+    if (lane < n && zsel == kNone) zsel = lastz;
+  }
+  // lane k < n: P(z_k) of its draw
+  float pk = 0.f;
+  if (lane < n && zsel >= 0) {
+    const int zw = zsel & 15, zl = zsel >> 4;
+    if (zl == 0) {
+      pk = p0tab[zw];
+    } else {
+      const uint32_t w = lw[zl - 1];
+      pk = w > 15u ? 0.f : wall_lik(fl, (uint32_t)zw, w) * lmp * lvv[zl - 1];
     }
   }
-  if (lane == 0) {
-    // ascending z, then one child per distinct z with its frequency
-    for (int i = 1; i < n; ++i)
-      for (int j = i; j > 0 && zk[j - 1] > zk[j]; --j) {
-        const int tz = zk[j];
-        zk[j] = zk[j - 1];
-        zk[j - 1] = tz;
-        const float tp = pk[j];
-        pk[j] = pk[j - 1];
-        pk[j - 1] = tp;
-      }
-    int r = 0;
-    for (int i = 0; i < n;) {
-      int j = i;
-      while (j < n && zk[j] == zk[i]) ++j;
-      const bool ok = zk[i] >= 0 && pk[i] > 0.f;
-      lv.cvalid[cb + r] = ok ? 1 : 0;
-      lv.cz[cb + r] = zk[i];
-      lv.ccount[cb + r] = j - i;
-      lv.cpz[cb + r] = pk[i];
-      if (out && ok) {
-        out->z[r] = zk[i];
-        out->count[r] = j - i;
-        out->inv[r] = 1.0f / pk[i];
-      }
-      r += ok ? 1 : 0;
-      i = j;
-    }
-    if (out) out->U = r;
-    for (; r < n; ++r) {
-      lv.cvalid[cb + r] = 0;
-      lv.cz[cb + r] = -1;
-      lv.ccount[cb + r] = 0;
-      lv.cpz[cb + r] = 0.f;
+  // one child per distinct z in ascending z order, with its frequency: lane k
+  // compares its draw with every other one
+  uint32_t eq = 0u, lt = 0u;
+  for (int j = 0; j < n; ++j) {
+    const int zj = __builtin_amdgcn_readlane(zsel, j);
+    eq |= (uint32_t)(zj == zsel) << j;
+    lt |= (uint32_t)(zj < zsel) << j;
+  }
+  const bool first = lane < n && (eq & ((1u << lane) - 1u)) == 0u;
+  const bool ok = lane < n && zsel >= 0 && pk > 0.f;
+  const uint32_t heads = (uint32_t)__ballot(first && ok);
+  const int U = __popc(heads);
+  if (first && ok) {
+    const int r = __popc(lt & heads);
+    lv.cvalid[cb + r] = 1;
+    lv.cz[cb + r] = zsel;
+    lv.ccount[cb + r] = __popc(eq);
+    lv.cpz[cb + r] = pk;
+    if (out) {
+      out->z[r] = zsel;
+      out->count[r] = __popc(eq);
+      out->inv[r] = 1.0f / pk;
     }
   }
+  if (lane >= U && lane < n) {
+    lv.cvalid[cb + lane] = 0;
+    lv.cz[cb + lane] = -1;
+    lv.ccount[cb + lane] = 0;
+    lv.cpz[cb + lane] = 0.f;
+  }
+  if (out && lane == 0) out->U = U;
 }
 
 // Tiled path: the statistics of the Q-node are spread over per-band partials
@@ -700,9 +759,11 @@ __device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, floa
       const int i = i0 + j * kBlock;
       const bool ok = i < ncell;
       const int t = t00 + (ok ? i : 0);
-      sg[j] = ok ? lv.sig[t] : 0u;
-      bt[j] = ok ? b[t] : 0.f;
-      rr[j] = ok ? Rt[(size_t)t * A + a] : 0.f;
+      const uint32_t sv = lv.sig[t];   // loaded by every lane, then masked
+      const float bv = b[t], rv = Rt[(size_t)t * A + a];
+      sg[j] = ok ? sv : 0u;
+      bt[j] = ok ? bv : 0.f;
+      rr[j] = ok ? rv : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < kCellBatch; ++j) {
@@ -805,8 +866,11 @@ __device__ void update_item(const DevModel &m, const LevelArgs &lv, Item it, flo
     for (int j = 0; j < kCellBatch; ++j) {
       const int i = i0 + j * kBlock;
       const bool ok = i < ncell;
-      sg[j] = ok ? lv.sig[t00 + i] : 0u;
-      bt[j] = ok ? b[t00 + i] : 0.f;
+      const int t = t00 + (ok ? i : 0);
+      const uint32_t sv = lv.sig[t];   // loaded by every lane, then masked
+      const float bv = b[t];
+      sg[j] = ok ? sv : 0u;
+      bt[j] = ok ? bv : 0.f;
     }
 #pragma unroll
     for (int j = 0; j < kCellBatch; ++j) {
@@ -960,8 +1024,10 @@ __device__ void leaf_item(const DevModel &m, const LevelArgs &lv, const TreeArgs
           const int i = i0 + j * kBlock;
           const bool ok = i < ncell;
           const int t = t00 + (ok ? i : 0);
-          sg[j] = ok ? lv.sig[t] : 0u;
-          bt[j] = ok ? b[t] : 0.f;
+          const uint32_t sv = lv.sig[t];   // loaded by every lane, then masked
+          const float bv = b[t];
+          sg[j] = ok ? sv : 0u;
+          bt[j] = ok ? bv : 0.f;
           load_q_row<APAD>(lv, A, t, q[j]);
         }
 #pragma unroll
@@ -1082,27 +1148,51 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     return;
   }
   float *bpl = smem;                      // [S] predicted belief b'
-  float *X = smem + ((S + 3) & ~3);       // band, then bins, then scratch
+  float *X = smem + ((S + 3) & ~3);       // band, then scratch
   float *band = X;
+  float *hist = X + small_x_floats(W, H, A, lv.n, m.L);   // [16][kBlock] bins (LEAF = false)
   const float *b = lv.pbel + (size_t)p * S;
+  const float rW = 1.0f / (float)W;
+  // per-cell inputs of a batch: signature, b(t), R(t,a); the first batch goes
+  // out before the band load.  Lanes past S load cell 0 and are masked.
+  uint32_t sg[kNodeBatch];
+  float bt[kNodeBatch], rr[kNodeBatch];
+#pragma unroll
+  for (int j = 0; j < kNodeBatch; ++j) {
+    const int t = tid + j * kBlock;
+    const int tc = t < S ? t : 0;
+    const uint32_t sv = lv.sig[tc];
+    const float bv = b[tc], rv = m.R[(size_t)tc * A + a];
+    sg[j] = t < S ? sv : 0u;
+    bt[j] = t < S ? bv : 0.f;
+    rr[j] = t < S ? rv : 0.f;
+  }
   s_stay[tid] = lv.staytab[a * 256 + tid];
   load_band<24>(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
+  if (!LEAF) {
+#pragma unroll
+    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+  }
   __syncthreads();
-  const float rW = 1.0f / (float)W;
   const float *sl = &m.slip[a * 9];
   const float rho = m.lm_p;
-  // b'(x) for every cell (slip stencil) and R(b,a) = sum_x R(x,a) b(x)
-  float racc = 0.f;
+  // b'(x) for every cell (slip stencil), R(b,a) = sum_x R(x,a) b(x) and the
+  // histogram of b' by true wall reading (per-thread bins; landmark cells
+  // weighted by their "no landmark" factor)
+  const bool one_pass = S <= kNodeBatch * kBlock;
+  float racc = 0.f, h0 = 0.f;
   for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
-    uint32_t sg[kNodeBatch];
-    float bt[kNodeBatch], rr[kNodeBatch];
+    if (t0 != tid) {
 #pragma unroll
-    for (int j = 0; j < kNodeBatch; ++j) {
-      const int t = t0 + j * kBlock;
-      const bool ok = t < S;
-      sg[j] = ok ? lv.sig[t] : 0u;
-      bt[j] = ok ? b[t] : 0.f;
-      rr[j] = ok ? m.R[(size_t)t * A + a] : 0.f;
+      for (int j = 0; j < kNodeBatch; ++j) {
+        const int t = t0 + j * kBlock;
+        const int tc = t < S ? t : 0;
+        const uint32_t sv = lv.sig[tc];
+        const float bv = b[tc], rv = m.R[(size_t)tc * A + a];
+        sg[j] = t < S ? sv : 0u;
+        bt[j] = t < S ? bv : 0.f;
+        rr[j] = t < S ? rv : 0.f;
+      }
     }
 #pragma unroll
     for (int j = 0; j < kNodeBatch; ++j) {
@@ -1110,10 +1200,21 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
       if (t < S) {
         racc = fmaf(bt[j], rr[j], racc);
         const int ly = fdiv(t, W, rW), lx = t - ly * W;
-        bpl[t] = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt[j]);
+        const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt[j]);
+        bpl[t] = bp;
+        if (!LEAF) {
+          const uint32_t lm = sig_lm(sg[j]);
+          const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
+          const uint32_t w = sig_wall(sg[j]);
+          if (w == 0u)
+            h0 += contrib;
+          else
+            hist[w * kBlock + tid] += contrib;
+        }
       }
     }
   }
+  if (!LEAF) hist[tid] = h0;
   racc = wave_sum(racc);
   if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = racc;
   __syncthreads();
@@ -1154,9 +1255,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     const int32_t *pch = lv.sort_chunk + 2 * kBlock;
     for (int i = tid; i < 16 * NV; i += kBlock) {
       const int w = i / NV, c = i - w * NV;
-      float sum = 0.f;
-      for (int k = pch[w]; k < pch[w + 1]; ++k) sum += part[k * NV + c];
-      s_HQ[i] = sum;
+      s_HQ[i] = range_sum(part + c, NV, pch[w], pch[w + 1]);
     }
     __syncthreads();
     if (tid < 16) s_H[tid] = s_HQ[tid * NV + APAD];
@@ -1164,46 +1263,16 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     __syncthreads();
   }
   if (!LEAF) {
-    // histogram of b' by true wall reading (per-thread bins in the dead band
-    // region; landmark cells weighted by their "no landmark" factor)
-    float *hist = X;                        // [16][kBlock]
+    // the 16 bins: thread i adds 16 threads' values of bin i/16, then 16
+    // lanes combine them
+    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
+    float s = 0.f;
 #pragma unroll
-    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
-    float h0 = 0.f;
-    for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
-      uint32_t sg[kNodeBatch];
+    for (int i = 0; i < 16; ++i) s += hb[i];
 #pragma unroll
-      for (int j = 0; j < kNodeBatch; ++j) {
-        const int t = t0 + j * kBlock;
-        sg[j] = t < S ? lv.sig[t] : 0u;
-      }
-#pragma unroll
-      for (int j = 0; j < kNodeBatch; ++j) {
-        const int t = t0 + j * kBlock;
-        if (t < S) {
-          const float bp = bpl[t];
-          const uint32_t lm = sig_lm(sg[j]);
-          const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
-          const uint32_t w = sig_wall(sg[j]);
-          if (w == 0u)
-            h0 += contrib;
-          else
-            hist[w * kBlock + tid] += contrib;
-        }
-      }
-    }
-    hist[tid] = h0;
-    __syncthreads();
-    {
-      const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
-      float s = 0.f;
-#pragma unroll
-      for (int i = 0; i < 16; ++i) s += hb[i];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-      if ((tid & 15) == 0) s_H[tid >> 4] = s;
-      if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-    }
+    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
+    if ((tid & 15) == 0) s_H[tid >> 4] = s;
+    if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
     __syncthreads();
   }
   // observation draws by wave 0; X now takes the landmark terms
@@ -1232,11 +1301,13 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     // Phi(b,a,z)(x') = O(z|x') b'(x') / P(z|b,a) for each drawn z (the
     // signatures of a batch of cells are loaded once for all children)
     for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
-      uint32_t sg[kNodeBatch];
+      if (!one_pass) {
 #pragma unroll
-      for (int j = 0; j < kNodeBatch; ++j) {
-        const int t = t0 + j * kBlock;
-        sg[j] = t < S ? lv.sig[t] : 0u;
+        for (int j = 0; j < kNodeBatch; ++j) {
+          const int t = t0 + j * kBlock;
+          const uint32_t sv = lv.sig[t < S ? t : 0];
+          sg[j] = t < S ? sv : 0u;
+        }
       }
       for (int r = 0; r < U; ++r) {
         const uint32_t zl = (uint32_t)(s_draw.z[r] >> 4);
@@ -1306,8 +1377,8 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
 }
 
 // ---------------------------------------------------------------------------
-// k_leaf_parent: the last level with one workgroup per (parent slot, band of
-// rows) that handles every action of the parent.  A leaf child's score is
+// k_leaf_parent: the last level with one workgroup per (parent slot, group of
+// kLeafGroup actions, band of rows).  A leaf child's score is
 // sum_x Phi(b,a,z)(x) Q(x,c) with Phi(b,a,z)(x) = O(z|x) b'_a(x) / P(z|b,a),
 // and O(z|x) depends on x only through its true wall reading w(x) and its
 // landmark, so every child of every action follows from
@@ -1315,52 +1386,61 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
 //   HQ_a[w][A'] = sum of lambda(x) b'_a(x)       (the histogram behind P(z)),
 // lambda = 1 - rho on landmark cells, else 1, plus the predicted mass b'_a on
 // each landmark cell.  The workgroup walks its band's free cells in wall-
-// reading order (k_prep_sort), forms b'_a(x) for every action from the one
-// 3x3 neighbourhood, and reads each Q and R row once for all actions.  With
-// several bands per parent, the band records are summed in band order by the
-// last band to finish; then the wavefronts draw the observations of the
-// actions in parallel, and the workgroup forms the leaf and Q-node values,
-// the node value and the backup towards the root.
+// reading order (k_prep_sort), forms b'_a(x) for its actions from the one
+// 3x3 neighbourhood, and reads each Q row once for them.  With several bands
+// per parent, the band records are summed in band order by the last band to
+// finish; then each wavefront draws the observations of one action, and the
+// workgroup forms the leaf and Q-node values.  The last group of a parent to
+// finish forms the node value and climbs towards the root.  Splitting the
+// actions into groups keeps a workgroup small enough (registers, LDS) for
+// several to share a CU, so every parent of a level runs at once.
 // ---------------------------------------------------------------------------
-constexpr int kLeafParentBatch = 4;   // sorted cells whose loads go out together
+constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
+constexpr int kLeafParentRound = 2;   // actions whose chunk partials are summed per round
+constexpr int kStayPitch = 257;       // stay table per action in LDS: 256 patterns, then the goal
 
 struct LeafParentShared {
   float slip[8 * 9];                    // slip table, when staged in LDS
-  DrawOut draw[8];
-  float leaf[8 * QV_MAX_SAMPLES * 8];   // [a][r][c] child scores
-  float rb[8];                          // R(b,a)
-  float qn[8];                          // Q-node values
-  float red[kBlock / kWave][8];
+  DrawOut draw[kLeafGroup];
+  float leaf[kLeafGroup * QV_MAX_SAMPLES * 8];   // [a][r][c] child scores
+  float rb[kLeafGroup];                 // R(b,a)
+  float qn[8];                          // Q-node values of the whole node
+  float red[kBlock / kWave][kLeafGroup];
   int last;
 };
 
 // Floats of dynamic LDS: one region that holds in turn the band, the chunk
-// partials and the landmark tables; then the stay tables and the histograms.
+// partials and the landmark tables; then the stay tables and the histograms
+// of the workgroup's actions.
 __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM) {
   const size_t band = (size_t)(TH + 2) * (W + 2);
   const size_t lmk = (size_t)5 * L + 16 * (kBlock / kWave);   // landmark tables, P(zw) tables
-  const size_t part = (size_t)kBlock * 2 * (AM + 1);         // chunk partials, two actions
+  const size_t part = (size_t)kBlock * kLeafParentRound * (AM + 1);   // chunk partials, one round
   size_t x = band > lmk ? band : lmk;
   x = x > part ? x : part;
-  return x + (size_t)AM * 256 + (size_t)AM * 16 * (AM + 1);
+  return x + (size_t)kLeafGroup * kStayPitch + (size_t)kLeafGroup * 16 * (AM + 1);
 }
 
 // SLIP_LDS: read the slip table from LDS (for a model in device memory, whose
-// table would otherwise sit in vector registers).
-template <int AM, bool SLIP_LDS>
+// table would otherwise sit in vector registers).  QV: how Q rows are read
+// (load_q_row).  AM: Q columns (children's actions) padded to 4 or 8.
+template <int AM, bool SLIP_LDS, int QV>
 __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const TreeArgs &tr,
-                                 int p, int band, float *smem, LeafParentShared &sh) {
+                                 int p, int grp, int band, float *smem, LeafParentShared &sh) {
+  constexpr int AG = kLeafGroup;
   constexpr int NV = AM + 1;
-  constexpr int RECN = AM * 16 * NV + AM;   // band record: HQ, then R(b,a)
+  constexpr int RECN = AG * 16 * NV + AG;   // band record: HQ, then R(b,a)
   const int A = m.A, W = m.W, BW = W + 2, S = m.S, L = m.L;
   const int K = lv.K, n = lv.n;
+  const int ng = leaf_groups(A), a0 = grp * AG;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   if (!lv.pvalid[p]) {
     // children of an absent parent are absent; the parent takes no part in
     // any backup
     if (band == 0)
-      for (int i = tid; i < K; i += kBlock) {
-        const int c = p * K + i;
+      for (int i = tid; i < AG * n; i += kBlock) {
+        if (a0 + i / n >= A) break;
+        const int c = p * K + a0 * n + i;
         lv.cvalid[c] = 0;
         lv.cz[c] = -1;
         lv.ccount[c] = 0;
@@ -1370,184 +1450,205 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   }
   const int TH = lv.TH, y0 = band * TH, th = min(TH, m.H - y0);
   const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)5 * L + 16 * (kBlock / kWave);
-  const size_t partf = (size_t)kBlock * 2 * NV;
+  const size_t partf = (size_t)kBlock * kLeafParentRound * NV;
   const size_t xf = bandf > lmkf ? (bandf > partf ? bandf : partf) : (lmkf > partf ? lmkf : partf);
   float *X = smem;             // band, then the chunk partials, then the landmark tables
-  float *part = X;             // [kBlock][2 NV], later the backup scratch
-  float *stay = smem + xf;     // [A][256]
-  float *HQ = stay + AM * 256;   // [AM][16][NV]
+  float *part = X;             // [kBlock][round NV], later the backup scratch
+  float *stay = smem + xf;     // [AG][kStayPitch]
+  float *HQ = stay + AG * kStayPitch;   // [AG][16][NV]
   const float *b = lv.pbel + (size_t)p * S;
-  for (int i = tid; i < A * 256; i += kBlock) stay[i] = lv.staytab[i];
+  // stay tables of the group's actions; zeros for actions a >= A, whose sums
+  // then stay zero
+  for (int i = tid; i < AG * kStayPitch; i += kBlock) {
+    const int al = i / kStayPitch, j = i - al * kStayPitch, a = a0 + al;
+    stay[i] = a < A ? (j < 256 ? lv.staytab[a * 256 + j] : 1.f) : 0.f;
+  }
   if (SLIP_LDS && tid < A * 9) sh.slip[tid] = m.slip[tid];
   load_band<24>(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
   __syncthreads();
   const float *slip = SLIP_LDS ? sh.slip : m.slip;   // kernel argument: read as scalars
   const float rho = m.lm_p;
   const float rW = 1.0f / (float)W;
+  // the goal keeps its own mass (the band holds zero there)
+  const float bgoal = (m.goal >= y0 * W && m.goal < (y0 + th) * W) ? b[m.goal] : 0.f;
   // R(b,a) = sum_x R(x,a) b(x) over the band's own rows, in cell order
   // (coalesced rows of R; the goal's own mass is read from b)
-  float racc[AM];
+  float racc[AG];
 #pragma unroll
-  for (int a = 0; a < AM; ++a) racc[a] = 0.f;
+  for (int a = 0; a < AG; ++a) racc[a] = 0.f;
   {
     const float *Rt = m.R;
     const bool r_vec = (A == AM) && ((reinterpret_cast<uintptr_t>(Rt) & 15u) == 0);
     const int ncell = th * W, t00 = y0 * W;
     for (int i0 = tid; i0 < ncell; i0 += 4 * kBlock) {
-      float r4[4][AM], bb[4];
+      float r4[4][AG], bb[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int i = i0 + k * kBlock;
         const int t = t00 + (i < ncell ? i : 0);
         if (r_vec) {
-          const float4 *row = reinterpret_cast<const float4 *>(Rt + (size_t)t * AM);
-#pragma unroll
-          for (int c4 = 0; c4 < AM / 4; ++c4) {
-            const float4 v4 = row[c4];
-            r4[k][4 * c4] = v4.x;
-            r4[k][4 * c4 + 1] = v4.y;
-            r4[k][4 * c4 + 2] = v4.z;
-            r4[k][4 * c4 + 3] = v4.w;
-          }
+          const float4 v4 = *reinterpret_cast<const float4 *>(Rt + (size_t)t * AM + a0);
+          r4[k][0] = v4.x;
+          r4[k][1] = v4.y;
+          r4[k][2] = v4.z;
+          r4[k][3] = v4.w;
         } else {
 #pragma unroll
-          for (int a = 0; a < AM; ++a) r4[k][a] = a < A ? Rt[(size_t)t * A + a] : 0.f;
+          for (int al = 0; al < AG; ++al) {
+            const int a = a0 + al;
+            const float rv = Rt[(size_t)t * A + (a < A ? a : 0)];
+            r4[k][al] = a < A ? rv : 0.f;
+          }
         }
-        const int ly = fdiv(i, W, rW);
-        bb[k] = (i < ncell) ? ((t == m.goal) ? b[t] : X[(ly + 1) * BW + (i - ly * W) + 1]) : 0.f;
+        const int ic = i < ncell ? i : 0;
+        const int ly = fdiv(ic, W, rW);
+        const float xv = X[(ly + 1) * BW + (ic - ly * W) + 1];
+        bb[k] = (i < ncell) ? ((t == m.goal) ? bgoal : xv) : 0.f;
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int a = 0; a < AM; ++a) racc[a] = fmaf(bb[k], r4[k][a], racc[a]);
+        for (int a = 0; a < AG; ++a) racc[a] = fmaf(bb[k], r4[k][a], racc[a]);
     }
   }
-  float acc[AM][NV];
+  float acc[AG][NV];
 #pragma unroll
-  for (int a = 0; a < AM; ++a)
+  for (int a = 0; a < AG; ++a)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[a][c] = 0.f;
+  // the eight off-centre slip weights of the group's actions, held in vector
+  // registers for the whole pass: as uniform scalars they would not fit the
+  // scalar register file next to the pass's pointers, and every use would
+  // reload a spilled one
+  float slr[AG][8];
+#pragma unroll
+  for (int al = 0; al < AG; ++al)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int a = a0 + al;
+      float v = a < A ? slip[a * 9 + (k < 4 ? k : k + 1)] : 0.f;
+      asm volatile("" : "+v"(v));
+      slr[al][k] = v;
+    }
   const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
   const int j0 = ch[2 * tid], j1 = ch[2 * tid + 1];
   // the chunk in batches: the next batch's entries load while this batch's
   // Q rows are in flight
   uint32_t en[kLeafParentBatch];
+  // positions past the chunk read a valid entry and are masked to zero, so
+  // the loads need no branch
+  const int jmax = max(j1 - 1, 0);
 #pragma unroll
-  for (int k = 0; k < kLeafParentBatch; ++k)
-    en[k] = j0 + k < j1 ? (uint32_t)lv.sort_cells[j0 + k] : 0u;
+  for (int k = 0; k < kLeafParentBatch; ++k) {
+    const uint32_t v = (uint32_t)lv.sort_cells[min(j0 + k, jmax)];
+    en[k] = j0 + k < j1 ? v : 0u;
+  }
   for (int j = j0; j < j1; j += kLeafParentBatch) {
     uint32_t e[kLeafParentBatch];
-    float q[kLeafParentBatch][AM], bg[kLeafParentBatch];
+    float q[kLeafParentBatch][AM];
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
       e[k] = en[k];
       const int t = (int)(e[k] & kSortCell);
-      load_q_row<AM>(lv, A, t, q[k]);
-      bg[k] = (e[k] & kSortGoal) ? b[t] : 0.f;   // the goal keeps its own mass
+      load_q_row<AM, QV>(lv, A, t, q[k]);
     }
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
       const int jn = j + kLeafParentBatch + k;
-      en[k] = jn < j1 ? (uint32_t)lv.sort_cells[jn] : 0u;
+      const uint32_t v = (uint32_t)lv.sort_cells[min(jn, jmax)];
+      en[k] = jn < j1 ? v : 0u;
     }
+    // every lane runs the whole batch: a slot past its chunk's end reads the
+    // band's first cell with weight zero, so the loads of the batch go out
+    // together with no branch between them
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
-      if (j + k < j1) {
-        const int t = (int)(e[k] & kSortCell);
-        const int gy = fdiv(t, W, rW);
-        const float *c = X + (gy - y0 + 1) * BW + (t - gy * W) + 1;
-        const float n0 = c[-BW - 1], n1 = c[-BW], n2 = c[-BW + 1], n3 = c[-1], n5 = c[1],
-                    n6 = c[BW - 1], n7 = c[BW], n8 = c[BW + 1];
-        const bool goal = (e[k] & kSortGoal) != 0;
-        const float self = goal ? bg[k] : c[0];
-        const uint32_t o8 = (e[k] >> kSortOutShift) & 0xFFu;
-        const bool lmk = (e[k] & kSortLandmark) != 0;
-        const float lam = lmk ? 1.f - rho : 1.f;
-        uint32_t lid = 0;
-        if (lmk) lid = sig_lm(lv.sig[t]);
+      const bool in = j + k < j1;
+      const int t = in ? (int)(e[k] & kSortCell) : y0 * W;
+      const int gy = fdiv(t, W, rW);
+      const float *c = X + (gy - y0 + 1) * BW + (t - gy * W) + 1;
+      const float n0 = c[-BW - 1], n1 = c[-BW], n2 = c[-BW + 1], n3 = c[-1], n5 = c[1],
+                  n6 = c[BW - 1], n7 = c[BW], n8 = c[BW + 1];
+      const bool goal = (e[k] & kSortGoal) != 0;
+      const float cv = c[0];
+      const float self = goal ? bgoal : cv;
+      // stay weight: the cell's blocked-move pattern, or 1 at the goal
+      const uint32_t sidx = goal ? 256u : (e[k] >> kSortOutShift) & 0xFFu;
+      const bool lmk = (e[k] & kSortLandmark) != 0;
+      const float lam = in ? (lmk ? 1.f - rho : 1.f) : 0.f;
+      float bv[AG];
 #pragma unroll
-        for (int a = 0; a < AM; ++a) {
-          if (a < A) {
-            // b'_a(x): the slip stencil in gather form (as stencil())
-            const float *sl = slip + a * 9;
-            float v = sl[8] * n0;
-            v = fmaf(sl[7], n1, v);
-            v = fmaf(sl[6], n2, v);
-            v = fmaf(sl[5], n3, v);
-            v = fmaf(sl[3], n5, v);
-            v = fmaf(sl[2], n6, v);
-            v = fmaf(sl[1], n7, v);
-            v = fmaf(sl[0], n8, v);
-            v = fmaf(goal ? 1.f : stay[a * 256 + o8], self, v);
-            if (lmk) st_coherent(lv.lmv + ((size_t)p * A + a) * L + lid - 1, v);
-            v *= lam;
+      for (int a = 0; a < AG; ++a) {
+        // b'_a(x): the slip stencil in gather form (as stencil()); slr skips
+        // the centre weight, so slip k > 4 sits at k - 1
+        const float *sl = slr[a];
+        float v = sl[7] * n0;
+        v = fmaf(sl[6], n1, v);
+        v = fmaf(sl[5], n2, v);
+        v = fmaf(sl[4], n3, v);
+        v = fmaf(sl[3], n5, v);
+        v = fmaf(sl[2], n6, v);
+        v = fmaf(sl[1], n7, v);
+        v = fmaf(sl[0], n8, v);
+        v = fmaf(stay[a * kStayPitch + sidx], self, v);
+        bv[a] = v;
+        v *= lam;
 #pragma unroll
-            for (int cc = 0; cc < AM; ++cc) acc[a][cc] = fmaf(v, q[k][cc], acc[a][cc]);
-            acc[a][AM] += v;
-          }
-        }
+        for (int cc = 0; cc < AM; ++cc) acc[a][cc] = fmaf(v, q[k][cc], acc[a][cc]);
+        acc[a][AM] += v;
+      }
+      if (in && lmk) {
+        // the predicted mass on a landmark cell, for its observation
+        const uint32_t lid = sig_lm(lv.sig[t]);
+#pragma unroll
+        for (int a = 0; a < AG; ++a)
+          if (a0 + a < A) st_coherent(lv.lmv + ((size_t)p * A + a0 + a) * L + lid - 1, bv[a]);
       }
     }
   }
   // chunk partials -> histograms by wall reading.  The chunks of reading w
-  // are [pch[w], pch[w+1]); their partials are added by a fixed binary tree
-  // over the position within that range (8 steps), two actions per round.
+  // are [pch[w], pch[w+1]); one thread per (w, value) adds their partials
+  // (range_sum), kLeafParentRound actions per round.
   const int32_t *pch = ch + 2 * kBlock;
-  int my_lo = 0, my_n = 0;
-  {
-    int w = 0;
-    while (w < 16 && pch[w + 1] <= tid) ++w;
-    if (w < 16) {
-      my_lo = pch[w];
-      my_n = pch[w + 1] - pch[w];
-    }
-  }
-  constexpr int G = 2, GW = G * NV;   // actions per round, floats per thread
+  constexpr int G = kLeafParentRound;
+  constexpr int GW = G * NV;          // floats per thread and round
   __syncthreads();                    // the band is read no more: part takes its place
 #pragma unroll
-  for (int a0 = 0; a0 < AM; a0 += G) {
-    if (a0 < A) {
+  for (int al = 0; al < AG; al += G) {
+    if (a0 + al < A) {
 #pragma unroll
       for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int c = 0; c < NV; ++c) part[tid * GW + g * NV + c] = acc[a0 + g][c];
+        for (int c = 0; c < NV; ++c) part[tid * GW + g * NV + c] = acc[al + g][c];
       __syncthreads();
-      const int r = tid - my_lo;
-#pragma unroll
-      for (int st = 1; st < kBlock; st <<= 1) {
-        if (my_n > 0 && (r & (2 * st - 1)) == 0 && r + st < my_n) {
-#pragma unroll
-          for (int i = 0; i < GW; ++i) part[tid * GW + i] += part[(tid + st) * GW + i];
-        }
-        __syncthreads();
-      }
       for (int i = tid; i < 16 * GW; i += kBlock) {
         const int w = i / GW, gi = i - w * GW;
         const int g = gi / NV, c = gi - g * NV;
-        if (a0 + g < AM)
-          HQ[((a0 + g) * 16 + w) * NV + c] = pch[w + 1] > pch[w] ? part[pch[w] * GW + gi] : 0.f;
+        HQ[((al + g) * 16 + w) * NV + c] = range_sum(part + gi, GW, pch[w], pch[w + 1]);
       }
       __syncthreads();
     }
   }
 #pragma unroll
-  for (int a = 0; a < AM; ++a) {
+  for (int a = 0; a < AG; ++a) {
     const float tot = wave_total_lane63(racc[a]);
     if (lane == kWave - 1) sh.red[wave][a] = tot;
   }
   __syncthreads();
-  if (tid < A) sh.rb[tid] = (sh.red[0][tid] + sh.red[1][tid]) + (sh.red[2][tid] + sh.red[3][tid]);
+  if (tid < AG) sh.rb[tid] = (sh.red[0][tid] + sh.red[1][tid]) + (sh.red[2][tid] + sh.red[3][tid]);
   __syncthreads();
   if (lv.tiles > 1) {
-    // band record out; the last band of the parent sums all records in band order
-    float *rec = lv.part + ((size_t)p * lv.tiles + band) * RECN;
-    for (int i = tid; i < RECN; i += kBlock) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
+    // band record out; the last band of the (parent, group) sums all records
+    // in band order
+    const size_t item = (size_t)p * ng + grp;
+    float *rec = lv.part + (item * lv.tiles + band) * RECN;
+    for (int i = tid; i < RECN; i += kBlock) st_coherent(rec + i, i < AG * 16 * NV ? HQ[i] : sh.rb[i - AG * 16 * NV]);
     wait_mem();
     __syncthreads();
-    if (tid == 0) sh.last = (count_arrival(&lv.ctr[p]) == lv.tiles - 1);
+    if (tid == 0) sh.last = (count_arrival(&lv.ctr[item]) == lv.tiles - 1);
     __syncthreads();
     if (!sh.last) return;
-    const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
+    const float *rec0 = lv.part + item * lv.tiles * RECN;
     for (int i = tid; i < RECN; i += kBlock) {
       float sum = 0.f;
       int t0 = 0;
@@ -1559,71 +1660,82 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
         for (int k = 0; k < 4; ++k) sum += x[k];
       }
       for (; t0 < lv.tiles; ++t0) sum += ld_coherent(rec0 + (size_t)t0 * RECN + i);
-      if (i < AM * 16 * NV)
+      if (i < AG * 16 * NV)
         HQ[i] = sum;
       else
-        sh.rb[i - AM * 16 * NV] = sum;
+        sh.rb[i - AG * 16 * NV] = sum;
     }
-    if (tid == 0) lv.ctr[p] = 0;
+    if (tid == 0) lv.ctr[item] = 0;
     __syncthreads();
   }
-  // observation draws: wavefront w takes actions w, w + 4, ...
+  // observation draws: wavefront w takes action a0 + w
   uint32_t *lw = (uint32_t *)X;
   for (int l = tid; l < L; l += kBlock) lw[l] = lv.lm_wall[l];
   wait_mem();
   __syncthreads();
   float *lvv = X + L + wave * L;
-  for (int a = wave; a < A; a += kBlock / kWave) {
+  if (a0 + wave < A) {
+    const int a = a0 + wave;
     for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     float hs = 0.f;
-    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
+    if (lane < 16) hs = HQ[(wave * 16 + lane) * NV + AM];
     if (lane == 16) {
-      hs = sh.rb[a];
+      hs = sh.rb[wave];
       lv.reward[p * A + a] = hs;
     }
-    sample_draws(m, lv, p, a, hs, lw, lvv, X + 5 * L + 16 * wave, &sh.draw[a]);
+    sample_draws(m, lv, p, a, hs, lw, lvv, X + 5 * L + 16 * wave, &sh.draw[wave]);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // leaf values (Alg. 5) of every drawn child of every action:
+  // leaf values (Alg. 5) of every drawn child of the group's actions:
   //   zl = 0: (1/P(z)) sum_w O_w(zw|w) HQ_a[w][c];  zl = l: (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) Q(x_l,c)
-  for (int i = tid; i < A * n * AM; i += kBlock) {
-    const int a = i / (n * AM), r = (i / AM) - a * n, c = i - (i / AM) * AM;
+  for (int i = tid; i < AG * n * AM; i += kBlock) {
+    const int al = i / (n * AM), r = (i / AM) - al * n, c = i - (i / AM) * AM;
+    const int a = a0 + al;
     float v = 0.f;
-    if (c < A && r < sh.draw[a].U) {
-      const int z = sh.draw[a].z[r];
+    if (a < A && c < A && r < sh.draw[al].U) {
+      const int z = sh.draw[al].z[r];
       const uint32_t zw = (uint32_t)(z & 15);
       const int zl = z >> 4;
       if (zl == 0) {
 #pragma unroll
         for (int w = 0; w < 16; ++w)
-          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
+          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(al * 16 + w) * NV + c], v);
       } else {
         const int cell = m.lm_cell[zl - 1];
         v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
             ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * lv.Q[(size_t)cell * A + c];
       }
-      v *= sh.draw[a].inv[r];
+      v *= sh.draw[al].inv[r];
     }
     sh.leaf[i] = v;
   }
   __syncthreads();
-  // Q-node values (Alg. 6), the node value, then the backup towards the root
+  // Q-node values (Alg. 6) of the group's actions; the last group of the
+  // parent forms the node value, then the backup climbs towards the root
   const long long g = tr.first[lv.d] + p;
-  if (tid < A) {
-    const int a = tid;
-    float qv = sh.rb[a];
+  if (tid < AG && a0 + tid < A) {
+    const int al = tid, a = a0 + tid;
+    float qv = sh.rb[al];
     const long long lf = tr.first[lv.d + 1] + (long long)p * K + (long long)a * n;
-    for (int r = 0; r < sh.draw[a].U; ++r) {
+    for (int r = 0; r < sh.draw[al].U; ++r) {
       float best = -INFINITY;
-      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(a * n + r) * AM + c]);
+      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(al * n + r) * AM + c]);
       tr.value[lf + r] = best;
-      qv += tr.gamma * ((float)sh.draw[a].count[r] / (float)n) * best;
+      qv += tr.gamma * ((float)sh.draw[al].count[r] / (float)n) * best;
     }
-    tr.qvalue[g * A + a] = qv;
+    st_coherent(tr.qvalue + g * A + a, qv);
     sh.qn[a] = qv;
+  }
+  if (ng > 1) {
+    wait_mem();
+    __syncthreads();
+    if (tid == 0) sh.last = (count_arrival(&tr.node_ctr[g]) == ng - 1);
+    __syncthreads();
+    if (!sh.last) return;
+    if (tid < A) sh.qn[tid] = ld_coherent(tr.qvalue + g * A + tid);
   }
   __syncthreads();
   if (tid == 0) finish_node(tr, lv.d, g, sh.qn);
@@ -1631,12 +1743,22 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   climb_wg(tr, lv.d, p, part, &sh.last);
 }
 
-template <int AM>
+template <int AM, int QV>
 __global__ __launch_bounds__(kBlock) void k_leaf_parent(DevModel m, LevelArgs lv, TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ LeafParentShared sh;
-  const int p = blockIdx.x / lv.tiles, band = blockIdx.x - p * lv.tiles;
-  leaf_parent_item<AM, false>(m, lv, tr, p, band, smem, sh);
+  // Workgroup i runs on XCD i mod 8.  Slot p = node*K + a*n + r, and the low
+  // r (the first distinct draw of each Q-node, nearly always present) would
+  // all land on the same XCDs when K is a multiple of 8; rotating each group
+  // of 8 by its index deals the live parents evenly over the XCDs.
+  int i = blockIdx.x;
+  const int grp8 = i >> 3;
+  if ((grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
+  const int ng = leaf_groups(m.A);
+  const int per = ng * lv.tiles;
+  const int p = i / per, rem = i - p * per;
+  const int grp = rem / lv.tiles, band = rem - grp * lv.tiles;
+  leaf_parent_item<AM, false, QV>(m, lv, tr, p, grp, band, smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1758,12 +1880,8 @@ size_t leaf_lds_bytes(int W, int TH, int K, int A) {
 constexpr size_t kSmallLdsMax = 64 * 1024;
 static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
   const size_t S = (size_t)W * H;
-  size_t x = (size_t)(H + 2) * (W + 2);
-  x = std::max<size_t>(x, (size_t)16 * kBlock);
-  x = std::max<size_t>(x, (size_t)(16 + 1) * kBlock);   // leaf chunk partials, A <= 16
-  x = std::max<size_t>(x, (size_t)A * n + A);
-  x = std::max<size_t>(x, (size_t)2 * L + 16);
-  return (((S + 3) & ~(size_t)3) + x) * sizeof(float);
+  return (((S + 3) & ~(size_t)3) + small_x_floats(W, H, A, n, L) + (size_t)16 * kBlock) *
+         sizeof(float);
 }
 
 hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int D, int n,
@@ -1841,7 +1959,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
               sig, sort_cells, sort_chunk);
   }
   if (leaf_parent) {
-    const void *kf = AM == 4 ? (const void *)k_leaf_parent<4> : (const void *)k_leaf_parent<8>;
+    const void *kf = AM == 4 ? (q_vec ? (const void *)k_leaf_parent<4, 1> : (const void *)k_leaf_parent<4, 0>)
+                             : (q_vec ? (const void *)k_leaf_parent<8, 1> : (const void *)k_leaf_parent<8, 0>);
     hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_lp);
     if (e != hipSuccess) return e;
   } else if (small && !store_leaves && D > 0) {
@@ -1885,11 +2004,15 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
       lv.part = (float *)(ws + L.leafrec);
-      const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
-      if (AM == 4)
-        QV_LAUNCH_L(d, k_leaf_parent<4>, dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+      const unsigned nb = (unsigned)((long long)lv.nslots * leaf_groups(A) * L.leaf_tiles);
+      if (AM == 4 && q_vec)
+        QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+      else if (AM == 4)
+        QV_LAUNCH_L(d, (k_leaf_parent<4, 0>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+      else if (q_vec)
+        QV_LAUNCH_L(d, (k_leaf_parent<8, 1>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
       else
-        QV_LAUNCH_L(d, k_leaf_parent<8>, dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+        QV_LAUNCH_L(d, (k_leaf_parent<8, 0>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
       continue;
     }
     if (small) {
@@ -2040,8 +2163,10 @@ __global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
           leaf_item<APAD>(bq.m, lv, bq.tr, it, smem, sh);
       } else {
         const int local = i - bl.base[q];
-        leaf_parent_item<APAD, true>(bq.m, lv, bq.tr, local / lv.tiles, local % lv.tiles, smem,
-                                     shl);
+        const int per = leaf_groups(bq.m.A) * lv.tiles;
+        const int p = local / per, rem = local - p * per;
+        leaf_parent_item<APAD, true, -1>(bq.m, lv, bq.tr, p, rem / lv.tiles, rem % lv.tiles, smem,
+                                         shl);
       }
       __syncthreads();
     }

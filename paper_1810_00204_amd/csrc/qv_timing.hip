@@ -76,11 +76,18 @@ int32_t qv_timing_read(qv_kernel_time *out, int32_t max_entries, int32_t *n_out)
     float ms = 0.f;
     if (hipEventSynchronize(r.b) != hipSuccess) return QV_ERR_HIP;
     if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return QV_ERR_HIP;
+    // a template name with a comma reaches the launch macro in parentheses
+    const char *base = r.name;
+    int len = (int)std::strlen(base);
+    if (len >= 2 && base[0] == '(' && base[len - 1] == ')') {
+      ++base;
+      len -= 2;
+    }
     char nm[sizeof out[0].name];
     if (r.tag >= 0)
-      std::snprintf(nm, sizeof nm, "%s@L%d", r.name, r.tag);
+      std::snprintf(nm, sizeof nm, "%.*s@L%d", len, base, r.tag);
     else
-      std::snprintf(nm, sizeof nm, "%s", r.name);
+      std::snprintf(nm, sizeof nm, "%.*s", len, base);
     int32_t i = 0;
     while (i < n && std::strncmp(out[i].name, nm, sizeof out[i].name) != 0) ++i;
     if (i == n) {
