@@ -115,7 +115,7 @@ bool layout(qv_batch *b, int tile_cells, bool commit) {
         if (ph < 2 && banded)
           items = T.level_slots[d] * T.tiles * m.A;
         else if (ph == 2 && d + 1 == b->D[q] && lp)
-          items = T.level_slots[d] * leaf_groups(m.A) * lay[q].leaf_tiles;
+          items = T.level_slots[d] * lay[q].leaf_tiles;
         tot[ph * b->dmax + d] += items;
         if (tot[ph * b->dmax + d] > (1LL << 30)) return false;
       }

@@ -137,10 +137,6 @@ size_t leaf_lds_bytes(int W, int TH, int K, int A);
 hipError_t launch_batch_prep(const BatchPrep &bp, int cell_blocks, int lm_blocks,
                              int sort_blocks, hipStream_t st, bool timed);
 size_t leaf_parent_lds_bytes(int W, int TH, int L, int AM);
-// k_leaf_parent takes the actions of a parent in groups of kLeafGroup, one
-// workgroup per (parent, group, band) and one draw per wavefront.
-constexpr int kLeafGroup = kBlock / kWave;
-__host__ __device__ inline int leaf_groups(int A) { return (A + kLeafGroup - 1) / kLeafGroup; }
 hipError_t launch_batch_level(const BatchLevel &bl, int phase, int apad, size_t lds, int grid,
                               hipStream_t st, bool timed);
 int batch_level_occupancy(int phase, int apad, size_t lds);

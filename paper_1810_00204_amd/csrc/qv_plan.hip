@@ -29,6 +29,28 @@ namespace qv {
 // ---------------------------------------------------------------------------
 // map signature, stay table, counters
 // ---------------------------------------------------------------------------
+// Signature of cell s without its landmark id: the 8-neighbour move pattern
+// (bit set = the move is possible), free and goal bits, and the true wall
+// reading in bits 10..13.
+__device__ __forceinline__ uint32_t cell_bits(const DevModel &m, int s) {
+  const int y = s / m.W, x0 = s - y * m.W;
+  uint32_t v = 0;
+  int bit = 0;
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) continue;
+    const int ny = y + k / 3 - 1, nx = x0 + k % 3 - 1;
+    const bool ok = ny >= 0 && ny < m.H && nx >= 0 && nx < m.W && m.occ[ny * m.W + nx] == 0;
+    if (ok) v |= 1u << bit;
+    ++bit;
+  }
+  if (m.occ[s] == 0) v |= kSigFree;
+  if (s == m.goal) v |= kSigGoal;
+  // wall bits up/left/right/down are neighbours k = 1, 3, 5, 7 -> bits 1, 3, 4, 6
+  const uint32_t w = (((v >> 1) & 1u) ^ 1u) | ((((v >> 3) & 1u) ^ 1u) << 1) |
+                     ((((v >> 4) & 1u) ^ 1u) << 2) | ((((v >> 6) & 1u) ^ 1u) << 3);
+  return v | (w << 10);
+}
+
 // Thread g of the prep pass of one query: clears the error word, writes the
 // root records and the counters, the stay table and the signature of cell g.
 __device__ void prep_sig_one(const DevModel &m, uint32_t *sig, float *staytab, int32_t *err,
@@ -58,22 +80,7 @@ __device__ void prep_sig_one(const DevModel &m, uint32_t *sig, float *staytab, i
     staytab[s] = st;
   }
   if (g >= m.S) return;
-  const int y = s / m.W, x0 = s - y * m.W;
-  uint32_t v = 0;
-  int bit = 0;
-  for (int k = 0; k < 9; ++k) {
-    if (k == 4) continue;
-    const int ny = y + k / 3 - 1, nx = x0 + k % 3 - 1;
-    const bool ok = ny >= 0 && ny < m.H && nx >= 0 && nx < m.W && m.occ[ny * m.W + nx] == 0;
-    if (ok) v |= 1u << bit;
-    ++bit;
-  }
-  if (m.occ[s] == 0) v |= kSigFree;
-  if (s == m.goal) v |= kSigGoal;
-  // wall bits up/left/right/down are neighbours k = 1, 3, 5, 7 -> bits 1, 3, 4, 6
-  const uint32_t w = (((v >> 1) & 1u) ^ 1u) | ((((v >> 3) & 1u) ^ 1u) << 1) |
-                     ((((v >> 4) & 1u) ^ 1u) << 2) | ((((v >> 6) & 1u) ^ 1u) << 3);
-  sig[s] = v | (w << 10);
+  sig[s] = cell_bits(m, s);
 }
 
 __global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *err,
@@ -104,6 +111,30 @@ __device__ void prep_landmark_one(const DevModel &m, uint32_t *sig, int32_t *err
 
 __global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32_t *lm_wall) {
   prep_landmark_one(m, sig, err, lm_wall, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// The prep pass of a plan in one launch: as k_prep_sig, with each cell's
+// landmark id found by a scan of the landmark list (staged in LDS; the
+// lowest id wins if two share a cell) instead of a second launch that
+// inserts the ids, and thread l < L writing landmark l's wall reading.
+// Landmark errors are not flagged here (a plan does not read the error word).
+__global__ __launch_bounds__(256) void k_prep_plan(DevModel m, uint32_t *sig, float *staytab,
+                                                   int32_t *err, PrepExtra x) {
+  __shared__ int s_lm[QV_MAX_LANDMARKS];
+  for (int l = threadIdx.x; l < m.L; l += blockDim.x) s_lm[l] = m.lm_cell[l];
+  __syncthreads();
+  const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < m.L) {
+    const int c = s_lm[g];
+    x.lm_wall[g] = (c >= 0 && c < m.S) ? sig_wall(cell_bits(m, c)) : 0xFFFFFFFFu;
+  }
+  prep_sig_one(m, sig, staytab, err, x, g);
+  if (g >= m.S) return;
+  const int s = (int)g;
+  uint32_t id = 0;
+  for (int l = m.L - 1; l >= 0; --l)
+    if (s_lm[l] == s) id = (uint32_t)(l + 1);
+  if (id) sig[s] |= id << 14;
 }
 
 // Sorted cell entries: bits 0..21 the cell index (S <= 2048 * 2048 = 2^22),
@@ -256,6 +287,14 @@ static void prep_launch(const DevModel &dm, uint32_t *sig, float *staytab, int32
   if (dm.L > 0)
     QV_LAUNCH(k_prep_landmarks, dim3((dm.L + 255) / 256), dim3(256), 0, st, dm, sig, err,
               x.lm_wall);
+}
+
+static void prep_plan_launch(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
+                             const PrepExtra &x, hipStream_t st) {
+  const long long n =
+      std::max<long long>(std::max<long long>(std::max(dm.S, dm.A * 256), x.nzero), dm.L);
+  QV_LAUNCH(k_prep_plan, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, dm, sig, staytab,
+            err, x);
 }
 
 hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
@@ -1153,20 +1192,22 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   float *hist = X + small_x_floats(W, H, A, lv.n, m.L);   // [16][kBlock] bins (LEAF = false)
   const float *b = lv.pbel + (size_t)p * S;
   const float rW = 1.0f / (float)W;
-  // per-cell inputs of a batch: signature, b(t), R(t,a); the first batch goes
-  // out before the band load.  Lanes past S load cell 0 and are masked.
+  // per-cell inputs of a batch: signature and R(t,a) (b(t) comes from the
+  // band); the first batch goes out before the band load.  Lanes past S load
+  // cell 0 and are masked.
   uint32_t sg[kNodeBatch];
-  float bt[kNodeBatch], rr[kNodeBatch];
+  float rr[kNodeBatch];
 #pragma unroll
   for (int j = 0; j < kNodeBatch; ++j) {
     const int t = tid + j * kBlock;
     const int tc = t < S ? t : 0;
     const uint32_t sv = lv.sig[tc];
-    const float bv = b[tc], rv = m.R[(size_t)tc * A + a];
+    const float rv = m.R[(size_t)tc * A + a];
     sg[j] = t < S ? sv : 0u;
-    bt[j] = t < S ? bv : 0.f;
     rr[j] = t < S ? rv : 0.f;
   }
+  // the goal keeps its own mass (the band holds zero there)
+  const float bgoal = m.goal >= 0 ? b[m.goal] : 0.f;
   s_stay[tid] = lv.staytab[a * 256 + tid];
   load_band<24>(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
   if (!LEAF) {
@@ -1188,9 +1229,8 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
         const int t = t0 + j * kBlock;
         const int tc = t < S ? t : 0;
         const uint32_t sv = lv.sig[tc];
-        const float bv = b[tc], rv = m.R[(size_t)tc * A + a];
+        const float rv = m.R[(size_t)tc * A + a];
         sg[j] = t < S ? sv : 0u;
-        bt[j] = t < S ? bv : 0.f;
         rr[j] = t < S ? rv : 0.f;
       }
     }
@@ -1198,9 +1238,12 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     for (int j = 0; j < kNodeBatch; ++j) {
       const int t = t0 + j * kBlock;
       if (t < S) {
-        racc = fmaf(bt[j], rr[j], racc);
         const int ly = fdiv(t, W, rW), lx = t - ly * W;
-        const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt[j]);
+        // b(t): the band holds the belief (blocked cells hold no mass in any
+        // belief the planner accepts or forms), except at the goal
+        const float bt = t == m.goal ? bgoal : band[(ly + 1) * BW + lx + 1];
+        racc = fmaf(bt, rr[j], racc);
+        const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, s_stay, bt);
         bpl[t] = bp;
         if (!LEAF) {
           const uint32_t lm = sig_lm(sg[j]);
@@ -1377,70 +1420,70 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
 }
 
 // ---------------------------------------------------------------------------
-// k_leaf_parent: the last level with one workgroup per (parent slot, group of
-// kLeafGroup actions, band of rows).  A leaf child's score is
+// k_leaf_parent: the last level with one workgroup per (parent slot, band of
+// rows) that handles every action of the parent.  A leaf child's score is
 // sum_x Phi(b,a,z)(x) Q(x,c) with Phi(b,a,z)(x) = O(z|x) b'_a(x) / P(z|b,a),
 // and O(z|x) depends on x only through its true wall reading w(x) and its
 // landmark, so every child of every action follows from
 //   HQ_a[w][c] = sum over free x with reading w of lambda(x) b'_a(x) Q(x,c),
 //   HQ_a[w][A'] = sum of lambda(x) b'_a(x)       (the histogram behind P(z)),
 // lambda = 1 - rho on landmark cells, else 1, plus the predicted mass b'_a on
-// each landmark cell.  The workgroup walks its band's free cells in wall-
-// reading order (k_prep_sort), forms b'_a(x) for its actions from the one
-// 3x3 neighbourhood, and reads each Q row once for them.  With several bands
+// each landmark cell.  The prediction is linear in the slip weights:
+//   b'_a(x) = sum_k T'(a,k) s_k(x),  s_k(x) = b(x - d_k) + [move k blocked at x] b(x)
+// (s_4 = b(x)), so with the nine basis histograms
+//   E_k[w][c] = sum over x with reading w of lambda(x) s_k(x) Q(x,c)
+// every action's histogram is HQ_a = sum_k T'(a,k) E_k.  The workgroup walks
+// its band's free cells in wall-reading order (k_prep_sort), reads each 3x3
+// neighbourhood and Q row once and accumulates the 9 (A'+1) basis sums, which
+// do not depend on the number of actions.  The goal (whose own mass stays
+// with weight 1 for every action) is scored on its own.  With several bands
 // per parent, the band records are summed in band order by the last band to
-// finish; then each wavefront draws the observations of one action, and the
-// workgroup forms the leaf and Q-node values.  The last group of a parent to
-// finish forms the node value and climbs towards the root.  Splitting the
-// actions into groups keeps a workgroup small enough (registers, LDS) for
-// several to share a CU, so every parent of a level runs at once.
+// finish; then the wavefronts draw the observations of the actions in
+// parallel, and the workgroup forms the leaf and Q-node values, the node value
+// and the backup towards the root.
 // ---------------------------------------------------------------------------
 constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
-constexpr int kLeafParentRound = 2;   // actions whose chunk partials are summed per round
-constexpr int kStayPitch = 257;       // stay table per action in LDS: 256 patterns, then the goal
+constexpr int kLeafBasisRound = 3;    // basis sums (values of k) per histogram round
 
 struct LeafParentShared {
-  float slip[8 * 9];                    // slip table, when staged in LDS
-  DrawOut draw[kLeafGroup];
-  float leaf[kLeafGroup * QV_MAX_SAMPLES * 8];   // [a][r][c] child scores
-  float rb[kLeafGroup];                 // R(b,a)
-  float qn[8];                          // Q-node values of the whole node
-  float red[kBlock / kWave][kLeafGroup];
+  float slip[8 * 9];                    // slip table (rows a >= A zero)
+  DrawOut draw[8];
+  float leaf[8 * QV_MAX_SAMPLES * 8];   // [a][r][c] child scores
+  float rb[8];                          // R(b,a)
+  float qn[8];                          // Q-node values
+  float red[kBlock / kWave][8];
+  float goal[8 * 9];                    // [a][c] lambda b'_a Q(goal, c) of the goal cell
+  int goal_w;                           // the goal's wall reading, or -1 (not in this band)
   int last;
 };
 
 // Floats of dynamic LDS: one region that holds in turn the band, the chunk
-// partials and the landmark tables; then the stay tables and the histograms
-// of the workgroup's actions.
+// partials and the landmark tables; then the basis histograms and the
+// actions' histograms.
 __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM) {
   const size_t band = (size_t)(TH + 2) * (W + 2);
   const size_t lmk = (size_t)5 * L + 16 * (kBlock / kWave);   // landmark tables, P(zw) tables
-  const size_t part = (size_t)kBlock * kLeafParentRound * (AM + 1);   // chunk partials, one round
+  const size_t part = (size_t)kBlock * kLeafBasisRound * (AM + 1);   // chunk partials, one round
   size_t x = band > lmk ? band : lmk;
   x = x > part ? x : part;
-  return x + (size_t)kLeafGroup * kStayPitch + (size_t)kLeafGroup * 16 * (AM + 1);
+  return x + (size_t)9 * 16 * (AM + 1) + (size_t)AM * 16 * (AM + 1);
 }
 
-// SLIP_LDS: read the slip table from LDS (for a model in device memory, whose
-// table would otherwise sit in vector registers).  QV: how Q rows are read
-// (load_q_row).  AM: Q columns (children's actions) padded to 4 or 8.
-template <int AM, bool SLIP_LDS, int QV>
+// QV: how Q rows are read (load_q_row).  AM: Q columns padded to 4 or 8.
+template <int AM, int QV>
 __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const TreeArgs &tr,
-                                 int p, int grp, int band, float *smem, LeafParentShared &sh) {
-  constexpr int AG = kLeafGroup;
+                                 int p, int band, float *smem, LeafParentShared &sh) {
   constexpr int NV = AM + 1;
-  constexpr int RECN = AG * 16 * NV + AG;   // band record: HQ, then R(b,a)
+  constexpr int RECN = AM * 16 * NV + AM;   // band record: HQ, then R(b,a)
   const int A = m.A, W = m.W, BW = W + 2, S = m.S, L = m.L;
   const int K = lv.K, n = lv.n;
-  const int ng = leaf_groups(A), a0 = grp * AG;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   if (!lv.pvalid[p]) {
     // children of an absent parent are absent; the parent takes no part in
     // any backup
     if (band == 0)
-      for (int i = tid; i < AG * n; i += kBlock) {
-        if (a0 + i / n >= A) break;
-        const int c = p * K + a0 * n + i;
+      for (int i = tid; i < K; i += kBlock) {
+        const int c = p * K + i;
         lv.cvalid[c] = 0;
         lv.cz[c] = -1;
         lv.ccount[c] = 0;
@@ -1450,54 +1493,51 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   }
   const int TH = lv.TH, y0 = band * TH, th = min(TH, m.H - y0);
   const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)5 * L + 16 * (kBlock / kWave);
-  const size_t partf = (size_t)kBlock * kLeafParentRound * NV;
+  const size_t partf = (size_t)kBlock * kLeafBasisRound * NV;
   const size_t xf = bandf > lmkf ? (bandf > partf ? bandf : partf) : (lmkf > partf ? lmkf : partf);
   float *X = smem;             // band, then the chunk partials, then the landmark tables
-  float *part = X;             // [kBlock][round NV], later the backup scratch
-  float *stay = smem + xf;     // [AG][kStayPitch]
-  float *HQ = stay + AG * kStayPitch;   // [AG][16][NV]
+  float *part = X;             // [kBlock][round values], later the backup scratch
+  float *E = smem + xf;        // [9][16][NV] basis histograms
+  float *HQ = E + 9 * 16 * NV;   // [AM][16][NV]
   const float *b = lv.pbel + (size_t)p * S;
-  // stay tables of the group's actions; zeros for actions a >= A, whose sums
-  // then stay zero
-  for (int i = tid; i < AG * kStayPitch; i += kBlock) {
-    const int al = i / kStayPitch, j = i - al * kStayPitch, a = a0 + al;
-    stay[i] = a < A ? (j < 256 ? lv.staytab[a * 256 + j] : 1.f) : 0.f;
-  }
-  if (SLIP_LDS && tid < A * 9) sh.slip[tid] = m.slip[tid];
+  if (tid < AM * 9) sh.slip[tid] = tid < A * 9 ? m.slip[tid] : 0.f;
+  if (tid == 0) sh.goal_w = -1;
   load_band<24>(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
   __syncthreads();
-  const float *slip = SLIP_LDS ? sh.slip : m.slip;   // kernel argument: read as scalars
   const float rho = m.lm_p;
   const float rW = 1.0f / (float)W;
   // the goal keeps its own mass (the band holds zero there)
   const float bgoal = (m.goal >= y0 * W && m.goal < (y0 + th) * W) ? b[m.goal] : 0.f;
   // R(b,a) = sum_x R(x,a) b(x) over the band's own rows, in cell order
   // (coalesced rows of R; the goal's own mass is read from b)
-  float racc[AG];
+  float racc[AM];
 #pragma unroll
-  for (int a = 0; a < AG; ++a) racc[a] = 0.f;
+  for (int a = 0; a < AM; ++a) racc[a] = 0.f;
   {
     const float *Rt = m.R;
     const bool r_vec = (A == AM) && ((reinterpret_cast<uintptr_t>(Rt) & 15u) == 0);
     const int ncell = th * W, t00 = y0 * W;
     for (int i0 = tid; i0 < ncell; i0 += 4 * kBlock) {
-      float r4[4][AG], bb[4];
+      float r4[4][AM], bb[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int i = i0 + k * kBlock;
         const int t = t00 + (i < ncell ? i : 0);
         if (r_vec) {
-          const float4 v4 = *reinterpret_cast<const float4 *>(Rt + (size_t)t * AM + a0);
-          r4[k][0] = v4.x;
-          r4[k][1] = v4.y;
-          r4[k][2] = v4.z;
-          r4[k][3] = v4.w;
+          const float4 *row = reinterpret_cast<const float4 *>(Rt + (size_t)t * AM);
+#pragma unroll
+          for (int c4 = 0; c4 < AM / 4; ++c4) {
+            const float4 v4 = row[c4];
+            r4[k][4 * c4] = v4.x;
+            r4[k][4 * c4 + 1] = v4.y;
+            r4[k][4 * c4 + 2] = v4.z;
+            r4[k][4 * c4 + 3] = v4.w;
+          }
         } else {
 #pragma unroll
-          for (int al = 0; al < AG; ++al) {
-            const int a = a0 + al;
+          for (int a = 0; a < AM; ++a) {
             const float rv = Rt[(size_t)t * A + (a < A ? a : 0)];
-            r4[k][al] = a < A ? rv : 0.f;
+            r4[k][a] = a < A ? rv : 0.f;
           }
         }
         const int ic = i < ncell ? i : 0;
@@ -1508,35 +1548,21 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int a = 0; a < AG; ++a) racc[a] = fmaf(bb[k], r4[k][a], racc[a]);
+        for (int a = 0; a < AM; ++a) racc[a] = fmaf(bb[k], r4[k][a], racc[a]);
     }
   }
-  float acc[AG][NV];
+  // basis sums E_k[c] of this thread's chunk (one wall reading)
+  float acc[9][NV];
 #pragma unroll
-  for (int a = 0; a < AG; ++a)
+  for (int k = 0; k < 9; ++k)
 #pragma unroll
-    for (int c = 0; c < NV; ++c) acc[a][c] = 0.f;
-  // the eight off-centre slip weights of the group's actions, held in vector
-  // registers for the whole pass: as uniform scalars they would not fit the
-  // scalar register file next to the pass's pointers, and every use would
-  // reload a spilled one
-  float slr[AG][8];
-#pragma unroll
-  for (int al = 0; al < AG; ++al)
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const int a = a0 + al;
-      float v = a < A ? slip[a * 9 + (k < 4 ? k : k + 1)] : 0.f;
-      asm volatile("" : "+v"(v));
-      slr[al][k] = v;
-    }
+    for (int c = 0; c < NV; ++c) acc[k][c] = 0.f;
   const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
   const int j0 = ch[2 * tid], j1 = ch[2 * tid + 1];
   // the chunk in batches: the next batch's entries load while this batch's
-  // Q rows are in flight
+  // Q rows are in flight; positions past the chunk read a valid entry and are
+  // masked to zero, so the loads need no branch
   uint32_t en[kLeafParentBatch];
-  // positions past the chunk read a valid entry and are masked to zero, so
-  // the loads need no branch
   const int jmax = max(j1 - 1, 0);
 #pragma unroll
   for (int k = 0; k < kLeafParentBatch; ++k) {
@@ -1549,8 +1575,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
       e[k] = en[k];
-      const int t = (int)(e[k] & kSortCell);
-      load_q_row<AM, QV>(lv, A, t, q[k]);
+      load_q_row<AM, QV>(lv, A, (int)(e[k] & kSortCell), q[k]);
     }
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
@@ -1559,96 +1584,119 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
       en[k] = jn < j1 ? v : 0u;
     }
     // every lane runs the whole batch: a slot past its chunk's end reads the
-    // band's first cell with weight zero, so the loads of the batch go out
-    // together with no branch between them
+    // band's first cell with weight zero
 #pragma unroll
     for (int k = 0; k < kLeafParentBatch; ++k) {
       const bool in = j + k < j1;
       const int t = in ? (int)(e[k] & kSortCell) : y0 * W;
       const int gy = fdiv(t, W, rW);
       const float *c = X + (gy - y0 + 1) * BW + (t - gy * W) + 1;
-      const float n0 = c[-BW - 1], n1 = c[-BW], n2 = c[-BW + 1], n3 = c[-1], n5 = c[1],
-                  n6 = c[BW - 1], n7 = c[BW], n8 = c[BW + 1];
-      const bool goal = (e[k] & kSortGoal) != 0;
-      const float cv = c[0];
-      const float self = goal ? bgoal : cv;
-      // stay weight: the cell's blocked-move pattern, or 1 at the goal
-      const uint32_t sidx = goal ? 256u : (e[k] >> kSortOutShift) & 0xFFu;
-      const bool lmk = (e[k] & kSortLandmark) != 0;
-      const float lam = in ? (lmk ? 1.f - rho : 1.f) : 0.f;
-      float bv[AG];
+      const float self = c[0];
+      // s_k: the mass that move k brings to x (from the neighbour at -d_k),
+      // plus x's own mass when move k is blocked at x (bit clear in the
+      // 8-neighbour pattern); s_4 = b(x)
+      const uint32_t o8 = (e[k] >> kSortOutShift) & 0xFFu;
+      float s[9];
+      s[0] = c[BW + 1];
+      s[1] = c[BW];
+      s[2] = c[BW - 1];
+      s[3] = c[1];
+      s[4] = self;
+      s[5] = c[-1];
+      s[6] = c[-BW + 1];
+      s[7] = c[-BW];
+      s[8] = c[-BW - 1];
 #pragma unroll
-      for (int a = 0; a < AG; ++a) {
-        // b'_a(x): the slip stencil in gather form (as stencil()); slr skips
-        // the centre weight, so slip k > 4 sits at k - 1
-        const float *sl = slr[a];
-        float v = sl[7] * n0;
-        v = fmaf(sl[6], n1, v);
-        v = fmaf(sl[5], n2, v);
-        v = fmaf(sl[4], n3, v);
-        v = fmaf(sl[3], n5, v);
-        v = fmaf(sl[2], n6, v);
-        v = fmaf(sl[1], n7, v);
-        v = fmaf(sl[0], n8, v);
-        v = fmaf(stay[a * kStayPitch + sidx], self, v);
-        bv[a] = v;
-        v *= lam;
-#pragma unroll
-        for (int cc = 0; cc < AM; ++cc) acc[a][cc] = fmaf(v, q[k][cc], acc[a][cc]);
-        acc[a][AM] += v;
+      for (int kk = 0; kk < 9; ++kk) {
+        if (kk == 4) continue;
+        const int bit = kk < 4 ? kk : kk - 1;
+        s[kk] += ((o8 >> bit) & 1u) ? 0.f : self;
       }
-      if (in && lmk) {
-        // the predicted mass on a landmark cell, for its observation
-        const uint32_t lid = sig_lm(lv.sig[t]);
+      const bool goal = (e[k] & kSortGoal) != 0;
+      const bool lmk = (e[k] & kSortLandmark) != 0;
+      const float lam = (in && !goal) ? (lmk ? 1.f - rho : 1.f) : 0.f;
 #pragma unroll
-        for (int a = 0; a < AG; ++a)
-          if (a0 + a < A) st_coherent(lv.lmv + ((size_t)p * A + a0 + a) * L + lid - 1, bv[a]);
+      for (int kk = 0; kk < 9; ++kk) {
+        const float v = s[kk] * lam;
+#pragma unroll
+        for (int cc = 0; cc < AM; ++cc) acc[kk][cc] = fmaf(v, q[k][cc], acc[kk][cc]);
+        acc[kk][AM] += v;
+      }
+      if (in && (lmk || goal)) {
+        // b'_a(x) = sum_k T'(a,k) s_k(x): the predicted mass on a landmark
+        // cell (for its observation) and on the goal, where the band holds
+        // zero (s_k is the inflow only) and the own mass stays with weight 1
+        const uint32_t sg = lv.sig[t];
+        const uint32_t lid = sig_lm(sg);
+        const float lg = lmk ? 1.f - rho : 1.f;
+        for (int a = 0; a < A; ++a) {
+          float v = 0.f;
+#pragma unroll
+          for (int kk = 0; kk < 9; ++kk) v = fmaf(sh.slip[a * 9 + kk], s[kk], v);
+          if (goal) {
+            v += bgoal;
+            const float gv = lg * v;
+            sh.goal[a * NV + AM] = gv;
+#pragma unroll
+            for (int cc = 0; cc < AM; ++cc) sh.goal[a * NV + cc] = gv * q[k][cc];
+          }
+          if (lmk) st_coherent(lv.lmv + ((size_t)p * A + a) * L + lid - 1, v);
+        }
+        if (goal) sh.goal_w = (int)sig_wall(sg);
       }
     }
   }
-  // chunk partials -> histograms by wall reading.  The chunks of reading w
-  // are [pch[w], pch[w+1]); one thread per (w, value) adds their partials
-  // (range_sum), kLeafParentRound actions per round.
+  // chunk partials -> basis histograms by wall reading.  The chunks of
+  // reading w are [pch[w], pch[w+1]); one thread per (w, value) adds their
+  // partials (range_sum), kLeafBasisRound values of k per round.
   const int32_t *pch = ch + 2 * kBlock;
-  constexpr int G = kLeafParentRound;
+  constexpr int G = kLeafBasisRound;
   constexpr int GW = G * NV;          // floats per thread and round
   __syncthreads();                    // the band is read no more: part takes its place
 #pragma unroll
-  for (int al = 0; al < AG; al += G) {
-    if (a0 + al < A) {
+  for (int k0 = 0; k0 < 9; k0 += G) {
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+    for (int g = 0; g < G; ++g)
 #pragma unroll
-        for (int c = 0; c < NV; ++c) part[tid * GW + g * NV + c] = acc[al + g][c];
-      __syncthreads();
-      for (int i = tid; i < 16 * GW; i += kBlock) {
-        const int w = i / GW, gi = i - w * GW;
-        const int g = gi / NV, c = gi - g * NV;
-        HQ[((al + g) * 16 + w) * NV + c] = range_sum(part + gi, GW, pch[w], pch[w + 1]);
-      }
-      __syncthreads();
+      for (int c = 0; c < NV; ++c) part[tid * GW + g * NV + c] = acc[k0 + g][c];
+    __syncthreads();
+    for (int i = tid; i < 16 * GW; i += kBlock) {
+      const int w = i / GW, gi = i - w * GW;
+      const int g = gi / NV, c = gi - g * NV;
+      E[((k0 + g) * 16 + w) * NV + c] = range_sum(part + gi, GW, pch[w], pch[w + 1]);
     }
+    __syncthreads();
+  }
+  // the actions' histograms HQ_a = sum_k T'(a,k) E_k (k in order), plus the
+  // goal's own term on its reading
+  for (int i = tid; i < AM * 16 * NV; i += kBlock) {
+    const int a = i / (16 * NV), wc = i - a * 16 * NV;
+    float v = 0.f;
+    if (a < A) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v = fmaf(sh.slip[a * 9 + k], E[k * 16 * NV + wc], v);
+      if (wc / NV == sh.goal_w) v += sh.goal[a * NV + wc % NV];
+    }
+    HQ[i] = v;
   }
 #pragma unroll
-  for (int a = 0; a < AG; ++a) {
+  for (int a = 0; a < AM; ++a) {
     const float tot = wave_total_lane63(racc[a]);
     if (lane == kWave - 1) sh.red[wave][a] = tot;
   }
   __syncthreads();
-  if (tid < AG) sh.rb[tid] = (sh.red[0][tid] + sh.red[1][tid]) + (sh.red[2][tid] + sh.red[3][tid]);
+  if (tid < A) sh.rb[tid] = (sh.red[0][tid] + sh.red[1][tid]) + (sh.red[2][tid] + sh.red[3][tid]);
   __syncthreads();
   if (lv.tiles > 1) {
-    // band record out; the last band of the (parent, group) sums all records
-    // in band order
-    const size_t item = (size_t)p * ng + grp;
-    float *rec = lv.part + (item * lv.tiles + band) * RECN;
-    for (int i = tid; i < RECN; i += kBlock) st_coherent(rec + i, i < AG * 16 * NV ? HQ[i] : sh.rb[i - AG * 16 * NV]);
+    // band record out; the last band of the parent sums all records in band order
+    float *rec = lv.part + ((size_t)p * lv.tiles + band) * RECN;
+    for (int i = tid; i < RECN; i += kBlock) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
     wait_mem();
     __syncthreads();
-    if (tid == 0) sh.last = (count_arrival(&lv.ctr[item]) == lv.tiles - 1);
+    if (tid == 0) sh.last = (count_arrival(&lv.ctr[p]) == lv.tiles - 1);
     __syncthreads();
     if (!sh.last) return;
-    const float *rec0 = lv.part + item * lv.tiles * RECN;
+    const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
     for (int i = tid; i < RECN; i += kBlock) {
       float sum = 0.f;
       int t0 = 0;
@@ -1660,82 +1708,71 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
         for (int k = 0; k < 4; ++k) sum += x[k];
       }
       for (; t0 < lv.tiles; ++t0) sum += ld_coherent(rec0 + (size_t)t0 * RECN + i);
-      if (i < AG * 16 * NV)
+      if (i < AM * 16 * NV)
         HQ[i] = sum;
       else
-        sh.rb[i - AG * 16 * NV] = sum;
+        sh.rb[i - AM * 16 * NV] = sum;
     }
-    if (tid == 0) lv.ctr[item] = 0;
+    if (tid == 0) lv.ctr[p] = 0;
     __syncthreads();
   }
-  // observation draws: wavefront w takes action a0 + w
+  // observation draws: wavefront w takes actions w, w + 4, ...
   uint32_t *lw = (uint32_t *)X;
   for (int l = tid; l < L; l += kBlock) lw[l] = lv.lm_wall[l];
   wait_mem();
   __syncthreads();
   float *lvv = X + L + wave * L;
-  if (a0 + wave < A) {
-    const int a = a0 + wave;
+  for (int a = wave; a < A; a += kBlock / kWave) {
     for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     float hs = 0.f;
-    if (lane < 16) hs = HQ[(wave * 16 + lane) * NV + AM];
+    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
     if (lane == 16) {
-      hs = sh.rb[wave];
+      hs = sh.rb[a];
       lv.reward[p * A + a] = hs;
     }
-    sample_draws(m, lv, p, a, hs, lw, lvv, X + 5 * L + 16 * wave, &sh.draw[wave]);
+    sample_draws(m, lv, p, a, hs, lw, lvv, X + 5 * L + 16 * wave, &sh.draw[a]);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  // leaf values (Alg. 5) of every drawn child of the group's actions:
+  // leaf values (Alg. 5) of every drawn child of every action:
   //   zl = 0: (1/P(z)) sum_w O_w(zw|w) HQ_a[w][c];  zl = l: (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) Q(x_l,c)
-  for (int i = tid; i < AG * n * AM; i += kBlock) {
-    const int al = i / (n * AM), r = (i / AM) - al * n, c = i - (i / AM) * AM;
-    const int a = a0 + al;
+  for (int i = tid; i < A * n * AM; i += kBlock) {
+    const int a = i / (n * AM), r = (i / AM) - a * n, c = i - (i / AM) * AM;
     float v = 0.f;
-    if (a < A && c < A && r < sh.draw[al].U) {
-      const int z = sh.draw[al].z[r];
+    if (c < A && r < sh.draw[a].U) {
+      const int z = sh.draw[a].z[r];
       const uint32_t zw = (uint32_t)(z & 15);
       const int zl = z >> 4;
       if (zl == 0) {
 #pragma unroll
         for (int w = 0; w < 16; ++w)
-          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(al * 16 + w) * NV + c], v);
+          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
       } else {
         const int cell = m.lm_cell[zl - 1];
         v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
             ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * lv.Q[(size_t)cell * A + c];
       }
-      v *= sh.draw[al].inv[r];
+      v *= sh.draw[a].inv[r];
     }
     sh.leaf[i] = v;
   }
   __syncthreads();
-  // Q-node values (Alg. 6) of the group's actions; the last group of the
-  // parent forms the node value, then the backup climbs towards the root
+  // Q-node values (Alg. 6), the node value, then the backup towards the root
   const long long g = tr.first[lv.d] + p;
-  if (tid < AG && a0 + tid < A) {
-    const int al = tid, a = a0 + tid;
-    float qv = sh.rb[al];
+  if (tid < A) {
+    const int a = tid;
+    float qv = sh.rb[a];
     const long long lf = tr.first[lv.d + 1] + (long long)p * K + (long long)a * n;
-    for (int r = 0; r < sh.draw[al].U; ++r) {
+    for (int r = 0; r < sh.draw[a].U; ++r) {
       float best = -INFINITY;
-      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(al * n + r) * AM + c]);
+      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(a * n + r) * AM + c]);
       tr.value[lf + r] = best;
-      qv += tr.gamma * ((float)sh.draw[al].count[r] / (float)n) * best;
+      qv += tr.gamma * ((float)sh.draw[a].count[r] / (float)n) * best;
     }
-    st_coherent(tr.qvalue + g * A + a, qv);
+    tr.qvalue[g * A + a] = qv;
     sh.qn[a] = qv;
-  }
-  if (ng > 1) {
-    wait_mem();
-    __syncthreads();
-    if (tid == 0) sh.last = (count_arrival(&tr.node_ctr[g]) == ng - 1);
-    __syncthreads();
-    if (!sh.last) return;
-    if (tid < A) sh.qn[tid] = ld_coherent(tr.qvalue + g * A + tid);
   }
   __syncthreads();
   if (tid == 0) finish_node(tr, lv.d, g, sh.qn);
@@ -1754,11 +1791,8 @@ __global__ __launch_bounds__(kBlock) void k_leaf_parent(DevModel m, LevelArgs lv
   int i = blockIdx.x;
   const int grp8 = i >> 3;
   if ((grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
-  const int ng = leaf_groups(m.A);
-  const int per = ng * lv.tiles;
-  const int p = i / per, rem = i - p * per;
-  const int grp = rem / lv.tiles, band = rem - grp * lv.tiles;
-  leaf_parent_item<AM, false, QV>(m, lv, tr, p, grp, band, smem, sh);
+  const int p = i / lv.tiles, band = i - p * lv.tiles;
+  leaf_parent_item<AM, QV>(m, lv, tr, p, band, smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1927,7 +1961,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
   uint32_t *lm_wall = (uint32_t *)(ws + L.lm_wall);
   const PrepExtra px = {valid, zrec, cnt, pz, ctr,
                         (long long)(L.stats_ctr_len + L.node_ctr_len), lm_wall};
-  prep_launch(m, sig, staytab, err, px, st);
+  prep_plan_launch(m, sig, staytab, err, px, st);
 
   const size_t lds_band = band_bytes(m.W, TH);
   const size_t lds_stats = lds_band + 16 * kBlock * sizeof(float);
@@ -2004,7 +2038,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
       lv.part = (float *)(ws + L.leafrec);
-      const unsigned nb = (unsigned)((long long)lv.nslots * leaf_groups(A) * L.leaf_tiles);
+      const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
       if (AM == 4 && q_vec)
         QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
       else if (AM == 4)
@@ -2163,10 +2197,7 @@ __global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
           leaf_item<APAD>(bq.m, lv, bq.tr, it, smem, sh);
       } else {
         const int local = i - bl.base[q];
-        const int per = leaf_groups(bq.m.A) * lv.tiles;
-        const int p = local / per, rem = local - p * per;
-        leaf_parent_item<APAD, true, -1>(bq.m, lv, bq.tr, p, rem / lv.tiles, rem % lv.tiles, smem,
-                                         shl);
+        leaf_parent_item<APAD, -1>(bq.m, lv, bq.tr, local / lv.tiles, local % lv.tiles, smem, shl);
       }
       __syncthreads();
     }
