@@ -272,6 +272,10 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
       lv.ctr = ctr;
       lv.sort_cells = (const int32_t *)(qb + L.sort_cells);
       lv.sort_chunk = (const int32_t *)(qb + L.sort_chunk);
+      lv.slot_list = nullptr;   // the batch takes its items from a queue
+      lv.slot_n = nullptr;
+      lv.slot_cap = 0;
+      lv.porder = nullptr;
       if (d + 1 == D && bq.leaf_parent) {
         lv.TH = L.leaf_rows;
         lv.tiles = L.leaf_tiles;

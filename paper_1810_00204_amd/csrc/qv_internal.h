@@ -34,6 +34,8 @@ struct PlanLayout {
   size_t part_slots;      // max slots of a non-leaf level
   size_t stats_ctr_len;   // int32 counters: bands done per (slot, action)
   size_t node_ctr_len;    // int32 counters: parts done per node
+  size_t slot_list;       // int32 [slots_{D-1}]: last-level parents, live ones first
+                          // (its two counts follow the node counters)
 };
 
 // Per-level kernel arguments (passed by value).
@@ -57,6 +59,12 @@ struct LevelArgs {
   // free cells in true-wall-reading order and their chunks (see k_prep_sort)
   const int32_t *sort_cells, *sort_chunk;
   int sort_bands, sort_tc;   // bands sorted by extra workgroups of this launch (0: none)
+  // slots of level d+1 in the order the next level visits them: live ones
+  // from the front (count slot_n[0]), absent ones from the back (slot_n[1]);
+  // null when the next level does not use it
+  int32_t *slot_list, *slot_n;
+  int slot_cap;           // entries of slot_list
+  const int32_t *porder;  // this level's parent slots in visiting order (null: slot order)
 };
 
 // Whole-tree view for the expectimax backup (Alg. 6/7).

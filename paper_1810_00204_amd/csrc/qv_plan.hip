@@ -664,6 +664,30 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
     lv.cpz[cb + lane] = 0.f;
   }
   if (out && lane == 0) out->U = U;
+  if (lv.slot_list) {
+    // the next level's visiting order: present children from the front,
+    // absent ones from the back
+    int live0 = 0, dead0 = 0;
+    if (lane == 0) {
+      if (U > 0) live0 = atomicAdd(&lv.slot_n[0], U);
+      if (n > U) dead0 = atomicAdd(&lv.slot_n[1], n - U);
+    }
+    live0 = __shfl(live0, 0, kWave);
+    dead0 = __shfl(dead0, 0, kWave);
+    if (first && ok) lv.slot_list[live0 + __popc(lt & heads)] = cb + __popc(lt & heads);
+    if (lane >= U && lane < n) lv.slot_list[lv.slot_cap - 1 - (dead0 + lane - U)] = cb + lane;
+  }
+}
+
+// The n children of a Q-node whose parent is absent, in the next level's
+// visiting order (from the back); threads 0..n-1 of wavefront 0.
+__device__ __forceinline__ void list_absent_children(const LevelArgs &lv, int cb) {
+  if (!lv.slot_list || threadIdx.x >= kWave) return;
+  int dead0 = 0;
+  if (threadIdx.x == 0) dead0 = atomicAdd(&lv.slot_n[1], lv.n);
+  dead0 = __shfl(dead0, 0, kWave);
+  if ((int)threadIdx.x < lv.n)
+    lv.slot_list[lv.slot_cap - 1 - (dead0 + (int)threadIdx.x)] = cb + (int)threadIdx.x;
 }
 
 // Tiled path: the statistics of the Q-node are spread over per-band partials
@@ -766,6 +790,7 @@ __device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, floa
       lv.ccount[c] = 0;
       lv.cpz[c] = 0.f;
     }
+    if (tile == 0) list_absent_children(lv, p * lv.K + a * lv.n);
     return;
   }
   const int W = m.W, BW = W + 2, A = m.A;
@@ -1184,6 +1209,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
       lv.ccount[cb + tid] = 0;
       lv.cpz[cb + tid] = 0.f;
     }
+    list_absent_children(lv, cb);
     return;
   }
   float *bpl = smem;                      // [S] predicted belief b'
@@ -1784,14 +1810,18 @@ template <int AM, int QV>
 __global__ __launch_bounds__(kBlock) void k_leaf_parent(DevModel m, LevelArgs lv, TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ LeafParentShared sh;
-  // Workgroup i runs on XCD i mod 8.  Slot p = node*K + a*n + r, and the low
-  // r (the first distinct draw of each Q-node, nearly always present) would
-  // all land on the same XCDs when K is a multiple of 8; rotating each group
-  // of 8 by its index deals the live parents evenly over the XCDs.
+  // With a visiting order, the present parents come first: they are
+  // dispatched first, dealt to the XCDs in turn and spread over the CUs,
+  // while the workgroups of absent parents (which only mark their children
+  // absent) come last.  Without one, workgroup i runs on XCD i mod 8; slot
+  // p = node*K + a*n + r, and the low r (the first distinct draw of each
+  // Q-node, nearly always present) would all land on the same XCDs when K
+  // is a multiple of 8, so each group of 8 is rotated by its index.
   int i = blockIdx.x;
   const int grp8 = i >> 3;
-  if ((grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
-  const int p = i / lv.tiles, band = i - p * lv.tiles;
+  if (!lv.porder && (grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
+  const int j = i / lv.tiles, band = i - j * lv.tiles;
+  const int p = lv.porder ? lv.porder[j] : j;
   leaf_parent_item<AM, QV>(m, lv, tr, p, band, smem, sh);
 }
 
@@ -1960,7 +1990,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
 
   uint32_t *lm_wall = (uint32_t *)(ws + L.lm_wall);
   const PrepExtra px = {valid, zrec, cnt, pz, ctr,
-                        (long long)(L.stats_ctr_len + L.node_ctr_len), lm_wall};
+                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2), lm_wall};
   prep_plan_launch(m, sig, staytab, err, px, st);
 
   const size_t lds_band = band_bytes(m.W, TH);
@@ -2034,6 +2064,15 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.sort_chunk = sort_chunk;
     lv.sort_bands = 0;
     lv.sort_tc = 0;
+    // the last level's parents in a visiting order formed by the level above
+    // (present ones first)
+    const bool order = leaf_parent && D >= 2;
+    int32_t *slot_list = (int32_t *)(ws + L.slot_list);
+    int32_t *slot_n = ctr + L.stats_ctr_len + L.node_ctr_len;
+    lv.slot_list = (order && d == D - 2) ? slot_list : nullptr;
+    lv.slot_n = slot_n;
+    lv.slot_cap = (int)T.level_slots[D - 1];
+    lv.porder = (order && d == D - 1) ? slot_list : nullptr;
     if (last && leaf_parent) {
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
