@@ -133,8 +133,10 @@ bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L,
   L->leafpart = take((size_t)T.level_slots[D] * T.tiles * A * 4);
   L->stats_ctr_len = (size_t)ps * A;
   L->node_ctr_len = (size_t)tot;
-  L->counters = take((L->stats_ctr_len + L->node_ctr_len + 2) * 4);
-  L->slot_list = take((size_t)(D > 0 ? T.level_slots[D - 1] : 1) * 4);
+  L->counters = take((L->stats_ctr_len + L->node_ctr_len + 2 * (QV_MAX_DEPTH + 1)) * 4);
+  long long list_len = 1;
+  for (int d = 1; d < D; ++d) list_len += T.level_slots[d];
+  L->slot_list = take((size_t)list_len * 4);
   L->lm_wall = take((size_t)(m->L > 0 ? m->L : 1) * 4);
   // the last level runs one workgroup per (parent, band of about 8192 cells)
   L->leaf_rows = std::max(1, std::min(m->H, 8192 / m->W));

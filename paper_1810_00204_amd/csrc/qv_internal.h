@@ -34,8 +34,8 @@ struct PlanLayout {
   size_t part_slots;      // max slots of a non-leaf level
   size_t stats_ctr_len;   // int32 counters: bands done per (slot, action)
   size_t node_ctr_len;    // int32 counters: parts done per node
-  size_t slot_list;       // int32 [slots_{D-1}]: last-level parents, live ones first
-                          // (its two counts follow the node counters)
+  size_t slot_list;       // int32: each level d = 1..D-1's slots in visiting order,
+                          // present ones first (counts follow the node counters)
 };
 
 // Per-level kernel arguments (passed by value).

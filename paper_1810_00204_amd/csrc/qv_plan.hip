@@ -547,7 +547,7 @@ __device__ __forceinline__ void obs_page(int g, int L, const float (&fl)[4], flo
 // Philox uniforms (the first z whose running total exceeds u P), and writes
 // one child record per distinct z (ascending) with its frequency (Alg. 3/4).
 // One full wavefront; out (LDS) optional; p0tab: 16 floats of LDS.
-__device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
+__device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
                              const uint32_t *lw, const float *lvv, float *p0tab, DrawOut *out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = lv.n;
@@ -664,30 +664,38 @@ __device__ void sample_draws(const DevModel &m, const LevelArgs &lv, int p, int 
     lv.cpz[cb + lane] = 0.f;
   }
   if (out && lane == 0) out->U = U;
-  if (lv.slot_list) {
-    // the next level's visiting order: present children from the front,
-    // absent ones from the back
-    int live0 = 0, dead0 = 0;
-    if (lane == 0) {
-      if (U > 0) live0 = atomicAdd(&lv.slot_n[0], U);
-      if (n > U) dead0 = atomicAdd(&lv.slot_n[1], n - U);
-    }
-    live0 = __shfl(live0, 0, kWave);
-    dead0 = __shfl(dead0, 0, kWave);
-    if (first && ok) lv.slot_list[live0 + __popc(lt & heads)] = cb + __popc(lt & heads);
-    if (lane >= U && lane < n) lv.slot_list[lv.slot_cap - 1 - (dead0 + lane - U)] = cb + lane;
-  }
+  return U;
 }
 
-// The n children of a Q-node whose parent is absent, in the next level's
-// visiting order (from the back); threads 0..n-1 of wavefront 0.
+// The next level's visiting order: a Q-node's children cb .. cb+n-1, the U
+// present ones (packed first) appended at the front of lv.slot_list, the
+// absent ones at the back.  Two steps, so that a caller can issue the
+// atomics early and write the entries once their positions have arrived:
+// list_take on thread 0 (positions returned), list_put on wavefront 0.
+struct ListPos {
+  int live0, dead0;
+};
+__device__ __forceinline__ ListPos list_take(const LevelArgs &lv, int U) {
+  ListPos lp = {0, 0};
+  if (U > 0) lp.live0 = atomicAdd(&lv.slot_n[0], U);
+  if (lv.n > U) lp.dead0 = atomicAdd(&lv.slot_n[1], lv.n - U);
+  return lp;
+}
+__device__ __forceinline__ void list_put(const LevelArgs &lv, int cb, int U, ListPos lp) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int live0 = __shfl(lp.live0, 0, kWave), dead0 = __shfl(lp.dead0, 0, kWave);
+  if (lane < U)
+    lv.slot_list[live0 + lane] = cb + lane;
+  else if (lane < lv.n)
+    lv.slot_list[lv.slot_cap - 1 - (dead0 + lane - U)] = cb + lane;
+}
+
+// The n children of a Q-node whose parent is absent; all of wavefront 0.
 __device__ __forceinline__ void list_absent_children(const LevelArgs &lv, int cb) {
   if (!lv.slot_list || threadIdx.x >= kWave) return;
-  int dead0 = 0;
-  if (threadIdx.x == 0) dead0 = atomicAdd(&lv.slot_n[1], lv.n);
-  dead0 = __shfl(dead0, 0, kWave);
-  if ((int)threadIdx.x < lv.n)
-    lv.slot_list[lv.slot_cap - 1 - (dead0 + (int)threadIdx.x)] = cb + (int)threadIdx.x;
+  ListPos lp = {0, 0};
+  if (threadIdx.x == 0) lp = list_take(lv, 0);
+  list_put(lv, cb, 0, lp);
 }
 
 // Tiled path: the statistics of the Q-node are spread over per-band partials
@@ -725,7 +733,12 @@ __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int 
   }
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
-  sample_draws(m, lv, p, a, hs, lw, lvv, lds + 2 * m.L, nullptr);
+  const int U = sample_draws(m, lv, p, a, hs, lw, lvv, lds + 2 * m.L, nullptr);
+  if (lv.slot_list) {
+    ListPos lp = {0, 0};
+    if (lane == 0) lp = list_take(lv, U);
+    list_put(lv, p * lv.K + a * lv.n, U, lp);
+  }
 }
 
 // Workgroups go to the 8 XCDs in turn (workgroup id mod 8), each XCD with
@@ -748,6 +761,13 @@ __device__ __forceinline__ Item decode_item(int idx, int tiles, int A) {
   it.a = idx - pt * A;
   it.p = pt / tiles;
   it.tile = pt - it.p * tiles;
+  return it;
+}
+
+// As decode_item, with the parents taken in the level's visiting order.
+__device__ __forceinline__ Item decode_item(int idx, const LevelArgs &lv, int A) {
+  Item it = decode_item(idx, lv.tiles, A);
+  if (lv.porder) it.p = lv.porder[it.p];
   return it;
 }
 
@@ -882,7 +902,7 @@ __device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, floa
 __global__ __launch_bounds__(kBlock) void k_stats(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
-  stats_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv.tiles, m.A), smem, sh);
+  stats_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -959,7 +979,7 @@ __device__ void update_item(const DevModel &m, const LevelArgs &lv, Item it, flo
 __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
-  update_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv.tiles, m.A), smem, sh);
+  update_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1162,7 +1182,7 @@ template <int APAD>
 __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
-  leaf_item<APAD>(m, lv, tr, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv.tiles, m.A), smem, sh);
+  leaf_item<APAD>(m, lv, tr, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv, m.A), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1199,7 +1219,8 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     }
   }
   const int bid = xcd_local_id(blockIdx.x, nodes);
-  const int p = bid / A, a = bid - p * A;
+  const int pj = bid / A, a = bid - pj * A;
+  const int p = lv.porder ? lv.porder[pj] : pj;   // present parents first
   const int cb = p * lv.K + a * lv.n;
   const int tid = threadIdx.x;
   if (!lv.pvalid[p]) {
@@ -1360,6 +1381,10 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   }
   __syncthreads();
   const int U = s_draw.U;
+  // the children's place in the next level's visiting order: the atomics go
+  // out now and their positions are used after the children are written
+  ListPos lpos = {0, 0};
+  if (!LEAF && lv.slot_list && tid == 0) lpos = list_take(lv, U);
   // per drawn z: O_w(zw | w) / P(z|b,a) for the 16 wall readings
   if (!LEAF && tid < U * 16) {
     const int r = tid >> 4, w = tid & 15;
@@ -1390,6 +1415,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
         }
       }
     }
+    if (lv.slot_list && tid < kWave) list_put(lv, cb, U, lpos);
     return;
   }
   // leaves (Alg. 5): sum_x Phi(b,a,z_r)(x) Q(x,c) for drawn z_r = zw + 16 zl
@@ -1990,7 +2016,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
 
   uint32_t *lm_wall = (uint32_t *)(ws + L.lm_wall);
   const PrepExtra px = {valid, zrec, cnt, pz, ctr,
-                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2), lm_wall};
+                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2 * (QV_MAX_DEPTH + 1)),
+                        lm_wall};
   prep_plan_launch(m, sig, staytab, err, px, st);
 
   const size_t lds_band = band_bytes(m.W, TH);
@@ -2064,15 +2091,21 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.sort_chunk = sort_chunk;
     lv.sort_bands = 0;
     lv.sort_tc = 0;
-    // the last level's parents in a visiting order formed by the level above
-    // (present ones first)
-    const bool order = leaf_parent && D >= 2;
+    // the per-parent last level visits its parents in an order formed by the
+    // level above (present ones first).  Level e's list would start after
+    // those of levels 1..e-1, its two counts at slot_n + 2 e.  (At inner
+    // levels, which have at most one workgroup per CU, the extra dependent
+    // load of the order at the start of every workgroup costs more than it
+    // gains, so they keep slot order.)
     int32_t *slot_list = (int32_t *)(ws + L.slot_list);
     int32_t *slot_n = ctr + L.stats_ctr_len + L.node_ctr_len;
-    lv.slot_list = (order && d == D - 2) ? slot_list : nullptr;
-    lv.slot_n = slot_n;
-    lv.slot_cap = (int)T.level_slots[D - 1];
-    lv.porder = (order && d == D - 1) ? slot_list : nullptr;
+    long long loff[QV_MAX_DEPTH + 1] = {0};
+    for (int e = 2; e <= D - 1; ++e) loff[e] = loff[e - 1] + T.level_slots[e - 1];
+    const bool order_next = leaf_parent && d + 1 == D - 1;
+    lv.slot_list = order_next ? slot_list + loff[d + 1] : nullptr;
+    lv.slot_n = slot_n + 2 * (d + 1);
+    lv.slot_cap = order_next ? (int)T.level_slots[d + 1] : 0;
+    lv.porder = (leaf_parent && d >= 1 && d == D - 1) ? slot_list + loff[d] : nullptr;
     if (last && leaf_parent) {
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
