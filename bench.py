@@ -185,12 +185,16 @@ def kernel_work(name, prob, counts):
     stats = P * A * S * 3.0             # bin add, R(b,a) FMA
     child = C * S * 6.0                 # O product, normalisation
     score = C * S * 2.0 * A             # A FMAs against Q per leaf cell
-    # leaf scores from wall-reading histograms: per (parent, action, cell)
-    # R(b,a) (2), lambda b' (1), A FMAs with Q and the histogram add (1);
-    # per leaf child 16 A FMAs
-    hist_q = P * A * S * (2.0 + 2.0 * A + 2.0) + C * 32.0 * A
+    # leaf scores from the nine basis histograms (k_leaf_parent): per
+    # (parent, cell) the eight inflow sums s_k (8), lambda s_k (9), 9 (AM+1)
+    # accumulations with Q (2 flops each) and R(b,a) (2 A); per parent the
+    # transform HQ_a = sum_k T'(a,k) E_k (A 16 (AM+1) 9 FMAs); per leaf child
+    # 16 A FMAs
+    AM = 4 if A <= 4 else 8
+    basis = (P * S * (8.0 + 9.0 + 18.0 * (AM + 1) + 2.0 * A)
+             + P * A * 16.0 * (AM + 1) * 18.0 + C * 32.0 * A)
     if "k_leaf_parent" in base:
-        return stencil + hist_q, P * S * 4.0, "alu"
+        return basis, P * S * 4.0, "alu"
     if "k_node" in base:
         if leaf:
             return stencil + stats + child + score, P * S * 4.0, "alu"

@@ -161,26 +161,27 @@ constexpr int kSortChunkInts = 2 * kBlock + 17;
 constexpr int kSortMaxCells = 16384;   // cells of one sorted band (leaf bands <= 8192)
 // per-cell summary kept in LDS while sorting: bits 0..7 move pattern, 8..11
 // wall reading, 12 free, 13 goal, 14 landmark
+template <int NT = kBlock>
 __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_t *cells,
                           int32_t *chunk) {
-  __shared__ int cnt[16 * kBlock];   // [w][thread], then exclusive offsets
+  __shared__ int cnt[16 * NT];   // [w][thread], then exclusive offsets
   __shared__ uint16_t cs[kSortMaxCells];
-  __shared__ int wtot[kBlock / kWave];
+  __shared__ int wtot[NT / kWave];
   __shared__ int s_start[17], s_pchunk[17], s_C;
   const int tid = threadIdx.x;
   const int S = c_hi - c_lo;
   // the band's signatures, coalesced, eight loads in flight per thread
-  for (int i0 = tid; i0 < S; i0 += 8 * kBlock) {
+  for (int i0 = tid; i0 < S; i0 += 8 * NT) {
     uint32_t sg[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int i = i0 + k * kBlock;
+      const int i = i0 + k * NT;
       const uint32_t sv = sig[c_lo + (i < S ? i : 0)];   // every lane loads, then masks
       sg[k] = i < S ? sv : 0u;
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const int i = i0 + k * kBlock;
+      const int i = i0 + k * NT;
       if (i < S) {
         const uint32_t lm = sig_lm(sg[k]);
         cs[i] = (uint16_t)(sig_out8(sg[k]) | (sig_wall(sg[k]) << 8) |
@@ -191,7 +192,7 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     }
   }
   __syncthreads();
-  const int R = (S + kBlock - 1) / kBlock;
+  const int R = (S + NT - 1) / NT;
   const int c0 = min(S, tid * R), c1 = min(S, c0 + R);   // band-relative
   int n[16];
 #pragma unroll
@@ -203,10 +204,10 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     for (int k = 0; k < 16; ++k) n[k] += (w == k) ? 1 : 0;
   }
 #pragma unroll
-  for (int w = 0; w < 16; ++w) cnt[w * kBlock + tid] = n[w];
+  for (int w = 0; w < 16; ++w) cnt[w * NT + tid] = n[w];
   __syncthreads();
   // exclusive scan of cnt in (w, thread) order: thread i owns entries
-  // [16 i, 16 i + 16), then the 256 owner totals are scanned
+  // [16 i, 16 i + 16), then the NT owner totals are scanned
   int loc[16], sum = 0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
@@ -229,13 +230,13 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
   __syncthreads();
   if (tid == 0) {
     int Sf = 0;
-    for (int v = 0; v < kBlock / kWave; ++v) Sf += wtot[v];
+    for (int v = 0; v < NT / kWave; ++v) Sf += wtot[v];
     const int C = max(1, (Sf + (kBlock - 16) - 1) / (kBlock - 16));
     int pc = 0;
     for (int w = 0; w < 16; ++w) {
-      s_start[w] = cnt[w * kBlock];
+      s_start[w] = cnt[w * NT];
       s_pchunk[w] = pc;
-      const int nw = (w < 15 ? cnt[(w + 1) * kBlock] : Sf) - cnt[w * kBlock];
+      const int nw = (w < 15 ? cnt[(w + 1) * NT] : Sf) - cnt[w * NT];
       pc += (nw + C - 1) / C;
     }
     s_start[16] = Sf;
@@ -245,7 +246,7 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
   // scatter: each thread walks its cells again in order
   int o[16];
 #pragma unroll
-  for (int w = 0; w < 16; ++w) o[w] = cnt[w * kBlock + tid];
+  for (int w = 0; w < 16; ++w) o[w] = cnt[w * NT + tid];
   for (int t = c0; t < c1; ++t) {
     const uint32_t c = cs[t];
     if (!(c & (1u << 12))) continue;
@@ -259,16 +260,19 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
                                   ((c & (1u << 14)) ? kSortLandmark : 0u));
   }
   __syncthreads();
-  // chunk k belongs to the reading w with pchunk[w] <= k < pchunk[w+1]
-  int w = 0;
-  while (w < 16 && s_pchunk[w + 1] <= tid) ++w;
-  int j0 = 0, j1 = 0;
-  if (w < 16) {
-    j0 = s_start[w] + (tid - s_pchunk[w]) * s_C;
-    j1 = min(j0 + s_C, s_start[w + 1]);
+  // chunk k (one per thread of the leaf kernel, kBlock of them) belongs to
+  // the reading w with pchunk[w] <= k < pchunk[w+1]
+  if (tid < kBlock) {
+    int w = 0;
+    while (w < 16 && s_pchunk[w + 1] <= tid) ++w;
+    int j0 = 0, j1 = 0;
+    if (w < 16) {
+      j0 = s_start[w] + (tid - s_pchunk[w]) * s_C;
+      j1 = min(j0 + s_C, s_start[w + 1]);
+    }
+    chunk[2 * tid] = c_lo + j0;
+    chunk[2 * tid + 1] = c_lo + j1;
   }
-  chunk[2 * tid] = c_lo + j0;
-  chunk[2 * tid + 1] = c_lo + j1;
   if (tid <= 16) chunk[2 * kBlock + tid] = s_pchunk[tid];
 }
 
@@ -315,18 +319,18 @@ hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_
 // start belief) they are zeroed here as well.  Loads are issued in batches
 // so that each thread has several in flight.
 constexpr int kBandBatch = 8;
-template <int BATCH = kBandBatch>
+template <int BATCH = kBandBatch, int NT = kBlock>
 __device__ __forceinline__ void load_band(const DevModel &m, const uint32_t *sig,
                                           const float *b, int y0, int th, float *band,
                                           int BW, bool mask) {
   const int n = (th + 2) * BW;
   const float rBW = 1.0f / (float)BW;
-  for (int i0 = threadIdx.x; i0 < n; i0 += BATCH * kBlock) {
+  for (int i0 = threadIdx.x; i0 < n; i0 += BATCH * NT) {
     int cell[BATCH];
     float v[BATCH];
 #pragma unroll
     for (int j = 0; j < BATCH; ++j) {
-      const int i = i0 + j * kBlock;
+      const int i = i0 + j * NT;
       const int r = fdiv(i, BW, rBW);
       const int gy = y0 - 1 + r, gx = i - r * BW - 1;
       const bool in = i < n && gy >= 0 && gy < m.H && gx >= 0 && gx < m.W;
@@ -347,7 +351,7 @@ __device__ __forceinline__ void load_band(const DevModel &m, const uint32_t *sig
     }
 #pragma unroll
     for (int j = 0; j < BATCH; ++j) {
-      const int i = i0 + j * kBlock;
+      const int i = i0 + j * NT;
       if (i < n) band[i] = v[j];
     }
   }
@@ -383,6 +387,15 @@ __device__ __forceinline__ float predict_cell_v(const float *band, int BW, int l
 constexpr int kCellBatch = 4;   // cells whose loads a thread issues together
 constexpr int kLeafBatch = 2;
 constexpr int kNodeBatch = 16;  // the same in k_node (bound by LDS, not registers)
+constexpr int kNodeBlock = 512;  // threads of an inner-level k_node workgroup
+
+// Sum of the per-wavefront partials r[0..NW) in a fixed pairwise order.
+template <int NW>
+__device__ __forceinline__ float sum_waves(const float *r) {
+  static_assert(NW == 4 || NW == 8, "4 or 8 wavefronts");
+  if constexpr (NW == 4) return (r[0] + r[1]) + (r[2] + r[3]);
+  return ((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7]));
+}
 constexpr int kSortBatch = 8;   // cells of a leaf-histogram chunk loaded together
 
 // k_node's dynamic LDS: b' [S], then X (the band; then chunk partials or the
@@ -1197,10 +1210,15 @@ __global__ __launch_bounds__(kBlock) void k_leaf(DevModel m, LevelArgs lv, TreeA
 // Q-node workgroups, that sort the leaf bands (as k_prep_sort) while the
 // first level runs.
 template <int APAD, bool LEAF, bool SORT = false>
-__global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeArgs tr) {
+__global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m, LevelArgs lv,
+                                                                     TreeArgs tr) {
+  // threads: kNodeBlock at inner levels; the leaf variant keeps kBlock (one
+  // thread per sorted chunk)
+  constexpr int NB = LEAF ? kBlock : kNodeBlock;
+  constexpr int NBATCH = kNodeBatch * kBlock / NB;   // cells per thread and pass
   extern __shared__ float smem[];
   __shared__ float s_stay[256];
-  __shared__ float s_red[kBlock / kWave * 32];
+  __shared__ float s_red[NB / kWave * 32];
   __shared__ float s_H[17];
   __shared__ DrawOut s_draw;
   __shared__ float s_tab[QV_MAX_SAMPLES * 16];     // O_w(zw_r | w) / P(z_r)
@@ -1213,7 +1231,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     nodes -= lv.sort_bands;
     if ((int)blockIdx.x >= nodes) {
       const int band = blockIdx.x - nodes, c_lo = band * lv.sort_tc;
-      sort_band(c_lo, min(S, c_lo + lv.sort_tc), m.L, lv.sig, (int32_t *)lv.sort_cells,
+      sort_band<NB>(c_lo, min(S, c_lo + lv.sort_tc), m.L, lv.sig, (int32_t *)lv.sort_cells,
                 (int32_t *)lv.sort_chunk + (size_t)band * kSortChunkInts);
       return;
     }
@@ -1236,17 +1254,17 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   float *bpl = smem;                      // [S] predicted belief b'
   float *X = smem + ((S + 3) & ~3);       // band, then scratch
   float *band = X;
-  float *hist = X + small_x_floats(W, H, A, lv.n, m.L);   // [16][kBlock] bins (LEAF = false)
+  float *hist = X + small_x_floats(W, H, A, lv.n, m.L);   // [16][NB] bins (LEAF = false)
   const float *b = lv.pbel + (size_t)p * S;
   const float rW = 1.0f / (float)W;
   // per-cell inputs of a batch: signature and R(t,a) (b(t) comes from the
   // band); the first batch goes out before the band load.  Lanes past S load
   // cell 0 and are masked.
-  uint32_t sg[kNodeBatch];
-  float rr[kNodeBatch];
+  uint32_t sg[NBATCH];
+  float rr[NBATCH];
 #pragma unroll
-  for (int j = 0; j < kNodeBatch; ++j) {
-    const int t = tid + j * kBlock;
+  for (int j = 0; j < NBATCH; ++j) {
+    const int t = tid + j * NB;
     const int tc = t < S ? t : 0;
     const uint32_t sv = lv.sig[tc];
     const float rv = m.R[(size_t)tc * A + a];
@@ -1255,11 +1273,11 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   }
   // the goal keeps its own mass (the band holds zero there)
   const float bgoal = m.goal >= 0 ? b[m.goal] : 0.f;
-  s_stay[tid] = lv.staytab[a * 256 + tid];
-  load_band<24>(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
+  if (tid < 256) s_stay[tid] = lv.staytab[a * 256 + tid];
+  load_band<24 * kBlock / NB, NB>(m, lv.sig, b, 0, H, band, BW, lv.d == 0);
   if (!LEAF) {
 #pragma unroll
-    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+    for (int w = 1; w < 16; ++w) hist[w * NB + tid] = 0.f;
   }
   __syncthreads();
   const float *sl = &m.slip[a * 9];
@@ -1267,13 +1285,13 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   // b'(x) for every cell (slip stencil), R(b,a) = sum_x R(x,a) b(x) and the
   // histogram of b' by true wall reading (per-thread bins; landmark cells
   // weighted by their "no landmark" factor)
-  const bool one_pass = S <= kNodeBatch * kBlock;
+  const bool one_pass = S <= NBATCH * NB;
   float racc = 0.f, h0 = 0.f;
-  for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
+  for (int t0 = tid; t0 < S; t0 += NBATCH * NB) {
     if (t0 != tid) {
 #pragma unroll
-      for (int j = 0; j < kNodeBatch; ++j) {
-        const int t = t0 + j * kBlock;
+      for (int j = 0; j < NBATCH; ++j) {
+        const int t = t0 + j * NB;
         const int tc = t < S ? t : 0;
         const uint32_t sv = lv.sig[tc];
         const float rv = m.R[(size_t)tc * A + a];
@@ -1282,8 +1300,8 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
       }
     }
 #pragma unroll
-    for (int j = 0; j < kNodeBatch; ++j) {
-      const int t = t0 + j * kBlock;
+    for (int j = 0; j < NBATCH; ++j) {
+      const int t = t0 + j * NB;
       if (t < S) {
         const int ly = fdiv(t, W, rW), lx = t - ly * W;
         // b(t): the band holds the belief (blocked cells hold no mass in any
@@ -1299,7 +1317,7 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
           if (w == 0u)
             h0 += contrib;
           else
-            hist[w * kBlock + tid] += contrib;
+            hist[w * NB + tid] += contrib;
         }
       }
     }
@@ -1349,20 +1367,21 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
     }
     __syncthreads();
     if (tid < 16) s_H[tid] = s_HQ[tid * NV + APAD];
-    if (tid == 16) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    if (tid == 16) s_H[16] = sum_waves<NB / kWave>(s_red);
     __syncthreads();
   }
   if (!LEAF) {
-    // the 16 bins: thread i adds 16 threads' values of bin i/16, then 16
+    // the 16 bins: thread i adds 16 threads' values of bin i / TPB, then TPB
     // lanes combine them
-    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
+    constexpr int TPB = NB / 16;
+    const float *hb = hist + (tid / TPB) * NB + (tid % TPB) * 16;
     float s = 0.f;
 #pragma unroll
     for (int i = 0; i < 16; ++i) s += hb[i];
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-    if ((tid & 15) == 0) s_H[tid >> 4] = s;
-    if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+    for (int o = TPB / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TPB);
+    if (tid % TPB == 0) s_H[tid / TPB] = s;
+    if (tid == 0) s_H[16] = sum_waves<NB / kWave>(s_red);
     __syncthreads();
   }
   // observation draws by wave 0; X now takes the landmark terms
@@ -1394,11 +1413,11 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
   if (!LEAF) {
     // Phi(b,a,z)(x') = O(z|x') b'(x') / P(z|b,a) for each drawn z (the
     // signatures of a batch of cells are loaded once for all children)
-    for (int t0 = tid; t0 < S; t0 += kNodeBatch * kBlock) {
+    for (int t0 = tid; t0 < S; t0 += NBATCH * NB) {
       if (!one_pass) {
 #pragma unroll
-        for (int j = 0; j < kNodeBatch; ++j) {
-          const int t = t0 + j * kBlock;
+        for (int j = 0; j < NBATCH; ++j) {
+          const int t = t0 + j * NB;
           const uint32_t sv = lv.sig[t < S ? t : 0];
           sg[j] = t < S ? sv : 0u;
         }
@@ -1408,8 +1427,8 @@ __global__ __launch_bounds__(kBlock) void k_node(DevModel m, LevelArgs lv, TreeA
         const float *tab = s_tab + r * 16;
         float *out = lv.cbel + (size_t)(cb + r) * S;
 #pragma unroll
-        for (int j = 0; j < kNodeBatch; ++j) {
-          const int t = t0 + j * kBlock;
+        for (int j = 0; j < NBATCH; ++j) {
+          const int t = t0 + j * NB;
           if (t < S)
             out[t] = tab[sig_wall(sg[j])] * lm_lik(rho, zl, sig_lm(sg[j])) * bpl[t];
         }
@@ -1967,10 +1986,13 @@ size_t leaf_lds_bytes(int W, int TH, int K, int A) {
 
 // Dynamic LDS of k_node: b' of the whole grid, then the largest of the band,
 // the per-thread bins, the landmark terms and the backup scratch.
-constexpr size_t kSmallLdsMax = 64 * 1024;
+// dynamic LDS of the fused path: with the level-0 launch's sort workgroups
+// (sort_band<kNodeBlock>, about 68 KB of static LDS) a workgroup stays
+// within the 160 KB of a CU
+constexpr size_t kSmallLdsMax = 88 * 1024;
 static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
   const size_t S = (size_t)W * H;
-  return (((S + 3) & ~(size_t)3) + small_x_floats(W, H, A, n, L) + (size_t)16 * kBlock) *
+  return (((S + 3) & ~(size_t)3) + small_x_floats(W, H, A, n, L) + (size_t)16 * kNodeBlock) *
          sizeof(float);
 }
 
@@ -2039,11 +2061,15 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     return hipErrorInvalidValue;   // cannot happen: leaf bands hold <= 8192 cells
   // on the fused path with D >= 2 the level-0 launch sorts the leaf bands
   const bool sort_in_l0 = leaf_parent && small && D >= 2;
-  if (sort_in_l0) {
-    hipError_t e = hipFuncSetAttribute((const void *)k_node<8, false, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds_small);
-    if (e != hipSuccess) return e;
+  if (small) {
+    const void *kn[5] = {(const void *)k_node<8, false, true>, (const void *)k_node<8, false>,
+                         (const void *)k_node<4, true>, (const void *)k_node<8, true>,
+                         (const void *)k_node<16, true>};
+    for (const void *f : kn) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)lds_small);
+      if (e != hipSuccess) return e;
+    }
   }
   if (leaf_parent && !sort_in_l0) {
     QV_LAUNCH(k_prep_sort, dim3(L.leaf_tiles), dim3(kBlock), 0, st, m.S, L.leaf_rows * m.W, m.L,
@@ -2126,10 +2152,10 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       if (d == 0 && sort_in_l0) {
         lv.sort_bands = L.leaf_tiles;
         lv.sort_tc = L.leaf_rows * m.W;
-        QV_LAUNCH_L(d, (k_node<8, false, true>), dim3(nq + L.leaf_tiles), dim3(kBlock), lds_small,
+        QV_LAUNCH_L(d, (k_node<8, false, true>), dim3(nq + L.leaf_tiles), dim3(kNodeBlock), lds_small,
                     st, m, lv, tr);
       } else if (!last || store_leaves) {
-        QV_LAUNCH_L(d, (k_node<8, false>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
+        QV_LAUNCH_L(d, (k_node<8, false>), dim3(nq), dim3(kNodeBlock), lds_small, st, m, lv, tr);
       } else if (A <= 4) {
         QV_LAUNCH_L(d, (k_node<4, true>), dim3(nq), dim3(kBlock), lds_small, st, m, lv, tr);
       } else if (A <= 8) {

@@ -72,6 +72,16 @@ def test_plan_matches_oracle_rect_grid(seed, path):
     assert len(rep.excused) <= 3
 
 
+@pytest.mark.parametrize("side", [78, 82, 84, 88])
+def test_plan_near_fused_path_lds_limit(side):
+    """Square grids on both sides of the largest one the fused per-Q-node
+    path holds in LDS (the path switches to the banded kernels above it)."""
+    _say(f"plan {side}x{side} 8 actions L=32 D=2 n=2")
+    prob = wl.make_rect(seed=side, side=side, D=2, n=2)
+    rep = _check(prob, _q32(prob), beliefs=False)
+    assert rep.nodes > 1
+
+
 @pytest.mark.parametrize("path", list(PATHS))
 @pytest.mark.parametrize("case", ["depth0", "depth1", "n1", "ragged", "corridor", "goal_in_belief",
                                   "landmark_obs", "deep", "nine_actions", "many_samples"])
