@@ -1514,6 +1514,7 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
 // and the backup towards the root.
 // ---------------------------------------------------------------------------
 constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
+constexpr int kLeafBlock = 2 * kBlock;   // threads of a k_leaf_parent workgroup
 constexpr int kLeafBasisRound = 3;    // basis sums (values of k) per histogram round
 
 struct LeafParentShared {
@@ -1522,7 +1523,7 @@ struct LeafParentShared {
   float leaf[8 * QV_MAX_SAMPLES * 8];   // [a][r][c] child scores
   float rb[8];                          // R(b,a)
   float qn[8];                          // Q-node values
-  float red[kBlock / kWave][8];
+  float red[2 * kBlock / kWave][8];
   float goal[8 * 9];                    // [a][c] lambda b'_a Q(goal, c) of the goal cell
   int goal_w;                           // the goal's wall reading, or -1 (not in this band)
   int last;
@@ -1531,9 +1532,11 @@ struct LeafParentShared {
 // Floats of dynamic LDS: one region that holds in turn the band, the chunk
 // partials and the landmark tables; then the basis histograms and the
 // actions' histograms.
-__host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM) {
+__host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM,
+                                                        int NT = kLeafBlock) {
+  const int NW = NT / kWave;
   const size_t band = (size_t)(TH + 2) * (W + 2);
-  const size_t lmk = (size_t)5 * L + 16 * (kBlock / kWave);   // landmark tables, P(zw) tables
+  const size_t lmk = (size_t)(1 + NW) * L + 16 * NW;   // landmark tables, P(zw) tables
   const size_t part = (size_t)kBlock * kLeafBasisRound * (AM + 1);   // chunk partials, one round
   size_t x = band > lmk ? band : lmk;
   x = x > part ? x : part;
@@ -1541,10 +1544,19 @@ __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, i
 }
 
 // QV: how Q rows are read (load_q_row).  AM: Q columns padded to 4 or 8.
-template <int AM, int QV>
+// NT threads (kBlock or 2 kBlock): with 2 kBlock, neighbouring lanes 2k and
+// 2k + 1 share sorted chunk k (alternate cells) and every wavefront draws for
+// one action.
+template <int AM, int QV, int NT>
 __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const TreeArgs &tr,
                                  int p, int band, float *smem, LeafParentShared &sh) {
+  static_assert(NT == kBlock || NT == 2 * kBlock, "one or two threads per chunk");
   constexpr int NV = AM + 1;
+  constexpr int NW = NT / kWave;            // wavefronts
+  constexpr int HALVES = NT / kBlock;       // threads per sorted chunk
+  // sorted cells whose loads go out together (one at 2 kBlock threads, whose
+  // workgroups must fit in 128 registers for two to share a CU)
+  constexpr int LPB = NT == kBlock ? kLeafParentBatch : 1;
   constexpr int RECN = AM * 16 * NV + AM;   // band record: HQ, then R(b,a)
   const int A = m.A, W = m.W, BW = W + 2, S = m.S, L = m.L;
   const int K = lv.K, n = lv.n;
@@ -1553,7 +1565,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     // children of an absent parent are absent; the parent takes no part in
     // any backup
     if (band == 0)
-      for (int i = tid; i < K; i += kBlock) {
+      for (int i = tid; i < K; i += NT) {
         const int c = p * K + i;
         lv.cvalid[c] = 0;
         lv.cz[c] = -1;
@@ -1563,7 +1575,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     return;
   }
   const int TH = lv.TH, y0 = band * TH, th = min(TH, m.H - y0);
-  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)5 * L + 16 * (kBlock / kWave);
+  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)(1 + NW) * L + 16 * NW;
   const size_t partf = (size_t)kBlock * kLeafBasisRound * NV;
   const size_t xf = bandf > lmkf ? (bandf > partf ? bandf : partf) : (lmkf > partf ? lmkf : partf);
   float *X = smem;             // band, then the chunk partials, then the landmark tables
@@ -1573,7 +1585,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   const float *b = lv.pbel + (size_t)p * S;
   if (tid < AM * 9) sh.slip[tid] = tid < A * 9 ? m.slip[tid] : 0.f;
   if (tid == 0) sh.goal_w = -1;
-  load_band<24>(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
+  load_band<24 * kBlock / NT, NT>(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
   __syncthreads();
   const float rho = m.lm_p;
   const float rW = 1.0f / (float)W;
@@ -1588,11 +1600,11 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     const float *Rt = m.R;
     const bool r_vec = (A == AM) && ((reinterpret_cast<uintptr_t>(Rt) & 15u) == 0);
     const int ncell = th * W, t00 = y0 * W;
-    for (int i0 = tid; i0 < ncell; i0 += 4 * kBlock) {
+    for (int i0 = tid; i0 < ncell; i0 += 4 * NT) {
       float r4[4][AM], bb[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int i = i0 + k * kBlock;
+        const int i = i0 + k * NT;
         const int t = t00 + (i < ncell ? i : 0);
         if (r_vec) {
           const float4 *row = reinterpret_cast<const float4 *>(Rt + (size_t)t * AM);
@@ -1622,43 +1634,50 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
         for (int a = 0; a < AM; ++a) racc[a] = fmaf(bb[k], r4[k][a], racc[a]);
     }
   }
-  // basis sums E_k[c] of this thread's chunk (one wall reading)
+#pragma unroll
+  for (int a = 0; a < AM; ++a) {
+    const float tot = wave_total_lane63(racc[a]);
+    if (lane == kWave - 1) sh.red[wave][a] = tot;
+  }
+  // basis sums E_k[c] of this thread's cells of its chunk (one wall reading)
   float acc[9][NV];
 #pragma unroll
   for (int k = 0; k < 9; ++k)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[k][c] = 0.f;
   const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
-  const int j0 = ch[2 * tid], j1 = ch[2 * tid + 1];
+  const int ck = tid / HALVES, half = tid % HALVES;   // chunk, and which of its cells
+  const int j0 = ch[2 * ck] + half, j1 = ch[2 * ck + 1];
   // the chunk in batches: the next batch's entries load while this batch's
   // Q rows are in flight; positions past the chunk read a valid entry and are
   // masked to zero, so the loads need no branch
-  uint32_t en[kLeafParentBatch];
+  uint32_t en[LPB];
   const int jmax = max(j1 - 1, 0);
 #pragma unroll
-  for (int k = 0; k < kLeafParentBatch; ++k) {
-    const uint32_t v = (uint32_t)lv.sort_cells[min(j0 + k, jmax)];
-    en[k] = j0 + k < j1 ? v : 0u;
+  for (int k = 0; k < LPB; ++k) {
+    const int jk = j0 + k * HALVES;
+    const uint32_t v = (uint32_t)lv.sort_cells[min(jk, jmax)];
+    en[k] = jk < j1 ? v : 0u;
   }
-  for (int j = j0; j < j1; j += kLeafParentBatch) {
-    uint32_t e[kLeafParentBatch];
-    float q[kLeafParentBatch][AM];
+  for (int j = j0; j < j1; j += LPB * HALVES) {
+    uint32_t e[LPB];
+    float q[LPB][AM];
 #pragma unroll
-    for (int k = 0; k < kLeafParentBatch; ++k) {
+    for (int k = 0; k < LPB; ++k) {
       e[k] = en[k];
       load_q_row<AM, QV>(lv, A, (int)(e[k] & kSortCell), q[k]);
     }
 #pragma unroll
-    for (int k = 0; k < kLeafParentBatch; ++k) {
-      const int jn = j + kLeafParentBatch + k;
+    for (int k = 0; k < LPB; ++k) {
+      const int jn = j + (LPB + k) * HALVES;
       const uint32_t v = (uint32_t)lv.sort_cells[min(jn, jmax)];
       en[k] = jn < j1 ? v : 0u;
     }
     // every lane runs the whole batch: a slot past its chunk's end reads the
     // band's first cell with weight zero
 #pragma unroll
-    for (int k = 0; k < kLeafParentBatch; ++k) {
-      const bool in = j + k < j1;
+    for (int k = 0; k < LPB; ++k) {
+      const bool in = j + k * HALVES < j1;
       const int t = in ? (int)(e[k] & kSortCell) : y0 * W;
       const int gy = fdiv(t, W, rW);
       const float *c = X + (gy - y0 + 1) * BW + (t - gy * W) + 1;
@@ -1720,7 +1739,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   // chunk partials -> basis histograms by wall reading.  The chunks of
   // reading w are [pch[w], pch[w+1]); one thread per (w, value) adds their
   // partials (range_sum), kLeafBasisRound values of k per round.
-  const int32_t *pch = ch + 2 * kBlock;
+  const int32_t *pch = ch + 2 * kBlock;   // first chunk of each reading
   constexpr int G = kLeafBasisRound;
   constexpr int GW = G * NV;          // floats per thread and round
   __syncthreads();                    // the band is read no more: part takes its place
@@ -1729,18 +1748,29 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
 #pragma unroll
     for (int g = 0; g < G; ++g)
 #pragma unroll
-      for (int c = 0; c < NV; ++c) part[tid * GW + g * NV + c] = acc[k0 + g][c];
+      for (int c = 0; c < NV; ++c) {
+        // a chunk's two lanes add their sums (even lane's first) on the DPP
+        // network; the even lane stores the chunk's partial
+        if (k0 + g < 9) {
+          float v = acc[k0 + g][c];
+          if (HALVES == 2) {
+            const float o = __shfl_xor(v, 1, kWave);
+            v = half ? o + v : v + o;
+          }
+          if (half == 0) part[ck * GW + g * NV + c] = v;
+        }
+      }
     __syncthreads();
-    for (int i = tid; i < 16 * GW; i += kBlock) {
+    for (int i = tid; i < 16 * GW; i += NT) {
       const int w = i / GW, gi = i - w * GW;
       const int g = gi / NV, c = gi - g * NV;
-      E[((k0 + g) * 16 + w) * NV + c] = range_sum(part + gi, GW, pch[w], pch[w + 1]);
+      if (k0 + g < 9) E[((k0 + g) * 16 + w) * NV + c] = range_sum(part + gi, GW, pch[w], pch[w + 1]);
     }
     __syncthreads();
   }
   // the actions' histograms HQ_a = sum_k T'(a,k) E_k (k in order), plus the
   // goal's own term on its reading
-  for (int i = tid; i < AM * 16 * NV; i += kBlock) {
+  for (int i = tid; i < AM * 16 * NV; i += NT) {
     const int a = i / (16 * NV), wc = i - a * 16 * NV;
     float v = 0.f;
     if (a < A) {
@@ -1750,25 +1780,25 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     }
     HQ[i] = v;
   }
-#pragma unroll
-  for (int a = 0; a < AM; ++a) {
-    const float tot = wave_total_lane63(racc[a]);
-    if (lane == kWave - 1) sh.red[wave][a] = tot;
-  }
   __syncthreads();
-  if (tid < A) sh.rb[tid] = (sh.red[0][tid] + sh.red[1][tid]) + (sh.red[2][tid] + sh.red[3][tid]);
+  if (tid < A) {
+    float r8[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) r8[w] = sh.red[w][tid];
+    sh.rb[tid] = sum_waves<NW>(r8);
+  }
   __syncthreads();
   if (lv.tiles > 1) {
     // band record out; the last band of the parent sums all records in band order
     float *rec = lv.part + ((size_t)p * lv.tiles + band) * RECN;
-    for (int i = tid; i < RECN; i += kBlock) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
+    for (int i = tid; i < RECN; i += NT) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
     wait_mem();
     __syncthreads();
     if (tid == 0) sh.last = (count_arrival(&lv.ctr[p]) == lv.tiles - 1);
     __syncthreads();
     if (!sh.last) return;
     const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
-    for (int i = tid; i < RECN; i += kBlock) {
+    for (int i = tid; i < RECN; i += NT) {
       float sum = 0.f;
       int t0 = 0;
       for (; t0 + 4 <= lv.tiles; t0 += 4) {
@@ -1789,11 +1819,11 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   }
   // observation draws: wavefront w takes actions w, w + 4, ...
   uint32_t *lw = (uint32_t *)X;
-  for (int l = tid; l < L; l += kBlock) lw[l] = lv.lm_wall[l];
+  for (int l = tid; l < L; l += NT) lw[l] = lv.lm_wall[l];
   wait_mem();
   __syncthreads();
   float *lvv = X + L + wave * L;
-  for (int a = wave; a < A; a += kBlock / kWave) {
+  for (int a = wave; a < A; a += NW) {
     for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
@@ -1803,13 +1833,13 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
       hs = sh.rb[a];
       lv.reward[p * A + a] = hs;
     }
-    sample_draws(m, lv, p, a, hs, lw, lvv, X + 5 * L + 16 * wave, &sh.draw[a]);
+    sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 16 * wave, &sh.draw[a]);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   // leaf values (Alg. 5) of every drawn child of every action:
   //   zl = 0: (1/P(z)) sum_w O_w(zw|w) HQ_a[w][c];  zl = l: (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) Q(x_l,c)
-  for (int i = tid; i < A * n * AM; i += kBlock) {
+  for (int i = tid; i < A * n * AM; i += NT) {
     const int a = i / (n * AM), r = (i / AM) - a * n, c = i - (i / AM) * AM;
     float v = 0.f;
     if (c < A && r < sh.draw[a].U) {
@@ -1852,7 +1882,8 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
 }
 
 template <int AM, int QV>
-__global__ __launch_bounds__(kBlock) void k_leaf_parent(DevModel m, LevelArgs lv, TreeArgs tr) {
+__global__ __launch_bounds__(kLeafBlock, 4) void k_leaf_parent(DevModel m, LevelArgs lv,
+                                                                 TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ LeafParentShared sh;
   // With a visiting order, the present parents come first: they are
@@ -1867,7 +1898,7 @@ __global__ __launch_bounds__(kBlock) void k_leaf_parent(DevModel m, LevelArgs lv
   if (!lv.porder && (grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
   const int j = i / lv.tiles, band = i - j * lv.tiles;
   const int p = lv.porder ? lv.porder[j] : j;
-  leaf_parent_item<AM, QV>(m, lv, tr, p, band, smem, sh);
+  leaf_parent_item<AM, QV, kLeafBlock>(m, lv, tr, p, band, smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2138,13 +2169,13 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.part = (float *)(ws + L.leafrec);
       const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
       if (AM == 4 && q_vec)
-        QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+        QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else if (AM == 4)
-        QV_LAUNCH_L(d, (k_leaf_parent<4, 0>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+        QV_LAUNCH_L(d, (k_leaf_parent<4, 0>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else if (q_vec)
-        QV_LAUNCH_L(d, (k_leaf_parent<8, 1>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+        QV_LAUNCH_L(d, (k_leaf_parent<8, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else
-        QV_LAUNCH_L(d, (k_leaf_parent<8, 0>), dim3(nb), dim3(kBlock), lds_lp, st, m, lv, tr);
+        QV_LAUNCH_L(d, (k_leaf_parent<8, 0>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       continue;
     }
     if (small) {
@@ -2268,8 +2299,10 @@ __global__ void k_prep_landmarks_batch(BatchPrep bp) {
 // PHASE 2: the last level of a query with at most 8 actions, per (parent,
 // band) over all actions (k_leaf_parent).  Workgroups take `chunk` items at a time from the
 // queue until it runs dry; every workgroup leaves after one failed take.
+// (phase 2 runs k_leaf_parent's 512-thread form, so a query's results equal
+// those of its single-query plan bit for bit)
 template <int PHASE, int APAD>
-__global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
+__global__ __launch_bounds__(PHASE == 2 ? kLeafBlock : kBlock) void k_level_batch(BatchLevel bl) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
   __shared__ LeafParentShared shl;   // phase 2 only
@@ -2295,7 +2328,8 @@ __global__ __launch_bounds__(kBlock) void k_level_batch(BatchLevel bl) {
           leaf_item<APAD>(bq.m, lv, bq.tr, it, smem, sh);
       } else {
         const int local = i - bl.base[q];
-        leaf_parent_item<APAD, -1>(bq.m, lv, bq.tr, local / lv.tiles, local % lv.tiles, smem, shl);
+        leaf_parent_item<APAD, -1, kLeafBlock>(bq.m, lv, bq.tr, local / lv.tiles, local % lv.tiles,
+                                               smem, shl);
       }
       __syncthreads();
     }
@@ -2350,7 +2384,9 @@ int batch_level_occupancy(int phase, int apad, size_t lds) {
   if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, phase == 2 ? kLeafBlock : kBlock, lds) !=
+      hipSuccess)
+    return 0;
   return nb;
 }
 
@@ -2361,9 +2397,9 @@ hipError_t launch_batch_level(const BatchLevel &bl, int phase, int apad, size_t 
   if (phase == 0) {
     QV_LAUNCH_T(timed, d, (k_level_batch<0, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
   } else if (phase == 2 && apad <= 4) {
-    QV_LAUNCH_T(timed, d, (k_level_batch<2, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
+    QV_LAUNCH_T(timed, d, (k_level_batch<2, 4>), dim3(grid), dim3(kLeafBlock), lds, st, bl);
   } else if (phase == 2) {
-    QV_LAUNCH_T(timed, d, (k_level_batch<2, 8>), dim3(grid), dim3(kBlock), lds, st, bl);
+    QV_LAUNCH_T(timed, d, (k_level_batch<2, 8>), dim3(grid), dim3(kLeafBlock), lds, st, bl);
   } else if (apad <= 4) {
     QV_LAUNCH_T(timed, d, (k_level_batch<1, 4>), dim3(grid), dim3(kBlock), lds, st, bl);
   } else if (apad <= 8) {
