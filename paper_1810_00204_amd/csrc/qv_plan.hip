@@ -1515,7 +1515,7 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
 // ---------------------------------------------------------------------------
 constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
 constexpr int kLeafBlock = 2 * kBlock;   // threads of a k_leaf_parent workgroup
-constexpr int kLeafBasisRound = 3;    // basis sums (values of k) per histogram round
+constexpr int kLeafBasisRound = 5;    // basis sums (values of k) per histogram round (two rounds)
 
 struct LeafParentShared {
   float slip[8 * 9];                    // slip table (rows a >= A zero)
