@@ -30,7 +30,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
-BLOCK = 256   # threads per workgroup of the planning kernels
+BLOCK = 256        # threads per workgroup of the banded planning kernels
+NODE_BLOCK = 512   # k_node (inner levels) and k_leaf_parent workgroups
 
 
 def short_name(full: str) -> str:
@@ -64,10 +65,12 @@ def level_grids(workload: str):
     out = {}
     for d in range(D):
         slots = K ** d
-        out[("k_node", slots * A * BLOCK)] = d
+        out[("k_node", slots * A * NODE_BLOCK)] = d
+        if d == 0:   # level 0 also carries the leaf-band sort workgroups
+            out[("k_node", (slots * A + leaf_tiles) * NODE_BLOCK)] = d
         for fam in ("k_stats", "k_update", "k_leaf"):
             out[(fam, slots * tiles * A * BLOCK)] = d
-    out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * BLOCK)] = D - 1
+    out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * NODE_BLOCK)] = D - 1
     return out
 
 
