@@ -30,6 +30,8 @@ def test_level_grids_of_the_64x64_workload():
     g = rs.level_grids("rect64")
     K, A = prob.A * prob.n, prob.A
     for d in range(prob.D):
-        assert g[("k_node", K ** d * A * rs.BLOCK)] == d
+        assert g[("k_node", K ** d * A * rs.NODE_BLOCK)] == d
+    # level 0 also carries the leaf band's sort workgroup
+    assert g[("k_node", (A + 1) * rs.NODE_BLOCK)] == 0
     # the last level: one workgroup per (parent, band); 64 x 64 is one band
-    assert g[("k_leaf_parent", K ** (prob.D - 1) * rs.BLOCK)] == prob.D - 1
+    assert g[("k_leaf_parent", K ** (prob.D - 1) * rs.NODE_BLOCK)] == prob.D - 1
