@@ -404,7 +404,7 @@ constexpr int kSortBatch = 8;   // cells of a leaf-histogram chunk loaded togeth
 __host__ __device__ inline size_t small_x_floats(int W, int H, int A, int n, int L) {
   size_t x = (size_t)(H + 2) * (W + 2);
   const size_t c[4] = {(size_t)(16 + 1) * kBlock,   // leaf chunk partials, A <= 16
-                       (size_t)A * n + A, (size_t)2 * L + 16, (size_t)16};
+                       (size_t)A * n + A, (size_t)2 * L + 32, (size_t)16};
   for (int i = 0; i < 4; ++i) x = x > c[i] ? x : c[i];
   return x;
 }
@@ -501,23 +501,25 @@ struct DrawOut {
 // The observations z = zw + 16 zl come in blocks of 16 (one block per zl, the
 // wall reading zw inside it).  Block 0 is "no landmark seen": P(zw, 0) from
 // the LDS table p0.  Block l >= 1 is landmark l: O_w(zw | w_l) rho b'(x_l),
-// zero when landmark l sits on a blocked cell (w_l > 15).
-__device__ __forceinline__ void obs_block(int blk, int L, const float (&fl)[4], float lmp,
+// zero when landmark l sits on a blocked cell (w_l > 15).  O_w(zw | w)
+// depends on the misread pattern zw ^ w only: otab (LDS) holds its 16 values.
+// Every lane reads at valid addresses and selects, with no branch.
+__device__ __forceinline__ void obs_block(int blk, int L, const float *otab, float lmp,
                                           const float *p0, const uint32_t *lw,
                                           const float *lvv, float (&v)[16]) {
-  if (blk == 0) {
+  const bool lmk = blk >= 1 && blk <= L;
+  const int li = lmk ? blk - 1 : 0;
+  const uint32_t wl = lw[li];
+  const float ml = lvv[li];
+  const uint32_t w = lmk ? wl : 16u;
+  const float mass = lmk ? ml : 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = p0[i];
-    return;
+  for (int i = 0; i < 16; ++i) {
+    const float o = otab[(uint32_t)i ^ (w & 15u)];
+    const float pl = w > 15u ? 0.f : o * lmp * mass;
+    const float pz = p0[i];
+    v[i] = blk == 0 ? pz : pl;
   }
-  uint32_t w = 16u;
-  float mass = 0.f;
-  if (blk <= L) {
-    w = lw[blk - 1];
-    mass = lvv[blk - 1];
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = w > 15u ? 0.f : wall_lik(fl, (uint32_t)i, w) * lmp * mass;
 }
 
 // Running totals of one page of 64 blocks: lane j holds block 64 g + j and
@@ -525,13 +527,13 @@ __device__ __forceinline__ void obs_block(int blk, int L, const float (&fl)[4], 
 // entry i.  Totals grow in z order: within a lane entry by entry, across lanes
 // in lane order, across pages from `base`, which the call advances to the
 // page's end.  lastpos: the lane's last z of positive mass so far.
-__device__ __forceinline__ void obs_page(int g, int L, const float (&fl)[4], float lmp,
+__device__ __forceinline__ void obs_page(int g, int L, const float *otab, float lmp,
                                          const float *p0, const uint32_t *lw, const float *lvv,
                                          float &base, float (&F)[16], int &lastpos) {
   const int lane = threadIdx.x & (kWave - 1);
   const int blk = g * kWave + lane;
   float v[16];
-  obs_block(blk, L, fl, lmp, p0, lw, lvv, v);
+  obs_block(blk, L, otab, lmp, p0, lw, lvv, v);
   float run = 0.f;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
@@ -559,7 +561,8 @@ __device__ __forceinline__ void obs_page(int g, int L, const float (&fl)[4], flo
 // over all z in ascending order, draws n observations by inverse CDF with
 // Philox uniforms (the first z whose running total exceeds u P), and writes
 // one child record per distinct z (ascending) with its frequency (Alg. 3/4).
-// One full wavefront; out (LDS) optional; p0tab: 16 floats of LDS.
+// One full wavefront; out (LDS) optional; p0tab: 32 floats of LDS (P(zw, no
+// landmark), then the wall-likelihood table).
 __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
                              const uint32_t *lw, const float *lvv, float *p0tab, DrawOut *out) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -572,13 +575,18 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
     fl[j] = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.flip[j])));
   const float lmp = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m.lm_p)));
   const int L = __builtin_amdgcn_readfirstlane(m.L);
+  // O_w(zw | w) by misread pattern zw ^ w, once, into the LDS table otab
+  float *otab = p0tab + 16;
+  if (lane < 16) otab[lane] = wall_lik(fl, (uint32_t)lane, 0u);
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
   // P(zw, no landmark) = sum_w O_w(zw|w) H[w] (landmark cells entered H with
   // their "no landmark" factor already), published in the LDS table p0tab
   float p0 = 0.f;
 #pragma unroll
   for (int w = 0; w < 16; ++w) {
     const float hw = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hs), w));
-    p0 = fmaf(wall_lik(fl, (uint32_t)(lane & 15), (uint32_t)w), hw, p0);
+    p0 = fmaf(otab[(uint32_t)(lane & 15) ^ (uint32_t)w], hw, p0);
   }
   if (lane < 16) p0tab[lane] = p0;
   __builtin_amdgcn_s_waitcnt(0);
@@ -588,7 +596,7 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
   float F[16];
   float base = 0.f;
   int lastpos = -1;
-  for (int g = 0; g < npg; ++g) obs_page(g, L, fl, lmp, p0tab, lw, lvv, base, F, lastpos);
+  for (int g = 0; g < npg; ++g) obs_page(g, L, otab, lmp, p0tab, lw, lvv, base, F, lastpos);
   const float P = base;
   // lane k < n: its uniform from the Philox counter (a*ceil(n/4) + k/4, slot,
   // level, query), word k%4, and its target u P
@@ -611,7 +619,7 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
   float base2 = 0.f;
   int lp2 = -1;
   for (int g = 0; g < npg && found != all; ++g) {
-    if (npg > 1) obs_page(g, L, fl, lmp, p0tab, lw, lvv, base2, F, lp2);
+    if (npg > 1) obs_page(g, L, otab, lmp, p0tab, lw, lvv, base2, F, lp2);
     const bool live = g * kWave + lane <= L;
     for (int k = 0; k < n; ++k) {
       if ((found >> k) & 1u) continue;
@@ -643,7 +651,7 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
       pk = p0tab[zw];
     } else {
       const uint32_t w = lw[zl - 1];
-      pk = w > 15u ? 0.f : wall_lik(fl, (uint32_t)zw, w) * lmp * lvv[zl - 1];
+      pk = w > 15u ? 0.f : otab[(uint32_t)zw ^ (w & 15u)] * lmp * lvv[zl - 1];
     }
   }
   // one child per distinct z in ascending z order, with its frequency: lane k
@@ -1536,7 +1544,7 @@ __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, i
                                                         int NT = kLeafBlock) {
   const int NW = NT / kWave;
   const size_t band = (size_t)(TH + 2) * (W + 2);
-  const size_t lmk = (size_t)(1 + NW) * L + 16 * NW;   // landmark tables, P(zw) tables
+  const size_t lmk = (size_t)(1 + NW) * L + 32 * NW;   // landmark tables, sampler tables
   const size_t part = (size_t)kBlock * kLeafBasisRound * (AM + 1);   // chunk partials, one round
   size_t x = band > lmk ? band : lmk;
   x = x > part ? x : part;
@@ -1575,7 +1583,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     return;
   }
   const int TH = lv.TH, y0 = band * TH, th = min(TH, m.H - y0);
-  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)(1 + NW) * L + 16 * NW;
+  const size_t bandf = (size_t)(TH + 2) * BW, lmkf = (size_t)(1 + NW) * L + 32 * NW;
   const size_t partf = (size_t)kBlock * kLeafBasisRound * NV;
   const size_t xf = bandf > lmkf ? (bandf > partf ? bandf : partf) : (lmkf > partf ? lmkf : partf);
   float *X = smem;             // band, then the chunk partials, then the landmark tables
@@ -1833,7 +1841,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
       hs = sh.rb[a];
       lv.reward[p * A + a] = hs;
     }
-    sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 16 * wave, &sh.draw[a]);
+    sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
