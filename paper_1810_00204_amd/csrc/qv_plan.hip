@@ -2310,7 +2310,7 @@ __global__ void k_prep_landmarks_batch(BatchPrep bp) {
 // (phase 2 runs k_leaf_parent's 512-thread form, so a query's results equal
 // those of its single-query plan bit for bit)
 template <int PHASE, int APAD>
-__global__ __launch_bounds__(PHASE == 2 ? kLeafBlock : kBlock) void k_level_batch(BatchLevel bl) {
+__global__ __launch_bounds__(PHASE == 2 ? kLeafBlock : kBlock, PHASE == 2 && APAD == 4 ? 4 : 1) void k_level_batch(BatchLevel bl) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
   __shared__ LeafParentShared shl;   // phase 2 only
