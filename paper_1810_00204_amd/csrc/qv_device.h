@@ -105,6 +105,27 @@ __device__ __forceinline__ float dpp_add(float v) {
   return v + __int_as_float(s);
 }
 
+// The value of the neighbouring lane (lane ^ 1), on the DPP network.
+__device__ __forceinline__ float dpp_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Sum over each row of 16 lanes, returned to every lane of the row (pairs,
+// quads, half rows, then rows; every lane adds the same operands, so all
+// hold the same bits).
+__device__ __forceinline__ float row16_sum(float v) {
+  v = dpp_add<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xF>(v);   // row_half_mirror
+  v = dpp_add<0x140, 0xF>(v);   // row_mirror
+  return v;
+}
+
+// Sum over aligned groups of TPB = 16, 32 or 64 lanes on the DPP network; the
+// group's total is valid in its last lane.
+template <int TPB>
+__device__ __forceinline__ float group_sum(float v);
+
 // Sum over the 64 lanes in a fixed order; the total lands in lane 63
 // (pairs, quads, half rows, rows, then rows broadcast into rows 1/3 and 2/3).
 __device__ __forceinline__ float wave_total_lane63(float v) {
@@ -114,6 +135,15 @@ __device__ __forceinline__ float wave_total_lane63(float v) {
   v = dpp_add<0x140, 0xF>(v);   // row_mirror
   v = dpp_add<0x142, 0xA>(v);   // row_bcast:15
   v = dpp_add<0x143, 0xC>(v);   // row_bcast:31
+  return v;
+}
+
+template <int TPB>
+__device__ __forceinline__ float group_sum(float v) {
+  static_assert(TPB == 16 || TPB == 32 || TPB == 64, "groups of 16, 32 or 64 lanes");
+  if constexpr (TPB == 64) return wave_total_lane63(v);
+  v = row16_sum(v);
+  if constexpr (TPB == 32) v = dpp_add<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
   return v;
 }
 

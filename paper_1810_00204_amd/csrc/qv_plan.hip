@@ -432,7 +432,9 @@ __device__ __forceinline__ void load_q_row(const LevelArgs &lv, int A, int t, fl
 }
 
 // Sum of x[k * stride] over lo <= k < hi in a fixed order: eight running
-// sums over k - lo mod 8, then added pairwise.
+// sums over k - lo mod 8, then added pairwise.  The last partial group loads
+// all eight slots (x[0] in place of those past hi) and masks them, so its
+// loads go out together.
 __device__ __forceinline__ float range_sum(const float *x, int stride, int lo, int hi) {
   float s[8];
 #pragma unroll
@@ -441,9 +443,11 @@ __device__ __forceinline__ float range_sum(const float *x, int stride, int lo, i
   for (; k + 8 <= hi; k += 8)
 #pragma unroll
     for (int u = 0; u < 8; ++u) s[u] += x[(k + u) * stride];
+  float t[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u)
-    if (k + u < hi) s[u] += x[(k + u) * stride];
+  for (int u = 0; u < 8; ++u) t[u] = x[(k + u < hi ? k + u : 0) * stride];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) s[u] += (k + u < hi) ? t[u] : 0.f;
   return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
@@ -902,9 +906,8 @@ __device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, floa
     float s = 0.f;
 #pragma unroll
     for (int i = 0; i < 16; ++i) s += hb[i];
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-    if ((tid & 15) == 0) st_coherent(part + (tid >> 4), s);
+    s = group_sum<16>(s);
+    if ((tid & 15) == 15) st_coherent(part + (tid >> 4), s);
     if (tid == 0) st_coherent(part + 16, (red[0] + red[1]) + (red[2] + red[3]));
   }
   // the last band of this Q-node to finish draws its observations
@@ -1386,9 +1389,8 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
     float s = 0.f;
 #pragma unroll
     for (int i = 0; i < 16; ++i) s += hb[i];
-#pragma unroll
-    for (int o = TPB / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, TPB);
-    if (tid % TPB == 0) s_H[tid / TPB] = s;
+    s = group_sum<TPB>(s);
+    if (tid % TPB == TPB - 1) s_H[tid / TPB] = s;
     if (tid == 0) s_H[16] = sum_waves<NB / kWave>(s_red);
     __syncthreads();
   }
@@ -1524,6 +1526,9 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
 constexpr int kLeafParentBatch = 2;   // sorted cells whose loads go out together
 constexpr int kLeafBlock = 2 * kBlock;   // threads of a k_leaf_parent workgroup
 constexpr int kLeafBasisRound = 5;    // basis sums (values of k) per histogram round (two rounds)
+constexpr int kLeafPiece = 16;        // chunks per piece of a wall reading's chunk range
+constexpr int kLeafPieces = 32;       // pieces at most: kBlock / kLeafPiece + 15
+static_assert(kBlock / kLeafPiece + 15 <= kLeafPieces, "piece table too small");
 
 struct LeafParentShared {
   float slip[8 * 9];                    // slip table (rows a >= A zero)
@@ -1535,11 +1540,14 @@ struct LeafParentShared {
   float goal[8 * 9];                    // [a][c] lambda b'_a Q(goal, c) of the goal cell
   int goal_w;                           // the goal's wall reading, or -1 (not in this band)
   int last;
+  int pc_lo[kLeafPieces], pc_hi[kLeafPieces];   // chunk range of each piece
+  int pfirst[17];                              // first piece of each wall reading
 };
 
 // Floats of dynamic LDS: one region that holds in turn the band, the chunk
-// partials and the landmark tables; then the basis histograms and the
-// actions' histograms.
+// partials and the landmark tables; then one that holds the predicted masses
+// of the landmark cells during the cell pass and afterwards the basis
+// histograms, the actions' histograms and the piece sums of one round.
 __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, int AM,
                                                         int NT = kLeafBlock) {
   const int NW = NT / kWave;
@@ -1548,7 +1556,10 @@ __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, i
   const size_t part = (size_t)kBlock * kLeafBasisRound * (AM + 1);   // chunk partials, one round
   size_t x = band > lmk ? band : lmk;
   x = x > part ? x : part;
-  return x + (size_t)9 * 16 * (AM + 1) + (size_t)AM * 16 * (AM + 1);
+  const size_t hist = (size_t)9 * 16 * (AM + 1) + (size_t)AM * 16 * (AM + 1) +
+                     (size_t)kLeafPieces * kLeafBasisRound * (AM + 1);
+  const size_t lmt = (size_t)AM * L;
+  return x + (hist > lmt ? hist : lmt);
 }
 
 // QV: how Q rows are read (load_q_row).  AM: Q columns padded to 4 or 8.
@@ -1590,9 +1601,13 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   float *part = X;             // [kBlock][round values], later the backup scratch
   float *E = smem + xf;        // [9][16][NV] basis histograms
   float *HQ = E + 9 * 16 * NV;   // [AM][16][NV]
+  float *PP = HQ + AM * 16 * NV;   // [piece][round values]
+  float *LT = E;                   // [AM][L] b'_a of the landmark cells, during the cell pass
   const float *b = lv.pbel + (size_t)p * S;
   if (tid < AM * 9) sh.slip[tid] = tid < A * 9 ? m.slip[tid] : 0.f;
   if (tid == 0) sh.goal_w = -1;
+  // landmarks outside this band keep the mark -1 (predicted masses are >= 0)
+  for (int i = tid; i < AM * L; i += NT) LT[i] = -1.f;
   load_band<24 * kBlock / NT, NT>(m, lv.sig, b, y0, th, X, BW, lv.d == 0);
   __syncthreads();
   const float rho = m.lm_p;
@@ -1656,30 +1671,60 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
   const int ck = tid / HALVES, half = tid % HALVES;   // chunk, and which of its cells
   const int j0 = ch[2 * ck] + half, j1 = ch[2 * ck + 1];
-  // the chunk in batches: the next batch's entries load while this batch's
-  // Q rows are in flight; positions past the chunk read a valid entry and are
-  // masked to zero, so the loads need no branch
-  uint32_t en[LPB];
+  if (wave == NW - 1 && lane < 16) {
+    // reading w's chunks [pch[w], pch[w+1]) cut into pieces of at most
+    // kLeafPiece chunks; pieces are numbered in reading order
+    const int32_t *pch = ch + 2 * kBlock;
+    const int c0 = pch[lane], c1 = pch[lane + 1];
+    const int np = (c1 - c0 + kLeafPiece - 1) / kLeafPiece;
+    int pf = np;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      const int t = __shfl_up(pf, o, 16);
+      if (lane >= o) pf += t;
+    }
+    pf -= np;
+    sh.pfirst[lane] = pf;
+    if (lane == 15) sh.pfirst[16] = pf + np;
+    for (int j = 0; j < np; ++j) {
+      sh.pc_lo[pf + j] = c0 + j * kLeafPiece;
+      sh.pc_hi[pf + j] = min(c0 + (j + 1) * kLeafPiece, c1);
+    }
+  }
+  // the chunk in batches, software-pipelined: while a batch is computed, the
+  // next batch's Q rows and the entries of the one after are in flight;
+  // positions past the chunk read a valid entry and are masked to zero, so
+  // the loads need no branch
   const int jmax = max(j1 - 1, 0);
+  constexpr int STEP = LPB * HALVES;
+  uint32_t en[LPB], en2[LPB];
+  float qn[LPB][AM];
 #pragma unroll
   for (int k = 0; k < LPB; ++k) {
-    const int jk = j0 + k * HALVES;
+    const int jk = j0 + k * HALVES, jk2 = jk + STEP;
     const uint32_t v = (uint32_t)lv.sort_cells[min(jk, jmax)];
+    const uint32_t v2 = (uint32_t)lv.sort_cells[min(jk2, jmax)];
     en[k] = jk < j1 ? v : 0u;
+    en2[k] = jk2 < j1 ? v2 : 0u;
   }
-  for (int j = j0; j < j1; j += LPB * HALVES) {
+#pragma unroll
+  for (int k = 0; k < LPB; ++k) load_q_row<AM, QV>(lv, A, (int)(en[k] & kSortCell), qn[k]);
+  for (int j = j0; j < j1; j += STEP) {
     uint32_t e[LPB];
     float q[LPB][AM];
 #pragma unroll
     for (int k = 0; k < LPB; ++k) {
       e[k] = en[k];
-      load_q_row<AM, QV>(lv, A, (int)(e[k] & kSortCell), q[k]);
+#pragma unroll
+      for (int c = 0; c < AM; ++c) q[k][c] = qn[k][c];
+      en[k] = en2[k];
+      load_q_row<AM, QV>(lv, A, (int)(en[k] & kSortCell), qn[k]);
     }
 #pragma unroll
     for (int k = 0; k < LPB; ++k) {
-      const int jn = j + (LPB + k) * HALVES;
+      const int jn = j + 2 * STEP + k * HALVES;
       const uint32_t v = (uint32_t)lv.sort_cells[min(jn, jmax)];
-      en[k] = jn < j1 ? v : 0u;
+      en2[k] = jn < j1 ? v : 0u;
     }
     // every lane runs the whole batch: a slot past its chunk's end reads the
     // band's first cell with weight zero
@@ -1738,41 +1783,63 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
 #pragma unroll
             for (int cc = 0; cc < AM; ++cc) sh.goal[a * NV + cc] = gv * q[k][cc];
           }
-          if (lmk) st_coherent(lv.lmv + ((size_t)p * A + a) * L + lid - 1, v);
+          if (lmk) LT[a * L + lid - 1] = v;
         }
         if (goal) sh.goal_w = (int)sig_wall(sg);
       }
     }
   }
-  // chunk partials -> basis histograms by wall reading.  The chunks of
-  // reading w are [pch[w], pch[w+1]); one thread per (w, value) adds their
-  // partials (range_sum), kLeafBasisRound values of k per round.
-  const int32_t *pch = ch + 2 * kBlock;   // first chunk of each reading
+  // chunk partials -> basis histograms by wall reading, kLeafBasisRound
+  // values of k per round: one thread per (piece, value) adds the piece's
+  // chunk partials in chunk order, then one thread per (reading, value) adds
+  // the reading's piece sums in piece order (range_sum)
   constexpr int G = kLeafBasisRound;
   constexpr int GW = G * NV;          // floats per thread and round
   __syncthreads();                    // the band is read no more: part takes its place
+  // the landmark cells' predicted masses go out to lmv (the sampler of this
+  // or, with several bands, the last band reads them); kept in LDS during the
+  // cell pass, so no store waits there
+  for (int i = tid; i < A * L; i += NT) {
+    const int a = i / L, l = i - a * L;
+    const float v = LT[a * L + l];
+    if (v >= 0.f) st_coherent(lv.lmv + ((size_t)p * A + a) * L + l, v);
+  }
 #pragma unroll
   for (int k0 = 0; k0 < 9; k0 += G) {
+    if constexpr (HALVES == 2) {
+      // a chunk's two lanes add their sums on the DPP network (both get the
+      // same bits: addition commutes), then store alternate values
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-      for (int c = 0; c < NV; ++c) {
-        // a chunk's two lanes add their sums (even lane's first) on the DPP
-        // network; the even lane stores the chunk's partial
-        if (k0 + g < 9) {
-          float v = acc[k0 + g][c];
-          if (HALVES == 2) {
-            const float o = __shfl_xor(v, 1, kWave);
-            v = half ? o + v : v + o;
+      for (int gi = 0; gi < GW; gi += 2) {
+        const int g0 = gi / NV, c0 = gi % NV, g1 = (gi + 1) / NV, c1 = (gi + 1) % NV;
+        if (k0 + g0 < 9) {
+          float v0 = acc[k0 + g0][c0];
+          v0 += dpp_xor1(v0);
+          if (gi + 1 < GW && k0 + g1 < 9) {
+            float v1 = acc[k0 + g1][c1];
+            v1 += dpp_xor1(v1);
+            part[ck * GW + gi + half] = half ? v1 : v0;
+          } else {
+            part[ck * GW + gi] = v0;   // both lanes write the same value
           }
-          if (half == 0) part[ck * GW + g * NV + c] = v;
         }
       }
+    } else {
+#pragma unroll
+      for (int gi = 0; gi < GW; ++gi)
+        if (k0 + gi / NV < 9) part[ck * GW + gi] = acc[k0 + gi / NV][gi % NV];
+    }
+    __syncthreads();
+    const int npc = sh.pfirst[16];
+    for (int i = tid; i < npc * GW; i += NT) {
+      const int pc = i / GW, gi = i - pc * GW;
+      if (k0 + gi / NV < 9) PP[i] = range_sum(part + gi, GW, sh.pc_lo[pc], sh.pc_hi[pc]);
+    }
     __syncthreads();
     for (int i = tid; i < 16 * GW; i += NT) {
       const int w = i / GW, gi = i - w * GW;
       const int g = gi / NV, c = gi - g * NV;
-      if (k0 + g < 9) E[((k0 + g) * 16 + w) * NV + c] = range_sum(part + gi, GW, pch[w], pch[w + 1]);
+      if (k0 + g < 9) E[((k0 + g) * 16 + w) * NV + c] = range_sum(PP + gi, GW, sh.pfirst[w], sh.pfirst[w + 1]);
     }
     __syncthreads();
   }
