@@ -142,7 +142,7 @@ bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L,
   L->leaf_rows = std::max(1, std::min(m->H, 8192 / m->W));
   L->leaf_tiles = (m->H + L->leaf_rows - 1) / L->leaf_rows;
   L->sort_cells = take((size_t)S * 4);
-  L->sort_chunk = take((size_t)L->leaf_tiles * (2 * kBlock + 17) * 4);
+  L->sort_chunk = take((size_t)L->leaf_tiles * kSortChunkInts * 4);
   if (D > 0 && A <= 8 && L->leaf_tiles > 1) {
     // band records sized for histograms of 8 actions, the widest a kernel
     // uses for A <= 8 (a batch may pad a 4-action query to 8)

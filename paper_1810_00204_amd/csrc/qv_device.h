@@ -10,6 +10,9 @@ namespace qv {
 
 constexpr int kBlock = 256;   // threads per workgroup for the tiled kernels
 constexpr int kWave = 64;     // CDNA wavefront width
+// ints per sorted leaf band: kBlock chunk ranges, the first chunk of each
+// wall reading (17), the first sorted position of each wall reading (17)
+constexpr int kSortChunkInts = 2 * kBlock + 34;
 
 // Model as passed to kernels by value (small tables live in the kernarg
 // segment, so uniform indexing lands them in scalar registers).

@@ -28,7 +28,7 @@ struct PlanPtrs {
 struct PlanLayout {
   qv_tree_layout pub;
   size_t sig, staytab, part, lmv, leafpart, err, counters, lm_wall;
-  size_t sort_cells, sort_chunk;   // [S] and [leaf_tiles][2*kBlock + 17] int32
+  size_t sort_cells, sort_chunk;   // [S] and [leaf_tiles][kSortChunkInts] int32
   int leaf_rows, leaf_tiles;       // bands of the per-parent leaf level
   size_t leafrec;                  // [slots_{D-1}][leaf_tiles][record] band records
   size_t part_slots;      // max slots of a non-leaf level

@@ -156,8 +156,8 @@ constexpr uint32_t kSortLandmark = 1u << 31;
 //   chunk[2k], chunk[2k+1]      first and one-past-last position of chunk k
 //                               (equal for unused k)
 //   chunk[2 kBlock + w]         first chunk of reading w, w = 0..16
+//   chunk[2 kBlock + 17 + w]    first position of reading w, w = 0..16
 // One workgroup per band; thread i first counts cells c_lo + [i R, (i+1) R).
-constexpr int kSortChunkInts = 2 * kBlock + 17;
 constexpr int kSortMaxCells = 16384;   // cells of one sorted band (leaf bands <= 8192)
 // per-cell summary kept in LDS while sorting: bits 0..7 move pattern, 8..11
 // wall reading, 12 free, 13 goal, 14 landmark
@@ -273,7 +273,10 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     chunk[2 * tid] = c_lo + j0;
     chunk[2 * tid + 1] = c_lo + j1;
   }
-  if (tid <= 16) chunk[2 * kBlock + tid] = s_pchunk[tid];
+  if (tid <= 16) {
+    chunk[2 * kBlock + tid] = s_pchunk[tid];
+    chunk[2 * kBlock + 17 + tid] = c_lo + s_start[tid];
+  }
 }
 
 // band = blockIdx.x: cells [band * TC, min(S, (band + 1) * TC))
@@ -1669,8 +1672,24 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[k][c] = 0.f;
   const int32_t *ch = lv.sort_chunk + (size_t)band * kSortChunkInts;
-  const int ck = tid / HALVES, half = tid % HALVES;   // chunk, and which of its cells
-  const int j0 = ch[2 * ck] + half, j1 = ch[2 * ck + 1];
+  // chunk ck belongs to the reading w with pch[w] <= ck < pch[w+1]; the
+  // HALVES (pch[w+1] - pch[w]) lanes of reading w take its sorted positions
+  // [rst[w], rst[w+1]) in turn, so a wavefront's loads at one step fall on
+  // consecutive positions (neighbouring cells of one reading)
+  const int ck = tid / HALVES, half = tid % HALVES;
+  const int32_t *pchk = ch + 2 * kBlock, *rst = pchk + 17;
+  int lo = 0, hi = 0, cfirst = 0, nch = 1;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int a0 = pchk[v], a1 = pchk[v + 1], r0 = rst[v], r1 = rst[v + 1];
+    const bool mine = (ck >= a0) & (ck < a1);
+    lo = mine ? r0 : lo;
+    hi = mine ? r1 : hi;
+    cfirst = mine ? a0 : cfirst;
+    nch = mine ? a1 - a0 : nch;
+  }
+  const int sd = HALVES * nch;   // between one lane's positions
+  const int j0 = lo + (ck - cfirst) * HALVES + half, j1 = hi;
   if (wave == NW - 1 && lane < 16) {
     // reading w's chunks [pch[w], pch[w+1]) cut into pieces of at most
     // kLeafPiece chunks; pieces are numbered in reading order
@@ -1691,17 +1710,17 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
       sh.pc_hi[pf + j] = min(c0 + (j + 1) * kLeafPiece, c1);
     }
   }
-  // the chunk in batches, software-pipelined: while a batch is computed, the
-  // next batch's Q rows and the entries of the one after are in flight;
-  // positions past the chunk read a valid entry and are masked to zero, so
-  // the loads need no branch
+  // the lane's positions in batches, software-pipelined: while a batch is
+  // computed, the next batch's Q rows and the entries of the one after are
+  // in flight; positions past the reading read a valid entry and are masked
+  // to zero, so the loads need no branch
   const int jmax = max(j1 - 1, 0);
-  constexpr int STEP = LPB * HALVES;
+  const int STEP = LPB * sd;
   uint32_t en[LPB], en2[LPB];
   float qn[LPB][AM];
 #pragma unroll
   for (int k = 0; k < LPB; ++k) {
-    const int jk = j0 + k * HALVES, jk2 = jk + STEP;
+    const int jk = j0 + k * sd, jk2 = jk + STEP;
     const uint32_t v = (uint32_t)lv.sort_cells[min(jk, jmax)];
     const uint32_t v2 = (uint32_t)lv.sort_cells[min(jk2, jmax)];
     en[k] = jk < j1 ? v : 0u;
@@ -1722,7 +1741,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     }
 #pragma unroll
     for (int k = 0; k < LPB; ++k) {
-      const int jn = j + 2 * STEP + k * HALVES;
+      const int jn = j + 2 * STEP + k * sd;
       const uint32_t v = (uint32_t)lv.sort_cells[min(jn, jmax)];
       en2[k] = jn < j1 ? v : 0u;
     }
@@ -1730,7 +1749,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     // band's first cell with weight zero
 #pragma unroll
     for (int k = 0; k < LPB; ++k) {
-      const bool in = j + k * HALVES < j1;
+      const bool in = j + k * sd < j1;
       const int t = in ? (int)(e[k] & kSortCell) : y0 * W;
       const int gy = fdiv(t, W, rW);
       const float *c = X + (gy - y0 + 1) * BW + (t - gy * W) + 1;
