@@ -1442,8 +1442,10 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
 #pragma unroll
         for (int j = 0; j < NBATCH; ++j) {
           const int t = t0 + j * NB;
+          // written through (the next level reads it from other XCDs), so
+          // the end of the launch has fewer dirty L2 lines to write back
           if (t < S)
-            out[t] = tab[sig_wall(sg[j])] * lm_lik(rho, zl, sig_lm(sg[j])) * bpl[t];
+            st_coherent(out + t, tab[sig_wall(sg[j])] * lm_lik(rho, zl, sig_lm(sg[j])) * bpl[t]);
         }
       }
     }
