@@ -32,18 +32,28 @@ namespace qv {
 // Signature of cell s without its landmark id: the 8-neighbour move pattern
 // (bit set = the move is possible), free and goal bits, and the true wall
 // reading in bits 10..13.
+// The nine occupancy reads go out together: an off-grid neighbour reads the
+// cell itself and is masked (bitwise conditions, so no branch guards a load).
 __device__ __forceinline__ uint32_t cell_bits(const DevModel &m, int s) {
   const int y = s / m.W, x0 = s - y * m.W;
+  uint32_t o[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int ny = y + k / 3 - 1, nx = x0 + k % 3 - 1;
+    const uint32_t in = (uint32_t)(ny >= 0) & (uint32_t)(ny < m.H) & (uint32_t)(nx >= 0) &
+                        (uint32_t)(nx < m.W);
+    const uint32_t oc = m.occ[in ? ny * m.W + nx : s];
+    o[k] = in & (uint32_t)(oc == 0);   // 1: the move to neighbour k is possible
+  }
   uint32_t v = 0;
   int bit = 0;
+#pragma unroll
   for (int k = 0; k < 9; ++k) {
     if (k == 4) continue;
-    const int ny = y + k / 3 - 1, nx = x0 + k % 3 - 1;
-    const bool ok = ny >= 0 && ny < m.H && nx >= 0 && nx < m.W && m.occ[ny * m.W + nx] == 0;
-    if (ok) v |= 1u << bit;
+    v |= o[k] << bit;
     ++bit;
   }
-  if (m.occ[s] == 0) v |= kSigFree;
+  if (o[4]) v |= kSigFree;
   if (s == m.goal) v |= kSigGoal;
   // wall bits up/left/right/down are neighbours k = 1, 3, 5, 7 -> bits 1, 3, 4, 6
   const uint32_t w = (((v >> 1) & 1u) ^ 1u) | ((((v >> 3) & 1u) ^ 1u) << 1) |
@@ -51,10 +61,26 @@ __device__ __forceinline__ uint32_t cell_bits(const DevModel &m, int s) {
   return v | (w << 10);
 }
 
+// stay(a, pattern) from the slip row of a: T'(a,4) plus the slip mass of
+// every move whose target is blocked or off-grid (bit clear in the
+// 8-neighbour pattern).
+__device__ __forceinline__ float stay_value(const float (&sl)[9], int pat) {
+  float st = sl[4];
+  int bit = 0;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    if (k == 4) continue;
+    st += ((pat >> bit) & 1) ? 0.f : sl[k];
+    ++bit;
+  }
+  return st;
+}
+
 // Thread g of the prep pass of one query: clears the error word, writes the
-// root records and the counters, the stay table and the signature of cell g.
-__device__ void prep_sig_one(const DevModel &m, uint32_t *sig, float *staytab, int32_t *err,
-                             const PrepExtra &x, long long g) {
+// root records and the counters and the stay table (everything but the
+// signatures).
+__device__ void prep_misc_one(const DevModel &m, float *staytab, int32_t *err,
+                              const PrepExtra &x, long long g) {
   const int s = (int)g;
   if (g == 0) {
     err[0] = 0;
@@ -67,20 +93,18 @@ __device__ void prep_sig_one(const DevModel &m, uint32_t *sig, float *staytab, i
   }
   if (g < x.nzero) x.zero[g] = 0;
   if (g < m.A * 256) {
-    // stay(a, pattern): T'(a,4) plus the slip mass of every move whose
-    // target is blocked or off-grid (bit clear in the 8-neighbour pattern)
-    const int a = s >> 8, pat = s & 255;
-    float st = m.slip[a * 9 + 4];
-    int bit = 0;
-    for (int k = 0; k < 9; ++k) {
-      if (k == 4) continue;
-      if (!((pat >> bit) & 1)) st += m.slip[a * 9 + k];
-      ++bit;
-    }
-    staytab[s] = st;
+    float sl[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sl[k] = m.slip[(s >> 8) * 9 + k];
+    staytab[s] = stay_value(sl, s & 255);
   }
-  if (g >= m.S) return;
-  sig[s] = cell_bits(m, s);
+}
+
+// As prep_misc_one, plus the signature of cell g (without landmark ids).
+__device__ void prep_sig_one(const DevModel &m, uint32_t *sig, float *staytab, int32_t *err,
+                             const PrepExtra &x, long long g) {
+  prep_misc_one(m, staytab, err, x, g);
+  if (g < m.S) sig[g] = cell_bits(m, (int)g);
 }
 
 __global__ void k_prep_sig(DevModel m, uint32_t *sig, float *staytab, int32_t *err,
@@ -116,25 +140,62 @@ __global__ void k_prep_landmarks(DevModel m, uint32_t *sig, int32_t *err, uint32
 // The prep pass of a plan in one launch: as k_prep_sig, with each cell's
 // landmark id found by a scan of the landmark list (staged in LDS; the
 // lowest id wins if two share a cell) instead of a second launch that
-// inserts the ids, and thread l < L writing landmark l's wall reading.
-// Landmark errors are not flagged here (a plan does not read the error word).
+// inserts the ids.  Every landmark on a cell takes the cell's wall reading;
+// a landmark off the grid reads all ones.  The occupancy loads of a cell's
+// bits go out together with the landmark list's, so the pass costs one
+// round trip to memory.  Landmark errors are not flagged here (a plan does
+// not read the error word).
 __global__ __launch_bounds__(256) void k_prep_plan(DevModel m, uint32_t *sig, float *staytab,
                                                    int32_t *err, PrepExtra x) {
+  static_assert(QV_MAX_LANDMARKS <= 2 * 256, "two landmarks per thread");
   __shared__ int s_lm[QV_MAX_LANDMARKS];
-  for (int l = threadIdx.x; l < m.L; l += blockDim.x) s_lm[l] = m.lm_cell[l];
-  __syncthreads();
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = (int)g;
+  // every load first, at valid addresses (masked afterwards), so that one
+  // wait covers them all
+  int lmc[2] = {0, 0};
+  if (m.L > 0) {   // lm_cell may be null without landmarks
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int l = threadIdx.x + k * 256;
+      lmc[k] = m.lm_cell[l < m.L ? l : 0];
+    }
+  }
+  const int sc = g < m.S ? s : 0;
+  const uint32_t v = cell_bits(m, sc);
+  const int sa = g < m.A * 256 ? s >> 8 : 0;
+  float sl[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sl[k] = m.slip[sa * 9 + k];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    if (threadIdx.x + k * 256 < m.L) s_lm[threadIdx.x + k * 256] = lmc[k];
+  if (g < m.S) sig[s] = v;   // landmark ids are added below
+  if (g < m.A * 256) staytab[s] = stay_value(sl, s & 255);
+  if (g == 0) {
+    err[0] = 0;
+    if (x.valid) {
+      x.valid[0] = 1;
+      x.z[0] = -1;
+      x.count[0] = 0;
+      x.pz[0] = 0.f;
+    }
+  }
+  if (g < x.nzero) x.zero[g] = 0;
+  __syncthreads();
+  if (g < m.S) {
+    uint32_t id = 0;
+    for (int l = m.L - 1; l >= 0; --l)
+      if (s_lm[l] == s) {
+        id = (uint32_t)(l + 1);
+        x.lm_wall[l] = sig_wall(v);
+      }
+    if (id) sig[s] = v | (id << 14);
+  }
   if (g < m.L) {
     const int c = s_lm[g];
-    x.lm_wall[g] = (c >= 0 && c < m.S) ? sig_wall(cell_bits(m, c)) : 0xFFFFFFFFu;
+    if (c < 0 || c >= m.S) x.lm_wall[g] = 0xFFFFFFFFu;
   }
-  prep_sig_one(m, sig, staytab, err, x, g);
-  if (g >= m.S) return;
-  const int s = (int)g;
-  uint32_t id = 0;
-  for (int l = m.L - 1; l >= 0; --l)
-    if (s_lm[l] == s) id = (uint32_t)(l + 1);
-  if (id) sig[s] |= id << 14;
 }
 
 // Sorted cell entries: bits 0..21 the cell index (S <= 2048 * 2048 = 2^22),
