@@ -964,12 +964,16 @@ __device__ void stats_item(const DevModel &m, const LevelArgs &lv, Item it, floa
   if ((tid & (kWave - 1)) == 0) red[tid / kWave] = racc;
   __syncthreads();
   float *part = lv.part + (((size_t)p * A + a) * lv.tiles + tile) * 17;
-  // bin = tid/16 sums 16 consecutive per-thread entries, then 16 lanes combine
+  // bin = tid/16: lane k of the bin's 16 adds entries k, k + 16, ... (the 16
+  // lanes read consecutive words; the four bins of a wavefront start their
+  // walks one step apart, so no two lanes share an LDS bank), then the 16
+  // lanes combine
   {
-    const float *hb = hist + (tid >> 4) * kBlock + (tid & 15) * 16;
+    const int k = tid & 15, rot = (tid >> 4) & 3;
+    const float *hb = hist + (tid >> 4) * kBlock;
     float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) s += hb[i];
+    for (int i = 0; i < 16; ++i) s += hb[k + 16 * ((i + rot) & 15)];
     s = group_sum<16>(s);
     if ((tid & 15) == 15) st_coherent(part + (tid >> 4), s);
     if (tid == 0) st_coherent(part + 16, (red[0] + red[1]) + (red[2] + red[3]));
@@ -1446,13 +1450,16 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
     __syncthreads();
   }
   if (!LEAF) {
-    // the 16 bins: thread i adds 16 threads' values of bin i / TPB, then TPB
+    // the 16 bins: lane k of bin tid / TPB adds entries k, k + TPB, ... (the
+    // lanes read consecutive words; the bins sharing a wavefront start their
+    // walks one step apart, so no two lanes share an LDS bank), then TPB
     // lanes combine them
     constexpr int TPB = NB / 16;
-    const float *hb = hist + (tid / TPB) * NB + (tid % TPB) * 16;
+    const int k = tid % TPB, rot = (tid / TPB) % (kWave / TPB);
+    const float *hb = hist + (tid / TPB) * NB;
     float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) s += hb[i];
+    for (int i = 0; i < 16; ++i) s += hb[k + TPB * ((i + rot) & 15)];
     s = group_sum<TPB>(s);
     if (tid % TPB == TPB - 1) s_H[tid / TPB] = s;
     if (tid == 0) s_H[16] = sum_waves<NB / kWave>(s_red);
