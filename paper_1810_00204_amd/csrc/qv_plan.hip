@@ -530,6 +530,9 @@ __device__ __forceinline__ void st_coherent(float *p, float v) {
 }
 // wait until all memory operations this thread issued have completed
 __device__ __forceinline__ void wait_mem() { __builtin_amdgcn_s_waitcnt(0); }
+// wait until this wavefront's LDS operations have completed (lgkmcnt(0); the
+// vector memory and export counters at their maxima, so no store is waited for)
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 __device__ __forceinline__ int count_arrival(int32_t *ctr) {
   return __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -646,7 +649,7 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
   // O_w(zw | w) by misread pattern zw ^ w, once, into the LDS table otab
   float *otab = p0tab + 16;
   if (lane < 16) otab[lane] = wall_lik(fl, (uint32_t)lane, 0u);
-  __builtin_amdgcn_s_waitcnt(0);
+  wait_lds();
   __builtin_amdgcn_wave_barrier();
   // P(zw, no landmark) = sum_w O_w(zw|w) H[w] (landmark cells entered H with
   // their "no landmark" factor already), published in the LDS table p0tab
@@ -657,7 +660,7 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
     p0 = fmaf(otab[(uint32_t)(lane & 15) ^ (uint32_t)w], hw, p0);
   }
   if (lane < 16) p0tab[lane] = p0;
-  __builtin_amdgcn_s_waitcnt(0);
+  wait_lds();
   __builtin_amdgcn_wave_barrier();
   const int npg = (L + 1 + kWave - 1) / kWave;
   // the total P(z|b,a); a single page keeps its running totals for the search
@@ -813,7 +816,6 @@ __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int 
         __builtin_amdgcn_readlane(__float_as_int(wave_total_lane63(v[k])), 63));
     if (lane == k) hs = tot;
   }
-  if (lane == 16) lv.reward[idx] = hs;
   uint32_t *lw = (uint32_t *)lds;
   float *lvv = lds + m.L;
   for (int l = lane; l < m.L; l += kWave) {
@@ -823,6 +825,8 @@ __device__ void sample_qnode(const DevModel &m, const LevelArgs &lv, int p, int 
   __builtin_amdgcn_s_waitcnt(0);
   __builtin_amdgcn_wave_barrier();
   const int U = sample_draws(m, lv, p, a, hs, lw, lvv, lds + 2 * m.L, nullptr);
+  // (after the draws: the wait before them need not cover this store)
+  if (lane == 16) lv.reward[idx] = hs;
   if (lv.slot_list) {
     ListPos lp = {0, 0};
     if (lane == 0) lp = list_take(lv, U);
@@ -1467,7 +1471,6 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
   }
   // observation draws by wave 0; X now takes the landmark terms
   if (tid < kWave) {
-    if (tid == 16) lv.reward[p * A + a] = s_H[16];
     uint32_t *lw = (uint32_t *)X;
     float *lvv = X + m.L;
     for (int l = tid; l < m.L; l += kWave) {
@@ -1478,6 +1481,8 @@ __global__ __launch_bounds__(LEAF ? kBlock : kNodeBlock) void k_node(DevModel m,
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     sample_draws(m, lv, p, a, tid < 17 ? s_H[tid] : 0.f, lw, lvv, X + 2 * m.L, &s_draw);
+    // (after the draws: the wait before them need not cover this store)
+    if (tid == 16) lv.reward[p * A + a] = s_H[16];
   }
   __syncthreads();
   const int U = s_draw.U;
@@ -1993,11 +1998,10 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     __builtin_amdgcn_wave_barrier();
     float hs = 0.f;
     if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
-    if (lane == 16) {
-      hs = sh.rb[a];
-      lv.reward[p * A + a] = hs;
-    }
+    if (lane == 16) hs = sh.rb[a];
     sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
+    // (after the draws: the wait before them need not cover this store)
+    if (lane == 16) lv.reward[p * A + a] = hs;
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
