@@ -225,7 +225,11 @@ constexpr int kSortMaxCells = 16384;   // cells of one sorted band (leaf bands <
 template <int NT = kBlock>
 __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_t *cells,
                           int32_t *chunk) {
-  __shared__ int cnt[16 * NT];   // [w][thread], then exclusive offsets
+  // [w][thread], then exclusive offsets; entry e at e + e / 16 (one pad word
+  // per 16), so a thread's 16 consecutive entries and its neighbours' fall in
+  // different LDS banks
+  __shared__ int cnt[17 * NT];
+  auto cx = [](int e) { return e + (e >> 4); };
   __shared__ uint16_t cs[kSortMaxCells];
   __shared__ int wtot[NT / kWave];
   __shared__ int s_start[17], s_pchunk[17], s_C;
@@ -265,7 +269,7 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     for (int k = 0; k < 16; ++k) n[k] += (w == k) ? 1 : 0;
   }
 #pragma unroll
-  for (int w = 0; w < 16; ++w) cnt[w * NT + tid] = n[w];
+  for (int w = 0; w < 16; ++w) cnt[cx(w * NT + tid)] = n[w];
   __syncthreads();
   // exclusive scan of cnt in (w, thread) order: thread i owns entries
   // [16 i, 16 i + 16), then the NT owner totals are scanned
@@ -273,21 +277,16 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     loc[k] = sum;
-    sum += cnt[16 * tid + k];
+    sum += cnt[cx(16 * tid + k)];
   }
   const int lane = tid & (kWave - 1), wave = tid / kWave;
-  int inc = sum;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int y = __shfl_up(inc, o, kWave);
-    if (lane >= o) inc += y;
-  }
+  const int inc = wave_scan_incl(sum);
   if (lane == kWave - 1) wtot[wave] = inc;
   __syncthreads();
   int base = inc - sum;
   for (int v = 0; v < wave; ++v) base += wtot[v];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) cnt[16 * tid + k] = base + loc[k];
+  for (int k = 0; k < 16; ++k) cnt[cx(16 * tid + k)] = base + loc[k];
   __syncthreads();
   if (tid == 0) {
     int Sf = 0;
@@ -295,9 +294,9 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     const int C = max(1, (Sf + (kBlock - 16) - 1) / (kBlock - 16));
     int pc = 0;
     for (int w = 0; w < 16; ++w) {
-      s_start[w] = cnt[w * NT];
+      s_start[w] = cnt[cx(w * NT)];
       s_pchunk[w] = pc;
-      const int nw = (w < 15 ? cnt[(w + 1) * NT] : Sf) - cnt[w * NT];
+      const int nw = (w < 15 ? cnt[cx((w + 1) * NT)] : Sf) - cnt[cx(w * NT)];
       pc += (nw + C - 1) / C;
     }
     s_start[16] = Sf;
@@ -307,7 +306,7 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
   // scatter: each thread walks its cells again in order
   int o[16];
 #pragma unroll
-  for (int w = 0; w < 16; ++w) o[w] = cnt[w * NT + tid];
+  for (int w = 0; w < 16; ++w) o[w] = cnt[cx(w * NT + tid)];
   for (int t = c0; t < c1; ++t) {
     const uint32_t c = cs[t];
     if (!(c & (1u << 12))) continue;
