@@ -619,3 +619,183 @@ def test_filter_gradient_matches_torch_autograd():
     assert abs(nll.sum() - total.item()) < 1e-10
     np.testing.assert_allclose(gt, th.grad.numpy(), rtol=1e-9, atol=1e-11)
     np.testing.assert_allclose(gp, ph.grad.numpy(), rtol=1e-9, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# single-node expansion and leaf score: the references of the large-grid
+# GPU test, tied to the pinned tree search and to the dense model
+# ---------------------------------------------------------------------------
+
+def _expansion_cases():
+    a = wl.make_small(seed=21, D=2, n=2)
+    b = wl.make_rect(seed=22, side=16, n_landmarks=12, D=2, n=3)
+    b.lm_p = 0.8
+    return [a, b]
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_expand_node_equals_plan_records(case):
+    """qvo_expand_node at the root and at level-1 slots reproduces the
+    records and child beliefs that the depth-first search (pinned above by
+    brute force and by its invariants) writes for the same nodes."""
+    prob = _expansion_cases()[case]
+    Q = _q(prob)
+    res = oracle.plan(prob, Q, dump_beliefs=True)
+    dp = res["dump"]
+    A, n, K, S = prob.A, prob.n, prob.K, prob.S
+    checked = 0
+    nodes = [(0, 0, prob.b0.astype(np.float64))]
+    for s1 in np.flatnonzero(dp.level(dp.valid, 1))[:3]:
+        g1 = int(dp.level_off[1] + s1)
+        nodes.append((1, int(s1), dp.beliefs[g1 * S:(g1 + 1) * S].copy()))
+    for d, slot, b in nodes:
+        e = oracle.expand_node(prob, b, d, slot, beliefs=True)
+        gs = int(dp.level_off[d] + slot)
+        kids = int(dp.level_off[d + 1]) + slot * K + np.arange(K)
+        assert np.array_equal(e["valid"], dp.valid[kids].astype(np.int32))
+        v = e["valid"] == 1
+        assert np.array_equal(e["z"][v], dp.z[kids][v])
+        assert np.array_equal(e["count"][v], dp.count[kids][v])
+        assert np.array_equal(e["pz"][v], dp.pz[kids][v])
+        assert np.array_equal(e["margin"], dp.margin[gs * A * n:(gs + 1) * A * n])
+        assert np.array_equal(e["rb"], dp.rb[gs * A:(gs + 1) * A])
+        for c in np.flatnonzero(v):
+            gc = int(kids[c])
+            assert np.array_equal(e["beliefs"][c], dp.beliefs[gc * S:(gc + 1) * S])
+        checked += int(v.sum())
+    assert checked > 8
+
+
+@pytest.mark.parametrize("case", [0, 1])
+def test_expand_node_equals_dense_model(case):
+    """The same expansion from the dense matrices of the model (written
+    without the oracle): b' = b T_a, P(z) = b' O, the n draws by inverse CDF
+    of P over ascending z with the oracle's Philox uniforms (pinned by the
+    known-answer vectors), distinct z with counts, children O(z|.) b' / P(z),
+    and R(b,a) = b . R(.,a)."""
+    prob = _expansion_cases()[case]
+    T = dm.transition_matrices(prob)
+    O = dm.observation_matrix(prob)
+    rng = np.random.default_rng(case)
+    free = np.flatnonzero(prob.occ == 0)
+    b = np.zeros(prob.S)
+    b[free] = rng.random(free.size) ** 4
+    b /= b.sum()
+    d, slot = 1, 5
+    e = oracle.expand_node(prob, b, d, slot, beliefs=True)
+    A, n = prob.A, prob.n
+    for a in range(A):
+        bp = b @ T[a]
+        p = bp @ O
+        P = p.sum()
+        F = np.cumsum(np.where(p > 0, p, 0.0))
+        zs = []
+        for k in range(n):
+            u = oracle.obs_uniform(prob.seed, prob.query_id, d, slot, a, n, k)
+            z = int(np.flatnonzero((F > u * P) & (p > 0))[0])
+            zs.append(z)
+        zu, cnt = np.unique(zs, return_counts=True)
+        U = zu.size
+        sl = slice(a * n, (a + 1) * n)
+        assert list(e["valid"][sl]) == [1] * U + [0] * (n - U)
+        assert np.array_equal(e["z"][sl][:U], zu)
+        assert np.array_equal(e["count"][sl][:U], cnt)
+        np.testing.assert_allclose(e["pz"][sl][:U], p[zu], rtol=1e-12)
+        for r in range(U):
+            np.testing.assert_allclose(e["beliefs"][a * n + r], O[:, zu[r]] * bp / p[zu[r]],
+                                       rtol=1e-12, atol=1e-15)
+        assert abs(e["rb"][a] - b @ prob.R[:, a].astype(np.float64)) < 1e-12
+
+
+def test_leaf_score_is_best_alpha_vector_product():
+    """max_a sum_s b(s) Q(s,a) (Alg. 5 with the Q-MDP vectors): numpy on
+    random beliefs, the depth-0 plan's root value, and the leaf values the
+    depth-first search stores."""
+    prob = wl.make_rect(seed=23, side=16, n_landmarks=5, D=1, n=3)
+    rng = np.random.default_rng(7)
+    Q = rng.standard_normal((prob.S, prob.A)) * 10
+    for _ in range(5):
+        b = rng.random(prob.S)
+        b /= b.sum()
+        assert abs(oracle.leaf_score(prob, Q, b) - np.max(b @ Q)) <= 1e-12 * np.abs(Q).max()
+    r0 = oracle.plan(prob, Q, D=0)
+    v0 = r0["dump"].V[0]
+    assert v0 == oracle.leaf_score(prob, Q, prob.b0)
+    np.testing.assert_allclose(r0["rootQ"], prob.b0.astype(np.float64) @ Q, rtol=1e-12)
+    res = oracle.plan(prob, Q, dump_beliefs=True)
+    dp = res["dump"]
+    for c in np.flatnonzero(dp.level(dp.valid, 1)):
+        g = int(dp.level_off[1] + c)
+        assert dp.V[g] == oracle.leaf_score(prob, Q, dp.beliefs[g * prob.S:(g + 1) * prob.S])
+
+
+# ---------------------------------------------------------------------------
+# the filter with an absorbing goal cell
+# ---------------------------------------------------------------------------
+
+def _goal_filter_case(side, ntraj, T, seed):
+    ts = _filter_case(side=side, ntraj=ntraj, T=T, seed=seed)
+    prob = ts.problem
+    free = np.flatnonzero(prob.occ == 0)
+    prob.goal = int(free[len(free) // 2])      # absorbing; b0 puts mass on it
+    return ts
+
+
+def test_filter_nll_with_goal_equals_path_enumeration():
+    ts = _goal_filter_case(side=3, ntraj=2, T=3, seed=4)
+    prob = ts.problem
+    th = ts.theta.astype(np.float64)
+    ph = ts.phi.astype(np.float64)
+    slip = np.exp(th - th.max(1, keepdims=True))
+    slip /= slip.sum(1, keepdims=True)
+    flip = 1 / (1 + np.exp(-ph))
+    pr = types.SimpleNamespace(**{k: getattr(prob, k) for k in ("W", "H", "occ", "goal", "lm_cell", "lm_p")})
+    pr.slip, pr.flip, pr.A = slip, flip, 8
+    T = dm.transition_matrices(pr)
+    assert all(T[a, prob.goal, prob.goal] == 1.0 for a in range(8))
+    O = dm.observation_matrix(pr)
+    nll, _, _ = oracle.filter_nll_grad(prob, th, ph, ts.acts, ts.obs)
+    b0 = prob.b0.astype(np.float64)
+    import itertools
+    for i in range(ts.acts.shape[0]):
+        tot = 0.0
+        for path in itertools.product(range(prob.S), repeat=4):
+            p = b0[path[0]]
+            for t in range(3):
+                p *= T[ts.acts[i, t], path[t], path[t + 1]] * O[path[t + 1], ts.obs[i, t]]
+                if p == 0:
+                    break
+            tot += p
+        assert abs(-np.log(tot) - nll[i]) < 1e-12
+
+
+def test_filter_gradient_with_goal_matches_central_differences():
+    ts = _goal_filter_case(side=5, ntraj=3, T=6, seed=5)
+    prob = ts.problem
+    th = ts.theta.astype(np.float64)
+    ph = ts.phi.astype(np.float64)
+    nll, gt, gp = oracle.filter_nll_grad(prob, th, ph, ts.acts, ts.obs)
+    h = 1e-4
+
+    def f(t, p):
+        return oracle.filter_nll_grad(prob, t, p, ts.acts, ts.obs)[0].sum()
+
+    fd_t = np.zeros_like(th)
+    for idx in np.ndindex(th.shape):
+        tp, tm = th.copy(), th.copy()
+        tp[idx] += h
+        tm[idx] -= h
+        fd_t[idx] = (f(tp, ph) - f(tm, ph)) / (2 * h)
+    fd_p = np.zeros(4)
+    for j in range(4):
+        pp, pm = ph.copy(), ph.copy()
+        pp[j] += h
+        pm[j] -= h
+        fd_p[j] = (f(th, pp) - f(th, pm)) / (2 * h)
+    scale = max(np.abs(gt).max(), np.abs(gp).max())
+    assert np.abs(gt - fd_t).max() <= 1e-6 * scale
+    assert np.abs(gp - fd_p).max() <= 1e-6 * scale
+    # the goal changes the gradient: the same runs without it differ
+    prob.goal = -1
+    _, gt0, _ = oracle.filter_nll_grad(prob, th, ph, ts.acts, ts.obs)
+    assert np.abs(gt0 - gt).max() > 1e-3 * scale
