@@ -97,6 +97,8 @@ def lib():
         L.qvo_leaf_score.restype = C.c_double
         L.qvo_filter_nll_grad.argtypes = [mp, dp, dp, C.c_int, C.c_int, dp, ip, ip,
                                          dp, dp, dp]
+        L.qvo_fib_iterate.argtypes = [mp, dp, C.c_double, C.c_int, dp, dp, ip]
+        L.qvo_fib_backup_cells.argtypes = [mp, dp, C.c_int, ip, dp]
         _lib = L
     return _lib
 
@@ -319,3 +321,31 @@ def filter_nll_grad(prob, theta, phi, acts, obs, b0=None):
                                    _ptr(gp, C.c_double))
     assert st == 0, st
     return nll, gt.reshape(-1, 9), gp
+
+
+def fib_iterate(prob, tol=1e-12, max_sweeps=100000, init=None):
+    """Fast informed bound by Jacobi sweeps of its alpha-vector equation
+    (Sec. IV-A); returns (alpha [S, A] FP64, residual, sweeps)."""
+    m = Model(prob)
+    al = np.zeros((m.S, m.A))
+    ini = None if init is None else _f64(init).reshape(-1)
+    res = C.c_double(0.0)
+    sw = C.c_int(0)
+    st = lib().qvo_fib_iterate(m.ref, _ptr(ini, C.c_double) if ini is not None else None,
+                               float(tol), int(max_sweeps), _ptr(al, C.c_double),
+                               C.byref(res), C.byref(sw))
+    assert st == 0, st
+    return al, res.value, sw.value
+
+
+def fib_backup(prob, alpha, cells):
+    """Right-hand side of the FIB equation at the listed cells, given the
+    vectors alpha [S, A]; returns [len(cells), A]."""
+    m = Model(prob)
+    al = _f64(alpha).reshape(-1)
+    cells = np.ascontiguousarray(cells, dtype=np.int32)
+    out = np.zeros((cells.size, m.A))
+    st = lib().qvo_fib_backup_cells(m.ref, _ptr(al, C.c_double), int(cells.size),
+                                    _ptr(cells, C.c_int), _ptr(out, C.c_double))
+    assert st == 0, st
+    return out

@@ -339,6 +339,113 @@ int qvo_value_iterate(const qvo_model *m, double tol, int max_sweeps,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Fast informed bound (Sec. IV-A, the alpha-vector "Bellman equation" of    */
+/* FIB): one alpha vector per action,                                       */
+/*   alpha^a(x) = R(x,a) + gamma * sum_z max_a' sum_x' O(z|x') T(x,a,x')     */
+/*                                              * alpha^a'(x').              */
+/* ------------------------------------------------------------------------ */
+
+/* The right-hand side of the FIB equation at one cell x for every action,
+ * given the current vectors alpha [S*A] (row-major by cell).  The sum over z
+ * runs over every observation that some successor x' of x can produce: all
+ * 16 wall readings with "no landmark", and with the id of each landmark
+ * among the successors (every other z has O(z|x') = 0 for all of them, so
+ * its max over a' is 0).  Blocked x: 0.  The goal: absorbing, R = 0, so
+ * its right-hand side is gamma * max_a' alpha^a'(goal). */
+void qvo_fib_backup_cell(const qvo_model *m, const int *lm, const double *alpha, int x,
+                         double *out) {
+  int A = m->A;
+  if (m->occ[x]) { for (int a = 0; a < A; a++) out[a] = 0.0; return; }
+  for (int a = 0; a < A; a++) {
+    /* T(x,a,.) as a list of distinct successors */
+    int xs[9], nx = 0;
+    double tp[9];
+    if (x == m->goal) { xs[0] = x; tp[0] = 1.0; nx = 1; }
+    else {
+      for (int k = 0; k < 9; k++) {
+        int d = qvo_dest(m, x, k), i;
+        for (i = 0; i < nx; i++) if (xs[i] == d) break;
+        if (i == nx) { xs[nx] = d; tp[nx] = 0.0; nx++; }
+        tp[i] += m->slip[a * 9 + k];
+      }
+    }
+    /* landmark ids the successors can report (0 = none, always possible) */
+    int zl_list[10], nzl = 1;
+    zl_list[0] = 0;
+    for (int i = 0; i < nx; i++) if (lm[xs[i]]) {
+      int j;
+      for (j = 1; j < nzl; j++) if (zl_list[j] == lm[xs[i]]) break;
+      if (j == nzl) zl_list[nzl++] = lm[xs[i]];
+    }
+    double acc = 0.0;
+    for (int il = 0; il < nzl; il++) {
+      for (int zw = 0; zw < 16; zw++) {
+        int z = zw + 16 * zl_list[il];
+        double best = -INFINITY;
+        for (int ap = 0; ap < A; ap++) {
+          double v = 0.0;
+          for (int i = 0; i < nx; i++)
+            v += qvo_obs(m, lm, z, xs[i]) * tp[i] * alpha[(size_t)xs[i] * A + ap];
+          if (v > best) best = v;
+        }
+        acc += best;
+      }
+    }
+    out[a] = m->R[(size_t)x * A + a] + m->gamma * acc;
+  }
+}
+
+/* FIB value iteration: Jacobi sweeps alpha_{k+1} = H_FIB alpha_k from alpha_0
+ * = init (NULL: all zeros) until the residual r = max over free x and all a
+ * of |alpha_{k+1}(x,a) - alpha_k(x,a)| satisfies r = 0 or r <= tol * max(1,
+ * max |alpha_{k+1}|), or max_sweeps sweeps.  The mapping is monotone and a
+ * contraction (Sec. IV-A), so this converges from any start. */
+int qvo_fib_iterate(const qvo_model *m, const double *init, double tol, int max_sweeps,
+                    double *alpha, double *residual, int *sweeps) {
+  int S = m->W * m->H, A = m->A;
+  int *lm = qvo_landmark_map(m);
+  double *cur = (double *)calloc((size_t)S * A, sizeof(double));
+  double *nxt = (double *)calloc((size_t)S * A, sizeof(double));
+  if (!lm || !cur || !nxt) { free(lm); free(cur); free(nxt); return QVO_ERR_MEM; }
+  if (init) memcpy(cur, init, sizeof(double) * (size_t)S * A);
+  double r = INFINITY;
+  int it = 0;
+  while (it < max_sweeps) {
+    it++;
+    double vmax = 0.0;
+    r = 0.0;
+    for (int x = 0; x < S; x++) {
+      qvo_fib_backup_cell(m, lm, cur, x, nxt + (size_t)x * A);
+      if (m->occ[x]) continue;
+      for (int a = 0; a < A; a++) {
+        double d = fabs(nxt[(size_t)x * A + a] - cur[(size_t)x * A + a]);
+        if (d > r) r = d;
+        if (fabs(nxt[(size_t)x * A + a]) > vmax) vmax = fabs(nxt[(size_t)x * A + a]);
+      }
+    }
+    double *t = cur; cur = nxt; nxt = t;
+    if (r == 0.0 || r <= tol * (vmax > 1.0 ? vmax : 1.0)) break;
+  }
+  memcpy(alpha, cur, sizeof(double) * (size_t)S * A);
+  free(lm); free(cur); free(nxt);
+  if (residual) *residual = r;
+  if (sweeps) *sweeps = it;
+  return QVO_OK;
+}
+
+/* One FIB backup at each of the listed cells (for spot checks of a large
+ * table): out[i*A + a] = right-hand side of the FIB equation at cells[i]. */
+int qvo_fib_backup_cells(const qvo_model *m, const double *alpha, int ncells,
+                         const int *cells, double *out) {
+  int *lm = qvo_landmark_map(m);
+  if (!lm) return QVO_ERR_MEM;
+  for (int i = 0; i < ncells; i++)
+    qvo_fib_backup_cell(m, lm, alpha, cells[i], out + (size_t)i * m->A);
+  free(lm);
+  return QVO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* QV-tree search by sampled expectimax, depth first (Alg. 2, 3, 5, 6, 7)    */
 /* ------------------------------------------------------------------------ */
 
