@@ -369,6 +369,12 @@ def bench_filter(args, B, wl, torch, dev):
             "note": "one evaluation = forward filter, segment recomputation and adjoint"}
 
 
+def progress(msg):
+    """A line on stderr as each part of the run ends (stdout carries only the
+    JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def source_hash():
     from paper_1810_00204_amd.build import source_hash as h
     return h()
@@ -385,6 +391,8 @@ def main():
     seeds = [prob.seed + i for i in range(args.seeds)]
     # the CPU legs first, in forked workers, before anything touches the GPU
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, seeds, args.cpu_runs)
+    if cpu is not None:
+        progress(f"cpu baseline done: {cpu['value']:.3e} updates/s on {cpu['cores']} cores")
 
     import torch
     from paper_1810_00204_amd import binding as B
@@ -397,6 +405,7 @@ def main():
     flags = B.QV_PLAN_TILED if args.banded else 0
     r = plan_bench(B, torch, dev, prob, args.steps, args.warmup, args.seeds, flags,
                    args.workload, src)
+    progress(f"{prob.name}: {r['ms_per_step']:.4f} ms per plan")
 
     if args.copy_calibration:
         for mib in (256, 512):
@@ -436,8 +445,11 @@ def main():
                       "evaluated_belief_updates_per_s": rs["evaluated_updates_per_s"],
                       "nodes_per_level": rs["nodes_per_level"], "roofline": rs["roofline"],
                       "kernels": rs["kernels"], "value_iteration": rs["value_iteration"]}
+        progress(f"{sp.name}: {rs['ms_per_step']:.4f} ms per plan")
         line["batch"] = bench_batch(args, B, wl, torch, dev)
+        progress(f"batch: {line['batch']['ms_per_batch']:.3f} ms per batch")
         line["filter"] = bench_filter(args, B, wl, torch, dev)
+        progress(f"filter: {line['filter']['ms_per_eval']:.3f} ms per evaluation")
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

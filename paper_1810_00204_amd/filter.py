@@ -65,8 +65,9 @@ def _make_function():
         @staticmethod
         def forward(ctx, theta, phi, problem):
             nll, gs, gf = problem.run(theta, phi, grad=True)
-            ctx.save_for_backward(gs.to(theta.dtype), gf.to(phi.dtype))
-            return nll.sum().to(theta.dtype)
+            # gradients on the parameters' own device and dtype
+            ctx.save_for_backward(gs.to(theta.device, theta.dtype), gf.to(phi.device, phi.dtype))
+            return nll.sum().to(theta.device, theta.dtype)
 
         @staticmethod
         def backward(ctx, grad_out):

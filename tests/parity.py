@@ -20,6 +20,11 @@ DRAW_BAND = 3e-5
 ACTION_BAND = 1e-5
 REL = 1e-5
 
+# Session totals, printed at the end of the pytest run (tests/conftest.py):
+# compared trees, nodes and beliefs, and every excused draw or root action
+# with its oracle margin.
+TOTALS = {"trees": 0, "nodes": 0, "beliefs": 0, "draws_excused": [], "actions_excused": []}
+
 
 class Report:
     def __init__(self):
@@ -90,6 +95,10 @@ def compare_tree(prob, g, o, check_beliefs=True, rel=REL):
                 bad = np.abs(gb - ob) > tol
                 assert not bad.any(), (d, slot, np.flatnonzero(bad)[:5], gb[bad][:5], ob[bad][:5])
                 rep.beliefs += 1
+    TOTALS["trees"] += 1
+    TOTALS["nodes"] += rep.nodes
+    TOTALS["beliefs"] += rep.beliefs
+    TOTALS["draws_excused"].extend((prob.name,) + e for e in rep.excused)
     return rep
 
 
@@ -111,4 +120,22 @@ def root_action_ok(g_action, o_rootQ, o_action):
     if g_action == o_action:
         return True
     q = np.sort(o_rootQ)[::-1]
-    return (q[0] - q[1]) <= ACTION_BAND * max(1.0, abs(q[0]))
+    ok = (q[0] - q[1]) <= ACTION_BAND * max(1.0, abs(q[0]))
+    if ok:
+        TOTALS["actions_excused"].append((int(g_action), int(o_action), float(q[0] - q[1])))
+    return ok
+
+
+def summary() -> str:
+    t = TOTALS
+    if not t["trees"]:
+        return ""
+    lines = [f"parity: {t['trees']} trees, {t['nodes']} nodes, {t['beliefs']} beliefs compared "
+             f"with the oracle; {len(t['draws_excused'])} draws and "
+             f"{len(t['actions_excused'])} root actions excused as near ties"]
+    for e in t["draws_excused"]:
+        lines.append(f"  excused draw: {e[0]} level {e[1]} slot {e[2]} action {e[3]}, "
+                     f"oracle margin {e[4]:.3g} (band {DRAW_BAND:g})")
+    for e in t["actions_excused"]:
+        lines.append(f"  excused root action: gpu {e[0]} oracle {e[1]}, top-two gap {e[2]:.3g}")
+    return "\n".join(lines)

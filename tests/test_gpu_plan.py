@@ -53,16 +53,17 @@ PATHS = {"node": 0, "banded": B.QV_PLAN_TILED}
 
 
 @pytest.mark.parametrize("path", list(PATHS))
-@pytest.mark.parametrize("seed", range(16))
+@pytest.mark.parametrize("seed", range(100))
 def test_plan_matches_oracle_small_grid(seed, path):
     _say(f"plan 10x10 4 actions D=2 n=2 seed={seed} path={path}")
     prob = wl.make_small(seed=seed)
     rep = _check(prob, _q32(prob), flags=PATHS[path])
     assert rep.nodes > 1
+    assert len(rep.excused) <= 1
 
 
 @pytest.mark.parametrize("path", list(PATHS))
-@pytest.mark.parametrize("seed", range(2))
+@pytest.mark.parametrize("seed", range(10))
 def test_plan_matches_oracle_rect_grid(seed, path):
     """64x64 rectangles, 8 actions, 32 landmarks, depth 3, 4 samples."""
     _say(f"plan 64x64 8 actions L=32 D=3 n=4 seed={seed} path={path}")

@@ -46,12 +46,13 @@ def test_value_iteration_corridor_closed_form():
     assert res <= 1e-7 * max(1.0, np.abs(V).max()) or res == 0.0
 
 
-@pytest.mark.parametrize("maker", ["small", "rect", "ragged"])
+@pytest.mark.parametrize("maker", ["small", "rect", "ragged", "large"])
 def test_value_iteration_matches_fp64(maker):
     _say(f"VI vs FP64 {maker}")
     prob = {"small": lambda: wl.make_small(seed=1),
             "rect": lambda: wl.make_rect(seed=0),
-            "ragged": lambda: wl.make_small(seed=2, W=50, H=100)}[maker]()
+            "ragged": lambda: wl.make_small(seed=2, W=50, H=100),
+            "large": lambda: wl.make_large(seed=0)}[maker]()
     Q32, res, sw = _vi(prob, 1e-6)
     Q64, res64, sw64 = oracle.value_iterate(prob, tol=1e-12)
     err = np.abs(Q32 - Q64).max()
