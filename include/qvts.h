@@ -66,6 +66,13 @@ extern "C" {
  * Q-node); results are the same up to FP32 summation order. */
 #define QV_PLAN_TILED 2
 
+/* Check the start belief on the device before planning: the call becomes
+ * synchronous and returns QV_ERR_BELIEF_INVALID, with nothing planned and
+ * the outputs untouched, unless b0 is a distribution over the free cells
+ * (the b0 in B(X) of Sec. II): every entry finite and >= 0, zero on blocked
+ * cells, and the total (summed in FP64) within 1e-5 of 1. */
+#define QV_PLAN_CHECK 4
+
 /* ---- problem statement ------------------------------------------------- */
 /* The POMDP tuple (X, A, Z, T, O, R, b0, gamma) of Sec. II, specialised to
  * the grid world of Sec. V.  X is every cell of the W x H grid (blocked
@@ -97,6 +104,18 @@ const char *qv_status_string(int32_t status);
 /* The hipError_t of the last failing HIP call made by this thread. */
 int32_t qv_last_hip_error(void);
 
+/* ---- device validation of a problem statement (Sec. II tuple) ----------
+ * The host checks of every call (sizes, slip rows summing to 1, flip and
+ * landmark probabilities in [0,1], gamma in (0,1)) plus checks of the device
+ * arrays: every R(s,a) finite and every landmark on a free in-grid cell
+ * (else QV_ERR_INVALID_ARG); if b0 (device [S], may be NULL) is given, it
+ * must be a distribution over the free cells: entries finite and >= 0, zero
+ * on blocked cells, total within 1e-5 of 1 (else QV_ERR_BELIEF_INVALID).
+ * Synchronous.  Workspace: qv_check_workspace_bytes() bytes. */
+size_t qv_check_workspace_bytes(void);
+int32_t qv_model_check(const qv_model *m, const float *b0, void *ws, size_t ws_bytes,
+                       void *stream);
+
 /* ---- Bayes filter step (Sec. III, posterior belief update) -------------
  * For each i < batch:  b'(x') = sum_x T(x,a_i,x') b_i(x),
  *   p_i = P(z_i|b_i,a_i) = sum_x' O(z_i|x') b'(x'),
@@ -118,7 +137,8 @@ int32_t qv_belief_update(const qv_model *m, int32_t batch, const float *b,
  *   Q_k(s,a) = R(s,a) + gamma * sum_s' T(s,a,s') V_k(s'),
  *   V_{k+1}(s) = max_a Q_k(s,a),  (blocked cells: Q = V = 0),
  * in FP32, with the residual r_k = max_s |V_{k+1}(s) - V_k(s)| formed in
- * FP64.  Stops after the first sweep with r_k = 0 or
+ * FP64.  All sweeps run in one launch (a grid barrier between sweeps), so the
+ * host waits once.  Stops after the first sweep with r_k = 0 or
  * r_k <= tol * max(1, max_s |V_{k+1}(s)|), or after max_sweeps sweeps.
  * Q: [S*A] FP32 output, Q_k of the last sweep.  Synchronous: on return
  * *residual_out (host) and *sweeps_out (host) hold r_k and k. */
@@ -126,6 +146,25 @@ size_t qv_vi_workspace_bytes(const qv_model *m, int32_t max_sweeps);
 int32_t qv_value_iterate(const qv_model *m, float tol, int32_t max_sweeps,
                          float *Q, double *residual_out, int32_t *sweeps_out,
                          void *ws, size_t ws_bytes, void *stream);
+
+/* ---- fast informed bound (Sec. IV-A, the FIB alpha-vector equation) ----
+ * One alpha vector per action, the fixed point of
+ *   alpha^a(x) = R(x,a) + gamma * sum_z max_a' sum_x' O(z|x') T(x,a,x') alpha^a'(x'),
+ * by Jacobi sweeps in FP32 from alpha_0 = 0 (blocked cells: alpha = 0; the
+ * goal is absorbing).  The sum over z runs over every observation a
+ * successor of x can produce.  Residual r_k = max over free x and all a of
+ * |alpha_k - alpha_{k-1}|, formed in FP64; stops after the first sweep with
+ * r_k = 0 or r_k <= tol * max(1, max |alpha_k|), or after max_sweeps.
+ * alpha: [S*A] FP32 output, row-major by cell (the layout of a Q table, so
+ * it can be passed to qv_plan_step as the leaf table: leaves then score
+ * max_a' sum_s b(s) alpha^a'(s), the U_V = V_FIB of Alg. 5).  FIB lies
+ * between the POMDP value and Q-MDP (Sec. IV-A).  Synchronous: on return
+ * *residual_out and *sweeps_out (host) hold r_k and k.
+ * Workspace: qv_fib_workspace_bytes(m, max_sweeps). */
+size_t qv_fib_workspace_bytes(const qv_model *m, int32_t max_sweeps);
+int32_t qv_fib_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *alpha,
+                       double *residual_out, int32_t *sweeps_out, void *ws, size_t ws_bytes,
+                       void *stream);
 
 /* ---- one planning step (Alg. 1 inner loop + getOptimalAction) ---------
  * Builds the QV-tree of depth D from b0 level by level: every V-node is
@@ -140,7 +179,8 @@ int32_t qv_value_iterate(const qv_model *m, float tol, int32_t max_sweeps,
  * V(v) = max_a Q(v,a) (Alg. 6/7); the action is the lowest a whose root
  * Q-value is within 1e-9 of the maximum.
  * Q: [S*A] FP32 leaf table; b0: [S] FP32 start belief (a distribution with
- * no mass on blocked cells); action_out: [1] int32; rootQ_out: [A] FP32.
+ * no mass on blocked cells; checked on the device with QV_PLAN_CHECK, not
+ * checked otherwise); action_out: [1] int32; rootQ_out: [A] FP32.
  * The tree records stay in the workspace afterwards (qv_plan_layout). */
 size_t qv_plan_workspace_bytes(const qv_model *m, int32_t D, int32_t n, int32_t flags);
 int32_t qv_plan_step(const qv_model *m, const float *Q, const float *b0,

@@ -30,6 +30,7 @@ QV_MAX_DEPTH = 6
 QV_MAX_SAMPLES = 16
 QV_PLAN_STORE_LEAVES = 1
 QV_PLAN_TILED = 2
+QV_PLAN_CHECK = 4
 QV_BATCH_GRAPH = 1
 
 # every function the header declares
@@ -37,6 +38,8 @@ EXPORTS = [
     "qv_status_string", "qv_last_hip_error",
     "qv_belief_update_workspace_bytes", "qv_belief_update",
     "qv_vi_workspace_bytes", "qv_value_iterate",
+    "qv_fib_workspace_bytes", "qv_fib_iterate",
+    "qv_check_workspace_bytes", "qv_model_check",
     "qv_plan_workspace_bytes", "qv_plan_step", "qv_plan_layout",
     "qv_timing_enable", "qv_timing_read",
     "qv_filter_workspace_bytes", "qv_filter_nll_grad",
@@ -108,6 +111,15 @@ def lib():
         L.qv_value_iterate.argtypes = [mp, C.c_float, C.c_int32, vp, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32), vp, C.c_size_t, vp]
         L.qv_value_iterate.restype = C.c_int32
+        L.qv_check_workspace_bytes.argtypes = []
+        L.qv_check_workspace_bytes.restype = C.c_size_t
+        L.qv_model_check.argtypes = [mp, vp, vp, C.c_size_t, vp]
+        L.qv_model_check.restype = C.c_int32
+        L.qv_fib_workspace_bytes.argtypes = [mp, C.c_int32]
+        L.qv_fib_workspace_bytes.restype = C.c_size_t
+        L.qv_fib_iterate.argtypes = [mp, C.c_float, C.c_int32, vp, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_int32), vp, C.c_size_t, vp]
+        L.qv_fib_iterate.restype = C.c_int32
         L.qv_plan_workspace_bytes.argtypes = [mp, C.c_int32, C.c_int32, C.c_int32]
         L.qv_plan_workspace_bytes.restype = C.c_size_t
         L.qv_plan_step.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
@@ -195,6 +207,30 @@ def qv_value_iterate(model, tol, max_sweeps, Q, ws, stream=None):
     st = lib().qv_value_iterate(C.byref(model.c), float(tol), int(max_sweeps), _ptr(Q),
                                 C.byref(res), C.byref(sw), _ptr(ws), _nbytes(ws),
                                 _stream(stream))
+    return int(st), res.value, sw.value
+
+
+def qv_check_workspace_bytes() -> int:
+    return int(lib().qv_check_workspace_bytes())
+
+
+def qv_model_check(model, b0, ws, stream=None) -> int:
+    """Device validation of the model's arrays and (if given) the start belief."""
+    return int(lib().qv_model_check(C.byref(model.c), _ptr(b0) if b0 is not None else None,
+                                    _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_fib_workspace_bytes(model, max_sweeps: int) -> int:
+    return int(lib().qv_fib_workspace_bytes(C.byref(model.c), int(max_sweeps)))
+
+
+def qv_fib_iterate(model, tol, max_sweeps, alpha, ws, stream=None):
+    """Returns (status, residual, sweeps)."""
+    res = C.c_double(0.0)
+    sw = C.c_int32(0)
+    st = lib().qv_fib_iterate(C.byref(model.c), float(tol), int(max_sweeps), _ptr(alpha),
+                              C.byref(res), C.byref(sw), _ptr(ws), _nbytes(ws),
+                              _stream(stream))
     return int(st), res.value, sw.value
 
 

@@ -235,6 +235,39 @@ int32_t qv_value_iterate(const qv_model *m, float tol, int32_t max_sweeps, float
   return QV_OK;
 }
 
+size_t qv_check_workspace_bytes(void) { return 256; }
+
+int32_t qv_model_check(const qv_model *m, const float *b0, void *ws, size_t ws_bytes,
+                       void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (!ws_ok(ws, ws_bytes, qv_check_workspace_bytes())) return QV_ERR_WORKSPACE;
+  return run_model_check(make_dev_model(m), b0, true, (char *)ws, (hipStream_t)stream);
+}
+
+size_t qv_fib_workspace_bytes(const qv_model *m, int32_t max_sweeps) {
+  if (check_model(m) != QV_OK || max_sweeps < 1) return 0;
+  return fib_ws(m, max_sweeps);
+}
+
+int32_t qv_fib_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *alpha,
+                       double *residual_out, int32_t *sweeps_out, void *ws, size_t ws_bytes,
+                       void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (max_sweeps < 1 || !(tol >= 0.f) || !alpha || !residual_out || !sweeps_out)
+    return QV_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, fib_ws(m, max_sweeps))) return QV_ERR_WORKSPACE;
+  const DevModel dm = make_dev_model(m);
+  double r = 0.0;
+  int k = 0;
+  st = hip_status(run_fib(dm, tol, max_sweeps, alpha, &r, &k, (char *)ws, (hipStream_t)stream));
+  if (st != QV_OK) return st;
+  *residual_out = r;
+  *sweeps_out = k;
+  return QV_OK;
+}
+
 size_t qv_plan_workspace_bytes(const qv_model *m, int32_t D, int32_t n, int32_t flags) {
   if (check_model(m) != QV_OK || D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES)
     return 0;
@@ -262,10 +295,15 @@ int32_t qv_plan_step(const qv_model *m, const float *Q, const float *b0, int32_t
   if (st != QV_OK) return st;
   if (D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES) return QV_ERR_INVALID_ARG;
   if (!Q || !b0 || !action_out || !rootQ_out) return QV_ERR_INVALID_ARG;
-  if (flags & ~(QV_PLAN_STORE_LEAVES | QV_PLAN_TILED)) return QV_ERR_INVALID_ARG;
+  if (flags & ~(QV_PLAN_STORE_LEAVES | QV_PLAN_TILED | QV_PLAN_CHECK)) return QV_ERR_INVALID_ARG;
   PlanLayout L;
   if (!plan_layout_impl(m, D, n, flags, &L)) return QV_ERR_UNSUPPORTED;
   if (!ws_ok(ws, ws_bytes, L.pub.total_bytes)) return QV_ERR_WORKSPACE;
+  if (flags & QV_PLAN_CHECK) {
+    // b0 in B(X) (Sec. II), checked on the device before anything is planned
+    st = run_model_check(make_dev_model(m), b0, false, (char *)ws + L.err, (hipStream_t)stream);
+    if (st != QV_OK) return st;
+  }
   return hip_status(launch_plan(m, Q, b0, D, n, seed, query_id, flags, action_out, rootQ_out,
                                 (char *)ws, L, (hipStream_t)stream));
 }

@@ -164,6 +164,11 @@ size_t belief_update_ws(const qv_model *m, int batch);
 hipError_t run_value_iteration(const DevModel &dm, float tol, int max_sweeps, float *Q,
                                double *residual, int *sweeps, char *ws, hipStream_t st);
 size_t vi_ws(const qv_model *m, int max_sweeps);
+hipError_t run_fib(const DevModel &dm, float tol, int max_sweeps, float *alpha,
+                   double *residual, int *sweeps, char *ws, hipStream_t st);
+size_t fib_ws(const qv_model *m, int max_sweeps);
+int32_t run_model_check(const DevModel &m, const float *b0, bool check_r, char *rec,
+                        hipStream_t st);
 bool filter_supported(const qv_model *m);
 int filter_groups(int ntraj);
 size_t filter_ws(const qv_model *m, int ntraj, int T, int k, int G);

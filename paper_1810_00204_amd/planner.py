@@ -38,6 +38,16 @@ class Planner:
         B.check(st, "qv_value_iterate")
         return Q, res, sw
 
+    # -- offline fast informed bound (its alpha vectors score leaves as a Q table)
+    def fib_iterate(self, tol=1e-6, max_sweeps=10000):
+        torch = self.torch
+        al = torch.empty(self.m.S * self.m.A, dtype=torch.float32, device=self.device)
+        ws = torch.empty(B.qv_fib_workspace_bytes(self.m, max_sweeps), dtype=torch.uint8,
+                         device=self.device)
+        st, res, sw = B.qv_fib_iterate(self.m, tol, max_sweeps, al, ws)
+        B.check(st, "qv_fib_iterate")
+        return al, res, sw
+
     # -- one planning step ------------------------------------------------
     def plan(self, Q, b0=None, seed=None, query_id=None, stream=None):
         prob = self.prob

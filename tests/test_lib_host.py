@@ -120,3 +120,24 @@ def test_tree_capacity_limit_is_reported():
     assert B.qv_plan_workspace_bytes(m, 6, 16, 0) == 0
     st, _ = B.qv_plan_layout(m, 6, 16, 0)
     assert st == B.QV_ERR_UNSUPPORTED
+
+
+def test_fib_and_check_arguments_are_checked_on_the_host():
+    prob = wl.make_small(seed=1)
+    m = FakeModel(prob)
+    r, k = C.c_double(), C.c_int32()
+    fneed = B.qv_fib_workspace_bytes(m, 50)
+    assert fneed > B.qv_vi_workspace_bytes(m, 50) > 0   # A values per cell, not one
+    lib = B.lib()
+    assert lib.qv_fib_iterate(C.byref(m.c), 1e-6, 0, 0x10, C.byref(r), C.byref(k), 0x100, fneed, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_fib_iterate(C.byref(m.c), 1e-6, 50, None, C.byref(r), C.byref(k), 0x100, fneed, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_fib_iterate(C.byref(m.c), 1e-6, 50, 0x10, C.byref(r), C.byref(k), 0x100, fneed - 1, None) == B.QV_ERR_WORKSPACE
+    bad = FakeModel(prob, gamma=0.0)
+    assert lib.qv_fib_iterate(C.byref(bad.c), 1e-6, 50, 0x10, C.byref(r), C.byref(k), 0x100, fneed, None) == B.QV_ERR_INVALID_ARG
+    assert B.qv_check_workspace_bytes() == 256
+    assert lib.qv_model_check(C.byref(bad.c), 0x10, 0x100, 256, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_model_check(C.byref(m.c), 0x10, 0x100, 255, None) == B.QV_ERR_WORKSPACE
+    assert lib.qv_model_check(C.byref(m.c), 0x10, 0x104, 256, None) == B.QV_ERR_WORKSPACE
+    # the check flag is accepted by the plan call's flag test (bad depth still wins)
+    assert lib.qv_plan_step(C.byref(m.c), 0x10, 0x20, 7, 2, 1, 0, B.QV_PLAN_CHECK, 0x30, 0x40, 0x100, 1 << 20, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_plan_step(C.byref(m.c), 0x10, 0x20, 2, 2, 1, 0, 16, 0x30, 0x40, 0x100, 1 << 20, None) == B.QV_ERR_INVALID_ARG
