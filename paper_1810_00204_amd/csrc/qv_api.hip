@@ -184,31 +184,11 @@ size_t qv_belief_update_workspace_bytes(const qv_model *m, int32_t batch) {
 int32_t qv_belief_update(const qv_model *m, int32_t batch, const float *b, const int32_t *a,
                          const int32_t *z, float *b_out, float *p_out, int32_t check, void *ws,
                          size_t ws_bytes, void *stream) {
-  int32_t st = check_model(m);
+  const int32_t st = belief_update_args(m, batch, b, a, z, b_out, p_out);
   if (st != QV_OK) return st;
-  if (batch < 0) return QV_ERR_INVALID_ARG;
-  if (batch > 0 && (!b || !a || !z || !b_out || !p_out)) return QV_ERR_INVALID_ARG;
-  const size_t S = (size_t)m->W * m->H;
-  if (batch > 0 && (const void *)b < (const void *)(b_out + (size_t)batch * S) &&
-      (const void *)b_out < (const void *)(b + (size_t)batch * S))
-    return QV_ERR_INVALID_ARG;
   if (!ws_ok(ws, ws_bytes, belief_update_ws(m, batch))) return QV_ERR_WORKSPACE;
-  hipStream_t hs = (hipStream_t)stream;
-  const DevModel dm = make_dev_model(m);
-  st = hip_status(launch_belief_update(dm, batch, b, a, z, b_out, p_out, (char *)ws, hs));
-  if (st != QV_OK || !check) return st;
-  const size_t TH = tile_rows(m->W, m->H);
-  const size_t tiles = (m->H + TH - 1) / TH;
-  size_t off = align_up(S * 4, 256) + align_up((size_t)m->A * 256 * 4, 256) +
-               align_up((size_t)batch * tiles * 4, 256);
-  int32_t herr = 0;
-  st = hip_status(hipMemcpyAsync(&herr, (char *)ws + off, 4, hipMemcpyDeviceToHost, hs));
-  if (st != QV_OK) return st;
-  st = hip_status(hipStreamSynchronize(hs));
-  if (st != QV_OK) return st;
-  if (herr & (4 | 8)) return QV_ERR_ZERO_LIKELIHOOD;
-  if (herr) return QV_ERR_INVALID_ARG;
-  return QV_OK;
+  return belief_update_run(m, batch, b, a, z, b_out, p_out, check, (char *)ws,
+                           (hipStream_t)stream);
 }
 
 size_t qv_vi_workspace_bytes(const qv_model *m, int32_t max_sweeps) {

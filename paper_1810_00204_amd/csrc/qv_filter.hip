@@ -163,6 +163,39 @@ hipError_t launch_belief_update(const DevModel &m, int batch, const float *b,
   return hipGetLastError();
 }
 
+int32_t belief_update_args(const qv_model *m, int batch, const float *b, const int32_t *a,
+                           const int32_t *z, const float *b_out, const float *p_out) {
+  const int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (batch < 0) return QV_ERR_INVALID_ARG;
+  if (batch > 0 && (!b || !a || !z || !b_out || !p_out)) return QV_ERR_INVALID_ARG;
+  const size_t S = (size_t)m->W * m->H;
+  if (batch > 0 && (const void *)b < (const void *)(b_out + (size_t)batch * S) &&
+      (const void *)b_out < (const void *)(b + (size_t)batch * S))
+    return QV_ERR_INVALID_ARG;
+  return QV_OK;
+}
+
+int32_t belief_update_run(const qv_model *m, int batch, const float *b, const int32_t *a,
+                          const int32_t *z, float *b_out, float *p_out, int check, char *ws,
+                          hipStream_t hs) {
+  const DevModel dm = make_dev_model(m);
+  int32_t st = hip_status(launch_belief_update(dm, batch, b, a, z, b_out, p_out, ws, hs));
+  if (st != QV_OK || !check) return st;
+  const size_t S = (size_t)m->W * m->H;
+  const size_t TH = tile_rows(m->W, m->H);
+  const size_t tiles = (m->H + TH - 1) / TH;
+  const size_t off = align_up(S * 4, 256) + align_up((size_t)m->A * 256 * 4, 256) +
+                     align_up((size_t)batch * tiles * 4, 256);
+  int32_t herr = 0;
+  st = hip_status(hipMemcpyAsync(&herr, ws + off, 4, hipMemcpyDeviceToHost, hs));
+  if (st != QV_OK) return st;
+  st = hip_status(hipStreamSynchronize(hs));
+  if (st != QV_OK) return st;
+  if (herr & (4 | 8)) return QV_ERR_ZERO_LIKELIHOOD;
+  if (herr) return QV_ERR_INVALID_ARG;
+  return QV_OK;
+}
 
 // ===========================================================================
 // Differentiable filter: negative log-likelihood of logged observations under

@@ -161,6 +161,14 @@ hipError_t launch_belief_update(const DevModel &dm, int batch, const float *b,
                                 const int32_t *a, const int32_t *z, float *b_out,
                                 float *p_out, char *ws, hipStream_t st);
 size_t belief_update_ws(const qv_model *m, int batch);
+// Host checks of a belief-update call (everything but the workspace).
+int32_t belief_update_args(const qv_model *m, int batch, const float *b, const int32_t *a,
+                           const int32_t *z, const float *b_out, const float *p_out);
+// Enqueue the update on a workspace of belief_update_ws(m, batch) bytes; with
+// check, wait and report out-of-range or zero-likelihood rows.
+int32_t belief_update_run(const qv_model *m, int batch, const float *b, const int32_t *a,
+                          const int32_t *z, float *b_out, float *p_out, int check, char *ws,
+                          hipStream_t hs);
 hipError_t run_value_iteration(const DevModel &dm, float tol, int max_sweeps, float *Q,
                                double *residual, int *sweeps, char *ws, hipStream_t st);
 size_t vi_ws(const qv_model *m, int max_sweeps);
