@@ -132,6 +132,20 @@ int32_t qv_belief_update(const qv_model *m, int32_t batch, const float *b,
                          float *p_out, int32_t check, void *ws, size_t ws_bytes,
                          void *stream);
 
+/* As qv_belief_update, for callers that cannot allocate device memory (code
+ * under graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the scratch space lives in the library's own device memory, one fixed
+ * region of about 4.1 MiB per GPU, held until the process ends, instead of
+ * a caller workspace.  Limits: W*H <= 1048576 cells and batch * bands <=
+ * 16384 (bands of about 1024 cells, whole rows); larger calls return
+ * QV_ERR_UNSUPPORTED before anything is enqueued.  The call allocates
+ * nothing.  Every call on one GPU shares that GPU's region, so calls that
+ * overlap on one GPU (on different streams or threads) race; serialise
+ * them.  Same arguments, outputs and statuses as qv_belief_update. */
+int32_t qv_belief_update_noalloc(const qv_model *m, int32_t batch, const float *b,
+                                 const int32_t *a, const int32_t *z, float *b_out,
+                                 float *p_out, int32_t check, void *stream);
+
 /* ---- Q-MDP value iteration (Sec. V-B; Sec. IV-A with a perfect sensor) --
  * Jacobi sweeps from V_0 = 0:
  *   Q_k(s,a) = R(s,a) + gamma * sum_s' T(s,a,s') V_k(s'),

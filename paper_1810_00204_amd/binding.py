@@ -36,7 +36,7 @@ QV_BATCH_GRAPH = 1
 # every function the header declares
 EXPORTS = [
     "qv_status_string", "qv_last_hip_error",
-    "qv_belief_update_workspace_bytes", "qv_belief_update",
+    "qv_belief_update_workspace_bytes", "qv_belief_update", "qv_belief_update_noalloc",
     "qv_vi_workspace_bytes", "qv_value_iterate",
     "qv_fib_workspace_bytes", "qv_fib_iterate",
     "qv_check_workspace_bytes", "qv_model_check",
@@ -106,6 +106,8 @@ def lib():
         L.qv_belief_update.argtypes = [mp, C.c_int32, vp, vp, vp, vp, vp, C.c_int32, vp,
                                        C.c_size_t, vp]
         L.qv_belief_update.restype = C.c_int32
+        L.qv_belief_update_noalloc.argtypes = [mp, C.c_int32, vp, vp, vp, vp, vp, C.c_int32, vp]
+        L.qv_belief_update_noalloc.restype = C.c_int32
         L.qv_vi_workspace_bytes.argtypes = [mp, C.c_int32]
         L.qv_vi_workspace_bytes.restype = C.c_size_t
         L.qv_value_iterate.argtypes = [mp, C.c_float, C.c_int32, vp, C.POINTER(C.c_double),
@@ -194,6 +196,12 @@ def qv_belief_update(model, batch, b, a, z, b_out, p_out, check, ws, stream=None
     return int(lib().qv_belief_update(C.byref(model.c), int(batch), _ptr(b), _ptr(a), _ptr(z),
                                       _ptr(b_out), _ptr(p_out), int(check), _ptr(ws),
                                       _nbytes(ws), _stream(stream)))
+
+
+def qv_belief_update_noalloc(model, batch, b, a, z, b_out, p_out, check, stream=None) -> int:
+    return int(lib().qv_belief_update_noalloc(C.byref(model.c), int(batch), _ptr(b), _ptr(a),
+                                              _ptr(z), _ptr(b_out), _ptr(p_out), int(check),
+                                              _stream(stream)))
 
 
 def qv_vi_workspace_bytes(model, max_sweeps: int) -> int:

@@ -4,6 +4,7 @@
 // the first reduces P(z|b,a) per (belief, band) into the workspace, the
 // second sums those partials in band order and writes the posterior.
 #include <algorithm>
+#include <mutex>
 
 #include "qv_internal.h"
 
@@ -196,6 +197,62 @@ int32_t belief_update_run(const qv_model *m, int batch, const float *b, const in
   if (herr) return QV_ERR_INVALID_ARG;
   return QV_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Belief update without allocation: the same kernels on a scratch region in
+// the library's own device memory instead of a caller workspace.  Each GPU
+// holds its own copy of `scratch` for the life of the process; host code
+// uses the device address that hipGetSymbolAddress returns for the current
+// device, never the array's name (a host-side stand-in).
+// ---------------------------------------------------------------------------
+constexpr int kBuMaxCells = 1 << 20;     // S = W*H at most
+constexpr int kBuMaxParts = 1 << 14;     // batch * bands at most
+constexpr size_t kBuScratchBytes =
+    ((size_t)kBuMaxCells * 4) + ((size_t)QV_MAX_ACTIONS * 256 * 4 + 256) +
+    ((size_t)kBuMaxParts * 4) + 256;
+static __device__ __align__(256) char scratch[kBuScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch[kMaxDevices];
+
+// The current device's copy of `scratch` (looked up once per device).
+static hipError_t scratch_ptr(char **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = p;
+  }
+  *out = (char *)g_scratch[dev];
+  return hipSuccess;
+}
+
+}  // namespace qv
+
+extern "C" int32_t qv_belief_update_noalloc(const qv_model *m, int32_t batch, const float *b,
+                                            const int32_t *a, const int32_t *z, float *b_out,
+                                            float *p_out, int32_t check, void *stream) {
+  using namespace qv;
+  const int32_t st = belief_update_args(m, batch, b, a, z, b_out, p_out);
+  if (st != QV_OK) return st;
+  const long long S = (long long)m->W * m->H;
+  const long long TH = tile_rows(m->W, m->H);
+  const long long tiles = (m->H + TH - 1) / TH;
+  if (S > kBuMaxCells || (long long)batch * tiles > kBuMaxParts) return QV_ERR_UNSUPPORTED;
+  if (belief_update_ws(m, batch) > kBuScratchBytes) return QV_ERR_UNSUPPORTED;
+  char *ws = nullptr;
+  const int32_t hs = hip_status(scratch_ptr(&ws));
+  if (hs != QV_OK) return hs;
+  return belief_update_run(m, batch, b, a, z, b_out, p_out, check, ws, (hipStream_t)stream);
+}
+
+namespace qv {
 
 // ===========================================================================
 // Differentiable filter: negative log-likelihood of logged observations under
