@@ -61,6 +61,7 @@ def parse():
     ap.add_argument("--side-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--filter-steps", type=int, default=5)
+    ap.add_argument("--loop-runs", type=int, default=20)
     return ap.parse_args()
 
 
@@ -375,6 +376,43 @@ def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_closed_loop(args, B, wl, torch, dev):
+    """Closed-loop runs of the experiment model of Sec. V on the synthetic
+    100 x 40 map (nine actions, 0.95 sensor, the paper's stage reward):
+    plan, act in the simulated world, observe, update the belief, until the
+    robot stops or 300 steps; the comparison-table quantities over the runs."""
+    from paper_1810_00204_amd.experiment import ClosedLoop, summarize
+    prob = wl.make_paper(seed=0)
+    Q, sweeps = gpu_q(B, torch, prob, dev)
+    cl = ClosedLoop(prob, Q)
+    cl.run(wl.Environment(prob, seed=999), seed=999, max_steps=5)   # warm-up
+    runs = [cl.run(wl.Environment(prob, seed=1000 + r), seed=2000 + r, max_steps=300)
+            for r in range(args.loop_runs)]
+    out = summarize(runs)
+    out.update({"workload": f"{prob.name}: synthetic {prob.W}x{prob.H} map, 9 actions, "
+                            "wall bits read correctly w.p. 0.95, r in {-2,-1,0}, gamma 0.95, "
+                            "start belief uniform over free cells, stop on the stay action",
+                "depth": prob.D, "samples_per_action": prob.n, "max_steps": 300,
+                "value_iteration_sweeps": sweeps})
+    return out
+
+
+def bench_fib(B, torch, dev, prob):
+    """The fast informed bound of the headline workload: sweeps to a 1e-6
+    relative residual in one cooperative launch."""
+    m = B.DeviceModel(prob, dev)
+    al = torch.empty(m.S * m.A, dtype=torch.float32, device=dev)
+    ws = torch.empty(B.qv_fib_workspace_bytes(m, 10000), dtype=torch.uint8, device=dev)
+    B.check(B.qv_fib_iterate(m, 1e-6, 10000, al, ws)[0], "qv_fib_iterate")   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, res, sw = B.qv_fib_iterate(m, 1e-6, 10000, al, ws)
+    B.check(st, "qv_fib_iterate")
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"sweeps": sw, "residual": res, "ms": ms, "sweeps_per_s": sw / (ms * 1e-3),
+            "cell_action_backups_per_s": sw * m.S * m.A / (ms * 1e-3)}
+
+
 def source_hash():
     from paper_1810_00204_amd.build import source_hash as h
     return h()
@@ -450,6 +488,11 @@ def main():
         progress(f"batch: {line['batch']['ms_per_batch']:.3f} ms per batch")
         line["filter"] = bench_filter(args, B, wl, torch, dev)
         progress(f"filter: {line['filter']['ms_per_eval']:.3f} ms per evaluation")
+        line["fib"] = bench_fib(B, torch, dev, prob)
+        progress(f"fib: {line['fib']['sweeps']} sweeps in {line['fib']['ms']:.2f} ms")
+        line["closed_loop"] = bench_closed_loop(args, B, wl, torch, dev)
+        progress(f"closed loop: {line['closed_loop']['runs']} runs, failure rate "
+                 f"{line['closed_loop']['failure_rate']:.2f}")
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)

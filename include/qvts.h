@@ -180,6 +180,18 @@ int32_t qv_fib_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *
                        double *residual_out, int32_t *sweeps_out, void *ws, size_t ws_bytes,
                        void *stream);
 
+/* ---- blind-policy lower bound (the L_V of Alg. 5 without a point set) ---
+ * One vector per action, the value of taking that action forever:
+ *   alpha^a(x) = R(x,a) + gamma * sum_x' T(x,a,x') alpha^a(x'),
+ * each action's own fixed point (no max over actions), by the same FP32
+ * sweeps, residual rule and layout as qv_fib_iterate.  max_a b.alpha^a is a
+ * lower bound on the optimal value of b.  Synchronous.
+ * Workspace: qv_blind_workspace_bytes(m, max_sweeps). */
+size_t qv_blind_workspace_bytes(const qv_model *m, int32_t max_sweeps);
+int32_t qv_blind_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *alpha,
+                         double *residual_out, int32_t *sweeps_out, void *ws, size_t ws_bytes,
+                         void *stream);
+
 /* ---- one planning step (Alg. 1 inner loop + getOptimalAction) ---------
  * Builds the QV-tree of depth D from b0 level by level: every V-node is
  * expanded with all |A| actions (Alg. 2); each Q-node predicts, forms
@@ -225,6 +237,69 @@ typedef struct qv_tree_layout {
 } qv_tree_layout;
 int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
                        qv_tree_layout *out /* host */);
+
+/* ---- best-first (anytime) search: Alg. 1 with Alg. 2-7, Sec. IV-C ----
+ * A QV-tree grown one V-node expansion at a time, always at the node the
+ * root's heuristic points to (findVNodeToExpand), in a node pool held in
+ * the workspace.  A new V-node (Alg. 5) takes U = max_a' b.U_table[.,a']
+ * and L = max_a' b.L_table[.,a'] (U_table, L_table: device [S*A] FP32,
+ * e.g. the FIB vectors of qv_fib_iterate and the blind-policy vectors of
+ * qv_blind_iterate), H = U - L and E = itself.  Expanding V-node v runs,
+ * per action a, the prediction, P(z|b,a), n draws keyed by (node id, depth,
+ * query_id) as in qv_plan_step, the distinct children Phi(b,a,z) with weight
+ * f/n and their bounds (Alg. 2-5); then every ancestor is updated (Alg. 6:
+ * U_Q = R(b,a) + gamma sum w U_child, L_Q likewise, H_Q / E_Q from the child
+ * of largest gamma w H; Alg. 7: U_V = max U_Q, L_V = max L_Q, H_V and E_V
+ * from the action of largest U_Q, first maximum on ties), and the next node
+ * to expand is the root's E.  The selection stays on the device, so a call
+ * of qv_search_expand enqueues all its expansions with no host round trip.
+ * Node ids: the first root is 0; each expansion reserves K = A*n ids, child
+ * (a, r) at base + a*n + r (r-th distinct z, ascending); a root made by
+ * qv_search_update takes one id.  Expansions stop (no-ops) once the pool of
+ * max_nodes cannot hold another K children or the root's E is already
+ * expanded.  Grids whose belief, prediction and bins fit in LDS only
+ * ((H+2)(W+2) + W*H + 4096 floats <= 152 KiB); larger ones get
+ * QV_ERR_UNSUPPORTED (qv_plan_step serves them).
+ *   qv_search_workspace_bytes: 0 if unsupported.
+ *   qv_search_init: a tree holding only the root b0 (device [S]); async.
+ *   qv_search_expand: `expansions` expansions; async.
+ *   qv_search_result: getOptimalAction, the lowest action whose L_Q at the
+ *     root is within 1e-9 of the largest (action_out device int32 [1]; -1 if
+ *     the root is not expanded), and the root's U_Q, L_Q (device FP32 [A]);
+ *     async.
+ *   qv_search_update: update(a, z) of Alg. 1: the root moves to its child
+ *     under (a, z) with that child's subtree; if z was not drawn there, a new
+ *     root Phi(b_root, a, z) is formed (QV_ERR_ZERO_LIKELIHOOD if P(z|b,a) =
+ *     0, QV_ERR_UNSUPPORTED if the pool is full, the tree then unchanged).
+ *     Synchronous.
+ *   qv_search_layout_of: where the node records are in the workspace. */
+typedef struct qv_search_layout {
+  int32_t n, K, A, S, max_nodes;
+  size_t sig, staytab, lm_wall;
+  size_t belief;      /* float [max_nodes][S] */
+  size_t valid, z, count, pz, weight, parent, depth, U, L, H, E, expanded, child_base;
+                      /* per node: int32 / float [max_nodes]; parent = v*A + a or -1 */
+  size_t rb, UQ, LQ, HQ, EQ;   /* per (node, action): [max_nodes][A] */
+  size_t ctl;         /* int32: root, select, next, expansions, flags, err */
+  size_t log;         /* int32 [max_nodes]: node expanded by expansion e */
+  size_t err;
+  size_t total_bytes;
+} qv_search_layout;
+size_t qv_search_workspace_bytes(const qv_model *m, int32_t n, int32_t max_nodes);
+int32_t qv_search_layout_of(const qv_model *m, int32_t n, int32_t max_nodes,
+                            qv_search_layout *out /* host */);
+int32_t qv_search_init(const qv_model *m, const float *U_table, const float *L_table,
+                       const float *b0, int32_t n, int32_t max_nodes, void *ws, size_t ws_bytes,
+                       void *stream);
+int32_t qv_search_expand(const qv_model *m, const float *U_table, const float *L_table,
+                         int32_t n, int32_t max_nodes, uint64_t seed, uint32_t query_id,
+                         int32_t expansions, void *ws, size_t ws_bytes, void *stream);
+int32_t qv_search_result(const qv_model *m, int32_t n, int32_t max_nodes, int32_t *action_out,
+                         float *rootU_out, float *rootL_out, void *ws, size_t ws_bytes,
+                         void *stream);
+int32_t qv_search_update(const qv_model *m, const float *U_table, const float *L_table,
+                         int32_t n, int32_t max_nodes, int32_t a, int32_t z, void *ws,
+                         size_t ws_bytes, void *stream);
 
 /* ---- batched planning ------------------------------------------------------
  * Many independent planning steps (Alg. 1 inner loop, as qv_plan_step), each

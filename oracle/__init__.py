@@ -98,6 +98,7 @@ def lib():
         L.qvo_filter_nll_grad.argtypes = [mp, dp, dp, C.c_int, C.c_int, dp, ip, ip,
                                          dp, dp, dp]
         L.qvo_fib_iterate.argtypes = [mp, dp, C.c_double, C.c_int, dp, dp, ip]
+        L.qvo_blind_iterate.argtypes = [mp, C.c_double, C.c_int, dp, dp, ip]
         L.qvo_fib_backup_cells.argtypes = [mp, dp, C.c_int, ip, dp]
         _lib = L
     return _lib
@@ -349,3 +350,143 @@ def fib_backup(prob, alpha, cells):
                                     _ptr(cells, C.c_int), _ptr(out, C.c_double))
     assert st == 0, st
     return out
+
+
+def blind_iterate(prob, tol=1e-12, max_sweeps=100000):
+    """Blind-policy vectors (the value of taking one action forever), the
+    lower bound of the search; returns (alpha [S, A] FP64, residual, sweeps)."""
+    m = Model(prob)
+    al = np.zeros((m.S, m.A))
+    res = C.c_double(0.0)
+    sw = C.c_int(0)
+    st = lib().qvo_blind_iterate(m.ref, float(tol), int(max_sweeps), _ptr(al, C.c_double),
+                                 C.byref(res), C.byref(sw))
+    assert st == 0, st
+    return al, res.value, sw.value
+
+
+class SearchTree:
+    """Best-first QV-tree (Alg. 1, 2, 5, 6, 7 with the heuristics of Sec. IV-C),
+    FP64.  Node ids follow the allocation rule of the search: the root is
+    node 0; each expansion reserves K = |A| n consecutive ids, child (a, r)
+    of the expansion taking id base + a n + r; a new root made by update(a, z)
+    takes one id.  Each node keeps its belief, parent (node, action), weight
+    f/n, observation, depth, bounds U, L, heuristic H and node to expand E;
+    each expanded node keeps per action R(b,a), U_Q, L_Q, H_Q and E_Q."""
+
+    def __init__(self, prob, Ut, Lt, n, seed, qid, b0, tie=1e-9):
+        self.prob, self.n, self.seed, self.qid = prob, n, seed, qid
+        self.Ut = _f64(Ut).reshape(prob.S, prob.A)
+        self.Lt = _f64(Lt).reshape(prob.S, prob.A)
+        # gamma as the model carries it (an FP32 input, widened exactly)
+        self.A, self.K, self.g = prob.A, prob.A * n, float(np.float32(prob.gamma))
+        self.nodes = {}
+        self.next = 0
+        self.log = []          # expanded node per expansion
+        self.margins = []      # closest decision of the update that set E[root]
+        self.root = self._new(_f64(b0), None, 1.0, -1, 0)
+
+    # Alg. 5: a new V-node takes U_V = V_U(b), L_V = V_L(b), H = U - L, E = itself
+    def _new(self, b, parent, w, z, depth, nid=None):
+        if nid is None:
+            nid = self.next
+            self.next += 1
+        U = float(np.max(b @ self.Ut))
+        L = float(np.max(b @ self.Lt))
+        self.nodes[nid] = dict(b=b, parent=parent, w=w, z=z, depth=depth, U=U, L=L, H=U - L,
+                               E=nid, q=None, kids=None)
+        return nid
+
+    def expand(self):
+        """findVNodeToExpand, expand, then update every ancestor (Alg. 1)."""
+        v = self.nodes[self.root]["E"]
+        nd = self.nodes[v]
+        if nd["q"] is not None:
+            return False
+        ex = expand_node(self.prob, nd["b"], nd["depth"], v, n=self.n, seed=self.seed,
+                         qid=self.qid, beliefs=True)
+        base = self.next
+        self.next += self.K
+        kids = []
+        for a in range(self.A):
+            row = []
+            for r in range(self.n):
+                c = a * self.n + r
+                if ex["valid"][c]:
+                    row.append(self._new(ex["beliefs"][c], (v, a), ex["count"][c] / self.n,
+                                         int(ex["z"][c]), nd["depth"] + 1, nid=base + c))
+            kids.append(row)
+        nd["kids"] = kids
+        nd["rb"] = ex["rb"].copy()
+        self.log.append(v)
+        margin = np.inf
+        p = v
+        while p is not None:
+            margin = min(margin, self._update(p))
+            par = self.nodes[p]["parent"]
+            p = None if par is None else par[0]
+        self.margins.append(margin)
+        return True
+
+    def _update(self, v):
+        """Alg. 6 for every action of v, then Alg. 7 (with gamma in the
+        Q-node backup and H(b,a) = 1 for the action of largest U_Q only);
+        returns the smallest relative gap among the argmax decisions taken."""
+        nd, g = self.nodes[v], self.g
+        UQ, LQ, HQ, EQ = [], [], [], []
+        gap = np.inf
+        for a in range(self.A):
+            kids = nd["kids"][a]
+            u = nd["rb"][a] + g * sum(self.nodes[c]["w"] * self.nodes[c]["U"] for c in kids)
+            l = nd["rb"][a] + g * sum(self.nodes[c]["w"] * self.nodes[c]["L"] for c in kids)
+            h = [g * self.nodes[c]["w"] * self.nodes[c]["H"] for c in kids]
+            j = int(np.argmax(h))
+            if len(h) > 1:
+                srt = np.sort(h)[::-1]
+                gap = min(gap, (srt[0] - srt[1]) / max(abs(srt[0]), 1e-30))
+            UQ.append(u)
+            LQ.append(l)
+            HQ.append(h[j])
+            EQ.append(self.nodes[kids[j]]["E"])
+        a_star = int(np.argmax(UQ))
+        srt = np.sort(UQ)[::-1]
+        if self.A > 1:
+            gap = min(gap, (srt[0] - srt[1]) / max(1.0, abs(srt[0])))
+        nd.update(q=dict(UQ=np.array(UQ), LQ=np.array(LQ), HQ=np.array(HQ), EQ=np.array(EQ)),
+                  U=float(max(UQ)), L=float(max(LQ)), H=float(HQ[a_star]), E=int(EQ[a_star]))
+        return gap
+
+    def action(self, tie=1e-9):
+        """getOptimalAction: the lowest action whose lower bound L_Q at the
+        root is within 1e-9 of the largest."""
+        q = self.nodes[self.root]["q"]
+        lq = q["LQ"]
+        return int(np.flatnonzero(lq >= lq.max() - tie)[0])
+
+    def update(self, a, z):
+        """update(a, z): the root moves to its child under (a, z), keeping that
+        subtree; if z was not drawn there, a new root is formed from Phi(b, a, z)."""
+        nd = self.nodes[self.root]
+        if nd["q"] is not None:
+            for c in nd["kids"][a]:
+                if self.nodes[c]["z"] == z:
+                    self.root = c
+                    self.nodes[c]["parent"] = None
+                    return c
+        b, p, st = belief_update(self.prob, nd["b"], a, z)
+        assert st == 0 and p[0] > 0
+        self.root = self._new(b[0], None, 1.0, z, nd["depth"] + 1)
+        return self.root
+
+
+def search(prob, Ut, Lt, expansions, n=None, seed=None, qid=None, b0=None):
+    """A best-first search of `expansions` expansions from b0 (default: the
+    problem's); returns the SearchTree."""
+    t = SearchTree(prob, Ut, Lt, prob.n if n is None else n,
+                   prob.seed if seed is None else seed,
+                   prob.query_id if qid is None else qid,
+                   prob.b0 if b0 is None else b0)
+    for _ in range(expansions):
+        if not t.expand():
+            break
+    return t

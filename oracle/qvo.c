@@ -339,6 +339,52 @@ int qvo_value_iterate(const qvo_model *m, double tol, int max_sweeps,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Blind-policy lower bound: for each action a, the value of taking a       */
+/* forever, alpha^a = R_a + gamma T_a alpha^a (each action's own fixed      */
+/* point, no max over actions), by Jacobi sweeps from 0.  Every such vector */
+/* is the value of a feasible policy, so max_a b.alpha^a bounds the optimal */
+/* value from below; it is the lower bound L_V of the search (Alg. 5) when  */
+/* no point-based bound is used.  Stops on r = 0 or r <= tol * max(1,       */
+/* max |alpha|) over free cells and all actions.                            */
+/* ------------------------------------------------------------------------ */
+int qvo_blind_iterate(const qvo_model *m, double tol, int max_sweeps, double *alpha,
+                      double *residual, int *sweeps) {
+  int S = m->W * m->H, A = m->A;
+  double *cur = (double *)calloc((size_t)S * A, sizeof(double));
+  double *nxt = (double *)calloc((size_t)S * A, sizeof(double));
+  if (!cur || !nxt) { free(cur); free(nxt); return QVO_ERR_MEM; }
+  double r = INFINITY;
+  int it = 0;
+  while (it < max_sweeps) {
+    it++;
+    double vmax = 0.0;
+    r = 0.0;
+    for (int s = 0; s < S; s++) {
+      for (int a = 0; a < A; a++) {
+        double v = 0.0;
+        if (!m->occ[s]) {
+          double ev = 0.0;
+          if (s == m->goal) ev = cur[(size_t)s * A + a];
+          else for (int k = 0; k < 9; k++) ev += m->slip[a * 9 + k] * cur[(size_t)qvo_dest(m, s, k) * A + a];
+          v = m->R[(size_t)s * A + a] + m->gamma * ev;
+          double d = fabs(v - cur[(size_t)s * A + a]);
+          if (d > r) r = d;
+          if (fabs(v) > vmax) vmax = fabs(v);
+        }
+        nxt[(size_t)s * A + a] = v;
+      }
+    }
+    double *t = cur; cur = nxt; nxt = t;
+    if (r == 0.0 || r <= tol * (vmax > 1.0 ? vmax : 1.0)) break;
+  }
+  memcpy(alpha, cur, sizeof(double) * (size_t)S * A);
+  free(cur); free(nxt);
+  if (residual) *residual = r;
+  if (sweeps) *sweeps = it;
+  return QVO_OK;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Fast informed bound (Sec. IV-A, the alpha-vector "Bellman equation" of    */
 /* FIB): one alpha vector per action,                                       */
 /*   alpha^a(x) = R(x,a) + gamma * sum_z max_a' sum_x' O(z|x') T(x,a,x')     */

@@ -40,6 +40,9 @@ EXPORTS = [
     "qv_vi_workspace_bytes", "qv_value_iterate",
     "qv_fib_workspace_bytes", "qv_fib_iterate",
     "qv_check_workspace_bytes", "qv_model_check",
+    "qv_blind_workspace_bytes", "qv_blind_iterate",
+    "qv_search_workspace_bytes", "qv_search_layout_of", "qv_search_init", "qv_search_expand",
+    "qv_search_result", "qv_search_update",
     "qv_plan_workspace_bytes", "qv_plan_step", "qv_plan_layout",
     "qv_timing_enable", "qv_timing_read",
     "qv_filter_workspace_bytes", "qv_filter_nll_grad",
@@ -73,6 +76,14 @@ class qv_tree_layout(C.Structure):
                 ("reward", C.c_size_t),
                 ("belief_offset", C.c_size_t * (QV_MAX_DEPTH + 1)),
                 ("total_bytes", C.c_size_t)]
+
+
+class qv_search_layout(C.Structure):
+    _fields_ = [("n", C.c_int32), ("K", C.c_int32), ("A", C.c_int32), ("S", C.c_int32),
+                ("max_nodes", C.c_int32)] + [(f, C.c_size_t) for f in (
+                    "sig", "staytab", "lm_wall", "belief", "valid", "z", "count", "pz",
+                    "weight", "parent", "depth", "U", "L", "H", "E", "expanded", "child_base",
+                    "rb", "UQ", "LQ", "HQ", "EQ", "ctl", "log", "err", "total_bytes")]
 
 
 class qv_kernel_time(C.Structure):
@@ -117,6 +128,25 @@ def lib():
         L.qv_check_workspace_bytes.restype = C.c_size_t
         L.qv_model_check.argtypes = [mp, vp, vp, C.c_size_t, vp]
         L.qv_model_check.restype = C.c_int32
+        L.qv_blind_workspace_bytes.argtypes = [mp, C.c_int32]
+        L.qv_blind_workspace_bytes.restype = C.c_size_t
+        L.qv_blind_iterate.argtypes = [mp, C.c_float, C.c_int32, vp, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_int32), vp, C.c_size_t, vp]
+        L.qv_blind_iterate.restype = C.c_int32
+        L.qv_search_workspace_bytes.argtypes = [mp, C.c_int32, C.c_int32]
+        L.qv_search_workspace_bytes.restype = C.c_size_t
+        L.qv_search_layout_of.argtypes = [mp, C.c_int32, C.c_int32, C.POINTER(qv_search_layout)]
+        L.qv_search_layout_of.restype = C.c_int32
+        L.qv_search_init.argtypes = [mp, vp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+        L.qv_search_init.restype = C.c_int32
+        L.qv_search_expand.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
+                                       C.c_int32, vp, C.c_size_t, vp]
+        L.qv_search_expand.restype = C.c_int32
+        L.qv_search_result.argtypes = [mp, C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_size_t, vp]
+        L.qv_search_result.restype = C.c_int32
+        L.qv_search_update.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                       vp, C.c_size_t, vp]
+        L.qv_search_update.restype = C.c_int32
         L.qv_fib_workspace_bytes.argtypes = [mp, C.c_int32]
         L.qv_fib_workspace_bytes.restype = C.c_size_t
         L.qv_fib_iterate.argtypes = [mp, C.c_float, C.c_int32, vp, C.POINTER(C.c_double),
@@ -226,6 +256,56 @@ def qv_model_check(model, b0, ws, stream=None) -> int:
     """Device validation of the model's arrays and (if given) the start belief."""
     return int(lib().qv_model_check(C.byref(model.c), _ptr(b0) if b0 is not None else None,
                                     _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_blind_workspace_bytes(model, max_sweeps: int) -> int:
+    return int(lib().qv_blind_workspace_bytes(C.byref(model.c), int(max_sweeps)))
+
+
+def qv_blind_iterate(model, tol, max_sweeps, alpha, ws, stream=None):
+    """Returns (status, residual, sweeps)."""
+    res = C.c_double(0.0)
+    sw = C.c_int32(0)
+    st = lib().qv_blind_iterate(C.byref(model.c), float(tol), int(max_sweeps), _ptr(alpha),
+                                C.byref(res), C.byref(sw), _ptr(ws), _nbytes(ws),
+                                _stream(stream))
+    return int(st), res.value, sw.value
+
+
+def qv_search_workspace_bytes(model, n: int, max_nodes: int) -> int:
+    return int(lib().qv_search_workspace_bytes(C.byref(model.c), int(n), int(max_nodes)))
+
+
+def qv_search_layout_of(model, n: int, max_nodes: int):
+    out = qv_search_layout()
+    st = lib().qv_search_layout_of(C.byref(model.c), int(n), int(max_nodes), C.byref(out))
+    return int(st), out
+
+
+def qv_search_init(model, Ut, Lt, b0, n, max_nodes, ws, stream=None) -> int:
+    return int(lib().qv_search_init(C.byref(model.c), _ptr(Ut), _ptr(Lt), _ptr(b0), int(n),
+                                    int(max_nodes), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_search_expand(model, Ut, Lt, n, max_nodes, seed, query_id, expansions, ws,
+                     stream=None) -> int:
+    return int(lib().qv_search_expand(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(n),
+                                      int(max_nodes), C.c_uint64(int(seed) & (2 ** 64 - 1)),
+                                      C.c_uint32(int(query_id) & (2 ** 32 - 1)),
+                                      int(expansions), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_search_result(model, n, max_nodes, action_out, rootU_out, rootL_out, ws,
+                     stream=None) -> int:
+    return int(lib().qv_search_result(C.byref(model.c), int(n), int(max_nodes),
+                                      _ptr(action_out), _ptr(rootU_out), _ptr(rootL_out),
+                                      _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_search_update(model, Ut, Lt, n, max_nodes, a, z, ws, stream=None) -> int:
+    return int(lib().qv_search_update(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(n),
+                                      int(max_nodes), int(a), int(z), _ptr(ws), _nbytes(ws),
+                                      _stream(stream)))
 
 
 def qv_fib_workspace_bytes(model, max_sweeps: int) -> int:

@@ -248,6 +248,28 @@ int32_t qv_fib_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *
   return QV_OK;
 }
 
+size_t qv_blind_workspace_bytes(const qv_model *m, int32_t max_sweeps) {
+  return qv_fib_workspace_bytes(m, max_sweeps);
+}
+
+int32_t qv_blind_iterate(const qv_model *m, float tol, int32_t max_sweeps, float *alpha,
+                         double *residual_out, int32_t *sweeps_out, void *ws, size_t ws_bytes,
+                         void *stream) {
+  int32_t st = check_model(m);
+  if (st != QV_OK) return st;
+  if (max_sweeps < 1 || !(tol >= 0.f) || !alpha || !residual_out || !sweeps_out)
+    return QV_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, fib_ws(m, max_sweeps))) return QV_ERR_WORKSPACE;
+  const DevModel dm = make_dev_model(m);
+  double r = 0.0;
+  int k = 0;
+  st = hip_status(run_fib(dm, tol, max_sweeps, alpha, &r, &k, (char *)ws, (hipStream_t)stream, 1));
+  if (st != QV_OK) return st;
+  *residual_out = r;
+  *sweeps_out = k;
+  return QV_OK;
+}
+
 size_t qv_plan_workspace_bytes(const qv_model *m, int32_t D, int32_t n, int32_t flags) {
   if (check_model(m) != QV_OK || D < 0 || D > QV_MAX_DEPTH || n < 1 || n > QV_MAX_SAMPLES)
     return 0;

@@ -131,6 +131,23 @@ struct BatchPrep {
   int nq, nqueue;
 };
 
+// Best-first search: the node pool and control words in the workspace.
+struct SearchArgs {
+  int n, K, NV;                 // samples per action, |A| n, node capacity
+  uint32_t key0, key1, qid;     // Philox key and query id of the draws
+  const float *Ut, *Lt;         // upper / lower bound tables [S*A]
+  const uint32_t *sig;
+  const float *staytab;
+  const uint32_t *lm_wall;
+  float *bel;                   // [NV][S] beliefs
+  int32_t *valid, *z, *count, *parent, *depth, *E, *expanded, *cbase;   // [NV]
+  float *pz, *w, *U, *L, *H;                                            // [NV]
+  float *rb, *UQ, *LQ, *HQ;     // [NV][A] Q-node records
+  int32_t *EQ;                  // [NV][A]
+  int32_t *ctl;                 // root, select, next, expansions, flags, err
+  int32_t *log;                 // [NV] node expanded by each expansion
+};
+
 int tile_rows(int W, int H);
 DevModel make_dev_model(const qv_model *m);
 int32_t check_model(const qv_model *m);
@@ -157,6 +174,12 @@ hipError_t launch_plan(const qv_model *m, const float *Q, const float *b0, int D
                        float *rootQ_out, char *ws, const PlanLayout &L, hipStream_t st);
 hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
                        hipStream_t st);
+hipError_t launch_prep_lm(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
+                          uint32_t *lm_wall, hipStream_t st);
+// what: 0 init (b0), 1 one expansion (expand + update), 2 result, 3 update(a, z)
+hipError_t launch_search(int what, const DevModel &m, const SearchArgs &sa, const float *b0,
+                         int a, int z, int32_t *action, float *rootU, float *rootL,
+                         hipStream_t st);
 hipError_t launch_belief_update(const DevModel &dm, int batch, const float *b,
                                 const int32_t *a, const int32_t *z, float *b_out,
                                 float *p_out, char *ws, hipStream_t st);
@@ -173,7 +196,7 @@ hipError_t run_value_iteration(const DevModel &dm, float tol, int max_sweeps, fl
                                double *residual, int *sweeps, char *ws, hipStream_t st);
 size_t vi_ws(const qv_model *m, int max_sweeps);
 hipError_t run_fib(const DevModel &dm, float tol, int max_sweeps, float *alpha,
-                   double *residual, int *sweeps, char *ws, hipStream_t st);
+                   double *residual, int *sweeps, char *ws, hipStream_t st, int op = 0);
 size_t fib_ws(const qv_model *m, int max_sweeps);
 int32_t run_model_check(const DevModel &m, const float *b0, bool check_r, char *rec,
                         hipStream_t st);

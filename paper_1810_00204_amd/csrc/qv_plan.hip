@@ -21,6 +21,7 @@
 // all cross-workgroup sums run in a fixed order, so results are bitwise
 // reproducible.
 #include <algorithm>
+#include <cstdlib>
 
 #include "qv_internal.h"
 
@@ -371,6 +372,13 @@ hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_
   return hipGetLastError();
 }
 
+hipError_t launch_prep_lm(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
+                          uint32_t *lm_wall, hipStream_t st) {
+  const PrepExtra x = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, lm_wall};
+  prep_launch(dm, sig, staytab, err, x, st);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // shared pieces of the tiled kernels
 // ---------------------------------------------------------------------------
@@ -633,11 +641,14 @@ __device__ __forceinline__ void obs_page(int g, int L, const float *otab, float 
 // one child record per distinct z (ascending) with its frequency (Alg. 3/4).
 // One full wavefront; out (LDS) optional; p0tab: 32 floats of LDS (P(zw, no
 // landmark), then the wall-likelihood table).
+// cbase >= 0 places the child records at cbase + a*n instead of the
+// capacity slots p*K + a*n (p still keys the draws).
 __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
-                             const uint32_t *lw, const float *lvv, float *p0tab, DrawOut *out) {
+                             const uint32_t *lw, const float *lvv, float *p0tab, DrawOut *out,
+                             int cbase = -1) {
   const int lane = threadIdx.x & (kWave - 1);
   const int n = lv.n;
-  const int cb = p * lv.K + a * n;
+  const int cb = (cbase >= 0 ? cbase : p * lv.K) + a * n;
   // the model's sensor scalars, once, as uniform registers
   float fl[4];
 #pragma unroll
@@ -1075,6 +1086,237 @@ __global__ __launch_bounds__(kBlock) void k_update(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ BandShared sh;
   update_item(m, lv, decode_item(xcd_local_id(blockIdx.x, gridDim.x), lv, m.A), smem, sh);
+}
+
+// ---------------------------------------------------------------------------
+// Banded inner levels with every action of a parent in one item: a
+// workgroup per (parent slot, band) loads the parent's band once and serves
+// all |A| Q-nodes from it, instead of one item per (parent, band, action)
+// that each load the band.  The per-action arithmetic is that of stats_item
+// and update_item, in the same order, so results are bitwise the same.
+// ---------------------------------------------------------------------------
+constexpr int kParentCells = 8;   // cells per thread of a band: at most 2048 / kBlock
+
+struct ParentShared {
+  float stay[QV_MAX_ACTIONS * 256];   // stay probability by neighbour pattern, per action
+  float red[QV_MAX_ACTIONS][kBlock / kWave];
+  int zr[QV_MAX_ACTIONS * QV_MAX_SAMPLES];
+  float inv[QV_MAX_ACTIONS * QV_MAX_SAMPLES];
+  int U[QV_MAX_ACTIONS];
+  int last;
+};
+
+// Dynamic LDS floats of k_stats_parent: the band and the per-thread bins,
+// or the four wavefronts' sampler tables.
+__host__ __device__ inline size_t stats_parent_lds_floats(int W, int TH, int L) {
+  const size_t a = (size_t)(TH + 2) * (W + 2) + 16 * kBlock;
+  const size_t b = (size_t)(kBlock / kWave) * (2 * (size_t)L + 32);
+  return a > b ? a : b;
+}
+
+__device__ void stats_parent_item(const DevModel &m, const LevelArgs &lv, int p, int tile,
+                                  float *smem, ParentShared &sh) {
+  const int A = m.A, tid = threadIdx.x;
+  if (!lv.pvalid[p]) {
+    // children of an absent parent are marked absent by its first band
+    if (tile == 0) {
+      for (int i = tid; i < lv.K; i += kBlock) {
+        const int c = p * lv.K + i;
+        lv.cvalid[c] = 0;
+        lv.cz[c] = -1;
+        lv.ccount[c] = 0;
+        lv.cpz[c] = 0.f;
+      }
+      for (int a = 0; a < A; ++a) list_absent_children(lv, p * lv.K + a * lv.n);
+    }
+    return;
+  }
+  const int W = m.W, BW = W + 2;
+  const int y0 = tile * lv.TH;
+  const int th = min(lv.TH, m.H - y0);
+  float *band = smem;
+  float *hist = band + (lv.TH + 2) * BW;   // [16][kBlock] per-thread bins
+  const float *b = lv.pbel + (size_t)p * m.S;
+  for (int i = tid; i < A * 256; i += kBlock) sh.stay[i] = lv.staytab[i];
+  load_band(m, lv.sig, b, y0, th, band, BW, lv.d == 0);
+  const int ncell = th * W;
+  const float rW = 1.0f / (float)W;
+  const int t00 = y0 * W;
+  // the thread's cells (the same ones, in the same order, as stats_item's)
+  // with their rows of R: all loads go out before any is used
+  const int jn = (ncell + kBlock - 1) / kBlock;   // uniform
+  uint32_t sg[kParentCells];
+  float bt[kParentCells];
+  float racc[QV_MAX_ACTIONS];
+#pragma unroll
+  for (int a = 0; a < QV_MAX_ACTIONS; ++a) racc[a] = 0.f;
+#pragma unroll
+  for (int j = 0; j < kParentCells; ++j) {
+    if (j >= jn) break;
+    const int i = tid + j * kBlock;
+    const bool ok = i < ncell;
+    const int t = t00 + (ok ? i : 0);
+    const uint32_t sv = lv.sig[t];
+    const float bv = b[t];
+    sg[j] = ok ? sv : 0u;
+    bt[j] = ok ? bv : 0.f;
+  }
+  // R(b,a) = sum_x R(x,a) b(x) for every action (Sec. III), cells in order
+#pragma unroll
+  for (int j = 0; j < kParentCells; ++j) {
+    if (j >= jn) break;
+    const int i = tid + j * kBlock;
+    const float *row = m.R + (size_t)(t00 + (i < ncell ? i : 0)) * A;
+    float rv[QV_MAX_ACTIONS];
+#pragma unroll
+    for (int a = 0; a < QV_MAX_ACTIONS; ++a) rv[a] = row[a < A ? a : 0];
+    if (i < ncell) {
+#pragma unroll
+      for (int a = 0; a < QV_MAX_ACTIONS; ++a)
+        if (a < A) racc[a] = fmaf(bt[j], rv[a], racc[a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < QV_MAX_ACTIONS; ++a) {
+    if (a >= A) break;
+    const float r = wave_sum(racc[a]);
+    if ((tid & (kWave - 1)) == 0) sh.red[a][tid / kWave] = r;
+  }
+  __syncthreads();
+  const float rho = m.lm_p;
+  const int L = m.L;
+  for (int a = 0; a < A; ++a) {
+    const float *sl = &m.slip[a * 9];
+    const float *stay_a = sh.stay + a * 256;
+#pragma unroll
+    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+    float h0 = 0.f;
+#pragma unroll
+    for (int j = 0; j < kParentCells; ++j) {
+      const int i = tid + j * kBlock;
+      if (j >= jn || i >= ncell) break;
+      const int ly = fdiv(i, W, rW), lx = i - ly * W;
+      const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
+      const uint32_t lm = sig_lm(sg[j]);
+      float contrib = bp;
+      if (lm && lm <= (uint32_t)L) {
+        contrib = bp * (1.f - rho);
+        st_coherent(lv.lmv + ((size_t)p * A + a) * L + lm - 1, bp);
+      }
+      const uint32_t w = sig_wall(sg[j]);
+      if (w == 0u)
+        h0 += contrib;
+      else
+        hist[w * kBlock + tid] += contrib;
+    }
+    hist[tid] = h0;
+    __syncthreads();
+    float *part = lv.part + (((size_t)p * A + a) * lv.tiles + tile) * 17;
+    {
+      const int k = tid & 15, rot = (tid >> 4) & 3;
+      const float *hb = hist + (tid >> 4) * kBlock;
+      float sum = 0.f;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sum += hb[k + 16 * ((i + rot) & 15)];
+      sum = group_sum<16>(sum);
+      if ((tid & 15) == 15) st_coherent(part + (tid >> 4), sum);
+      if (tid == 0)
+        st_coherent(part + 16, (sh.red[a][0] + sh.red[a][1]) + (sh.red[a][2] + sh.red[a][3]));
+    }
+    __syncthreads();   // the bins are reused by the next action
+  }
+  // the last band of this parent to finish draws for every action
+  wait_mem();
+  __syncthreads();
+  if (tid == 0) sh.last = (count_arrival(&lv.ctr[p * A]) == lv.tiles - 1);
+  __syncthreads();
+  if (!sh.last) return;
+  const int wave = tid / kWave;
+  float *scratch = smem + (size_t)wave * (2 * L + 32);
+  for (int a = wave; a < A; a += kBlock / kWave) sample_qnode(m, lv, p, a, scratch);
+  if (tid == 0) lv.ctr[p * A] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_stats_parent(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ ParentShared sh;
+  const int idx = xcd_local_id(blockIdx.x, gridDim.x);
+  const int p = idx / lv.tiles;
+  stats_parent_item(m, lv, p, idx - p * lv.tiles, smem, sh);
+}
+
+__device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p, int tile,
+                                   float *smem, ParentShared &sh) {
+  if (!lv.pvalid[p]) return;
+  const int A = m.A, n = lv.n, K = lv.K, tid = threadIdx.x;
+  // the drawn children of every action (valid ones are packed first)
+  for (int i = tid; i < K; i += kBlock) {
+    const int c = p * K + i;
+    const int v = lv.cvalid[c];
+    sh.zr[i] = v ? lv.cz[c] : 0;
+    sh.inv[i] = v ? 1.0f / lv.cpz[c] : 0.f;
+  }
+  if (tid < A) {
+    int U = 0;
+    for (int r = 0; r < n; ++r) U += lv.cvalid[p * K + tid * n + r] ? 1 : 0;
+    sh.U[tid] = U;
+  }
+  for (int i = tid; i < A * 256; i += kBlock) sh.stay[i] = lv.staytab[i];
+  const int W = m.W, BW = W + 2, S = m.S;
+  const int y0 = tile * lv.TH;
+  const int th = min(lv.TH, m.H - y0);
+  float *band = smem;
+  const float *b = lv.pbel + (size_t)p * S;
+  load_band(m, lv.sig, b, y0, th, band, BW, lv.d == 0);
+  __syncthreads();
+  const int ncell = th * W;
+  const float rW = 1.0f / (float)W;
+  const float rho = m.lm_p;
+  const int t00 = y0 * W;
+  for (int i0 = tid; i0 < ncell; i0 += kCellBatch * kBlock) {
+    uint32_t sg[kCellBatch];
+    float bt[kCellBatch];
+#pragma unroll
+    for (int j = 0; j < kCellBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      const bool ok = i < ncell;
+      const int t = t00 + (ok ? i : 0);
+      const uint32_t sv = lv.sig[t];
+      const float bv = b[t];
+      sg[j] = ok ? sv : 0u;
+      bt[j] = ok ? bv : 0.f;
+    }
+    for (int a = 0; a < A; ++a) {
+      const int U = sh.U[a];
+      if (U == 0) continue;
+      const float *sl = &m.slip[a * 9];
+      const float *stay_a = sh.stay + a * 256;
+      const int cb = p * K + a * n;
+#pragma unroll
+      for (int j = 0; j < kCellBatch; ++j) {
+        const int i = i0 + j * kBlock;
+        if (i >= ncell) break;
+        const int ly = fdiv(i, W, rW), lx = i - ly * W;
+        const int t = t00 + i;
+        const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
+        const uint32_t w = sig_wall(sg[j]), lm = sig_lm(sg[j]);
+        for (int r = 0; r < U; ++r) {
+          const int zz = sh.zr[a * n + r];
+          const float o = wall_lik(m.flip, (uint32_t)(zz & 15), w) *
+                          lm_lik(rho, (uint32_t)(zz >> 4), lm);
+          lv.cbel[(size_t)(cb + r) * S + t] = o * bp * sh.inv[a * n + r];
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_parent(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ ParentShared sh;
+  const int idx = xcd_local_id(blockIdx.x, gridDim.x);
+  const int p = idx / lv.tiles;
+  update_parent_item(m, lv, p, idx - p * lv.tiles, smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2242,6 +2484,12 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
 
   const size_t lds_band = band_bytes(m.W, TH);
   const size_t lds_stats = lds_band + 16 * kBlock * sizeof(float);
+  // banded inner levels take one item per (parent, band) over all actions;
+  // QVTS_PER_ACTION_ITEMS=1 selects one item per (parent, band, action)
+  const char *pa_env = std::getenv("QVTS_PER_ACTION_ITEMS");
+  const bool per_action = pa_env && std::atoi(pa_env) == 1;
+  const bool per_parent = !per_action && (long long)TH * m.W <= kParentCells * kBlock;
+  const size_t lds_spar = stats_parent_lds_floats(m.W, TH, m.L) * sizeof(float);
   const size_t lds_leaf = leaf_lds_bytes(m.W, TH, K, A);
   const int q_vec = (A == 4 || A == 8) && ((uintptr_t)Q % 16 == 0);
   const size_t lds_small = small_lds_bytes(m.W, m.H, A, n, m.L);
@@ -2364,8 +2612,14 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       continue;
     }
     const unsigned nblk = (unsigned)((long long)lv.nslots * tiles * A);
-    QV_LAUNCH_L(d, k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
-    if (!last || store_leaves) {
+    const unsigned npar = (unsigned)((long long)lv.nslots * tiles);
+    if (per_parent)
+      QV_LAUNCH_L(d, k_stats_parent, dim3(npar), dim3(kBlock), lds_spar, st, m, lv);
+    else
+      QV_LAUNCH_L(d, k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
+    if ((!last || store_leaves) && per_parent) {
+      QV_LAUNCH_L(d, k_update_parent, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
+    } else if (!last || store_leaves) {
       QV_LAUNCH_L(d, k_update, dim3(nblk), dim3(kBlock), lds_band, st, m, lv);
     } else if (A <= 4) {
       QV_LAUNCH_L(d, k_leaf<4>, dim3(nblk), dim3(kBlock), lds_leaf, st, m, lv, tr);
@@ -2583,6 +2837,426 @@ hipError_t launch_batch_out(int nq, const int32_t *act_in, const float *rq_in, i
   if (n == 0) return hipSuccess;
   QV_LAUNCH(k_batch_out, dim3((n + 255) / 256), dim3(256), 0, st, nq, act_in, rq_in, act_out,
             rq_out);
+  return hipGetLastError();
+}
+
+}  // namespace qv
+
+namespace qv {
+
+// ===========================================================================
+// Best-first (anytime) QV-tree search, Alg. 1 with Alg. 2-7 and the
+// heuristics of Sec. IV-C.  The tree lives in a node pool in the workspace:
+// node 0 is the first root; every expansion reserves K = |A| n consecutive
+// node ids (child (a, r) of the expansion at base + a n + r, as the level
+// kernels place children in capacity slots); a root made by update(a, z)
+// takes one id.  Which node to expand next is kept on the device
+// (ctl[kCtlSelect] = E of the root), so a run of expansions is a chain of
+// launches with no host round trip: k_search_expand (one workgroup per
+// action of the selected node: prediction, P(z|b,a), draws, children
+// Phi(b,a,z) and their bounds U = max_a' b.U_table, L = max_a' b.L_table)
+// then k_search_update (Alg. 6/7 at the node and at every ancestor, one
+// thread), which selects the next node.  Grids whose belief, predicted
+// belief and bins fit in LDS only (the anytime search serves small and
+// medium maps; the level-synchronous plan covers the large ones).
+// ===========================================================================
+constexpr int kCtlRoot = 0, kCtlSelect = 1, kCtlNext = 2, kCtlExpansions = 3, kCtlFlags = 4,
+              kCtlErr = 5;
+constexpr int kSearchFull = 1;     // the pool cannot hold another expansion
+constexpr int kSearchDone = 2;     // the node to expand is already expanded
+
+__host__ __device__ inline size_t search_lds_floats(int W, int H) {
+  const size_t band = (size_t)(H + 2) * (W + 2);
+  const size_t S = (size_t)W * H;
+  return band + ((S + 3) & ~(size_t)3) + 16 * (size_t)kBlock;
+}
+
+// Bounds of a belief held as v(t) = scale * o(t) * bp(t) over all cells:
+// block sums of v(t) Ut(t, a') and v(t) Lt(t, a') (FP32, fixed order), then
+// the maxima over a' (lane 0 of thread 0 gets them).  o(t) = 1 when zr < 0.
+__device__ void search_bounds(const DevModel &m, const SearchArgs &sa, const float *bpl,
+                              int zr, float scale, float *out_b, float *red, float &U,
+                              float &L) {
+  const int A = m.A, S = m.S;
+  float acc[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) acc[i] = 0.f;
+  const uint32_t zw = (uint32_t)(zr & 15), zl = (uint32_t)(zr >> 4);
+  for (int t = threadIdx.x; t < S; t += kBlock) {
+    const uint32_t sg = sa.sig[t];
+    float o = 1.f;
+    if (zr >= 0) o = wall_lik(m.flip, zw, sig_wall(sg)) * lm_lik(m.lm_p, zl, sig_lm(sg));
+    const float v = o * bpl[t] * scale;
+    if (out_b) out_b[t] = v;
+#pragma unroll
+    for (int c = 0; c < QV_MAX_ACTIONS; ++c) {
+      if (c < A) {
+        acc[c] = fmaf(v, sa.Ut[(size_t)t * A + c], acc[c]);
+        acc[16 + c] = fmaf(v, sa.Lt[(size_t)t * A + c], acc[16 + c]);
+      }
+    }
+  }
+  const float tot = block_sum32(acc, red);
+  // thread c < 32 holds the total of value c; the maxima through LDS
+  if (threadIdx.x < 32) red[threadIdx.x] = tot;
+  __syncthreads();
+  U = -INFINITY;
+  L = -INFINITY;
+  for (int c = 0; c < A; ++c) {
+    U = fmaxf(U, red[c]);
+    L = fmaxf(L, red[16 + c]);
+  }
+  __syncthreads();
+}
+
+// The new node c's records (its belief is already in place).
+__device__ __forceinline__ void search_new_node(const SearchArgs &sa, int c, int parentq,
+                                                float w, int z, int depth, float U, float L) {
+  sa.valid[c] = 1;
+  sa.parent[c] = parentq;
+  sa.w[c] = w;
+  sa.z[c] = z;
+  sa.depth[c] = depth;
+  sa.U[c] = U;
+  sa.L[c] = L;
+  sa.H[c] = U - L;
+  sa.E[c] = c;
+  sa.expanded[c] = 0;
+  sa.cbase[c] = -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_search_init(DevModel m, SearchArgs sa,
+                                                        const float *b0) {
+  __shared__ float red[4 * 32];
+  extern __shared__ float smem[];
+  float *bpl = smem;
+  for (int t = threadIdx.x; t < m.S; t += kBlock) {
+    // the start belief, with no mass on blocked cells
+    bpl[t] = (sa.sig[t] & kSigFree) ? b0[t] : 0.f;
+  }
+  __syncthreads();
+  float U, L;
+  search_bounds(m, sa, bpl, -1, 1.f, sa.bel, red, U, L);
+  if (threadIdx.x == 0) {
+    search_new_node(sa, 0, -1, 1.f, -1, 0, U, L);
+    sa.pz[0] = 0.f;
+    sa.count[0] = 0;
+    sa.ctl[kCtlRoot] = 0;
+    sa.ctl[kCtlSelect] = 0;
+    sa.ctl[kCtlNext] = 1;
+    sa.ctl[kCtlExpansions] = 0;
+    sa.ctl[kCtlFlags] = 0;
+    sa.ctl[kCtlErr] = 0;
+  }
+}
+
+// One workgroup per action a of the selected node v (Alg. 2-5).
+__global__ __launch_bounds__(kBlock) void k_search_expand(DevModel m, SearchArgs sa) {
+  extern __shared__ float smem[];
+  __shared__ float s_stay[256];
+  __shared__ float s_red[4 * 32];
+  __shared__ float s_H[17];
+  __shared__ DrawOut s_draw;
+  const int a = blockIdx.x, tid = threadIdx.x;
+  const int v = sa.ctl[kCtlSelect], base = sa.ctl[kCtlNext];
+  if (sa.ctl[kCtlFlags] || v < 0 || sa.expanded[v] || base + sa.K > sa.NV) return;
+  const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2;
+  float *band = smem;
+  float *bpl = band + (size_t)(H + 2) * BW;
+  float *hist = bpl + ((S + 3) & ~3);   // [16][kBlock] per-thread bins
+  const float *b = sa.bel + (size_t)v * S;
+  LevelArgs lv{};
+  lv.d = sa.depth[v];
+  lv.n = sa.n;
+  lv.K = sa.K;
+  lv.key0 = sa.key0;
+  lv.key1 = sa.key1;
+  lv.qid = sa.qid;
+  lv.cvalid = sa.valid;
+  lv.cz = sa.z;
+  lv.ccount = sa.count;
+  lv.cpz = sa.pz;
+  s_stay[tid] = sa.staytab[a * 256 + tid];
+  load_band(m, sa.sig, b, 0, H, band, BW, false);
+#pragma unroll
+  for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+  __syncthreads();
+  const float rW = 1.0f / (float)W;
+  const float *sl = &m.slip[a * 9];
+  const float rho = m.lm_p;
+  const float bgoal = m.goal >= 0 ? b[m.goal] : 0.f;
+  // b' (slip stencil), R(b,a) and the histogram of b' by true wall reading
+  // (landmark cells with their "no landmark" factor), as the level kernels
+  float racc = 0.f, h0 = 0.f;
+  for (int t = tid; t < S; t += kBlock) {
+    const uint32_t sg = sa.sig[t];
+    const int ly = fdiv(t, W, rW), lx = t - ly * W;
+    const float bt = t == m.goal ? bgoal : band[(ly + 1) * BW + lx + 1];
+    racc = fmaf(bt, m.R[(size_t)t * A + a], racc);
+    const float bp = predict_cell_v(band, BW, ly, lx, sg, sl, s_stay, bt);
+    bpl[t] = bp;
+    const uint32_t lm = sig_lm(sg);
+    const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
+    const uint32_t w = sig_wall(sg);
+    if (w == 0u)
+      h0 += contrib;
+    else
+      hist[w * kBlock + tid] += contrib;
+  }
+  hist[tid] = h0;
+  racc = wave_sum(racc);
+  if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = racc;
+  __syncthreads();
+  {
+    const int k = tid & 15, rot = (tid >> 4) & 3;
+    const float *hb = hist + (tid >> 4) * kBlock;
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sum += hb[k + 16 * ((i + rot) & 15)];
+    sum = group_sum<16>(sum);
+    if ((tid & 15) == 15) s_H[tid >> 4] = sum;
+    if (tid == 0) s_H[16] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  }
+  __syncthreads();
+  // draws (Alg. 3/4) by wavefront 0, keyed by the node id and its depth; the
+  // landmark tables go where the bins were
+  if (tid < kWave) {
+    uint32_t *lw = (uint32_t *)hist;
+    float *lvv = hist + m.L;
+    for (int l = tid; l < m.L; l += kWave) {
+      lw[l] = sa.lm_wall[l];
+      const int c = m.lm_cell[l];
+      lvv[l] = (c >= 0 && c < S) ? bpl[c] : 0.f;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    sample_draws(m, lv, v, a, tid < 17 ? s_H[tid] : 0.f, lw, lvv, hist + 2 * m.L, &s_draw,
+                 base);
+  }
+  if (tid == 0) sa.rb[(size_t)v * A + a] = s_H[16];
+  __syncthreads();
+  // children Phi(b,a,z_r) and their bounds (Alg. 3, Alg. 5)
+  for (int r = 0; r < s_draw.U; ++r) {
+    const int c = base + a * sa.n + r;
+    float U, L;
+    search_bounds(m, sa, bpl, s_draw.z[r], s_draw.inv[r], sa.bel + (size_t)c * S, s_red, U, L);
+    if (tid == 0)
+      search_new_node(sa, c, v * A + a, (float)s_draw.count[r] / (float)sa.n, s_draw.z[r],
+                      lv.d + 1, U, L);
+  }
+}
+
+// Alg. 6 for every action of expanded node v, then Alg. 7 (gamma in the
+// Q-node backup; H(b,a) = 1 only for the action of largest U_Q; the child
+// of largest gamma * weight * H gives H_Q and E_Q; first maximum on ties).
+__device__ void search_update_node(const DevModel &m, const SearchArgs &sa, int v) {
+  const int A = m.A, n = sa.n, cb = sa.cbase[v];
+  const float g = m.gamma;
+  float bestU = -INFINITY, bestL = -INFINITY, Hs = 0.f;
+  int Es = v;
+  for (int a = 0; a < A; ++a) {
+    const float r = sa.rb[(size_t)v * A + a];
+    float su = 0.f, sl = 0.f, hq = -INFINITY;
+    int eq = v;
+    for (int i = 0; i < n; ++i) {
+      const int c = cb + a * n + i;
+      if (!sa.valid[c]) continue;
+      su = fmaf(sa.w[c], sa.U[c], su);
+      sl = fmaf(sa.w[c], sa.L[c], sl);
+      const float h = g * sa.w[c] * sa.H[c];
+      if (h > hq) {
+        hq = h;
+        eq = sa.E[c];
+      }
+    }
+    const float uq = fmaf(g, su, r), lq = fmaf(g, sl, r);
+    sa.UQ[(size_t)v * A + a] = uq;
+    sa.LQ[(size_t)v * A + a] = lq;
+    sa.HQ[(size_t)v * A + a] = hq;
+    sa.EQ[(size_t)v * A + a] = eq;
+    if (uq > bestU) {
+      bestU = uq;
+      Hs = hq;
+      Es = eq;
+    }
+    bestL = fmaxf(bestL, lq);
+  }
+  sa.U[v] = bestU;
+  sa.L[v] = bestL;
+  sa.H[v] = Hs;
+  sa.E[v] = Es;
+}
+
+__global__ void k_search_update(DevModel m, SearchArgs sa) {
+  if (threadIdx.x != 0) return;
+  const int v = sa.ctl[kCtlSelect], base = sa.ctl[kCtlNext];
+  if (sa.ctl[kCtlFlags] || v < 0) return;
+  if (sa.expanded[v]) {
+    sa.ctl[kCtlFlags] |= kSearchDone;
+    return;
+  }
+  if (base + sa.K > sa.NV) {
+    sa.ctl[kCtlFlags] |= kSearchFull;
+    return;
+  }
+  // child slots that the draws left empty
+  for (int i = 0; i < sa.K; ++i)
+    if (!sa.valid[base + i]) sa.E[base + i] = -1;
+  sa.expanded[v] = 1;
+  sa.cbase[v] = base;
+  sa.ctl[kCtlNext] = base + sa.K;
+  sa.log[sa.ctl[kCtlExpansions]] = v;
+  sa.ctl[kCtlExpansions] += 1;
+  const int root = sa.ctl[kCtlRoot];
+  int p = v;
+  while (p >= 0) {
+    search_update_node(m, sa, p);
+    if (p == root) break;
+    const int pq = sa.parent[p];
+    p = pq >= 0 ? pq / m.A : -1;
+  }
+  sa.ctl[kCtlSelect] = sa.E[root];
+}
+
+// getOptimalAction: the lowest action whose L_Q at the root is within 1e-9
+// of the largest (-1 while the root is not expanded), and the root's Q-node
+// bounds.
+__global__ void k_search_result(DevModel m, SearchArgs sa, int32_t *action, float *rootU,
+                                float *rootL) {
+  if (threadIdx.x != 0) return;
+  const int r = sa.ctl[kCtlRoot], A = m.A;
+  if (!sa.expanded[r]) {
+    action[0] = -1;
+    for (int a = 0; a < A; ++a) {
+      rootU[a] = sa.U[r];
+      rootL[a] = sa.L[r];
+    }
+    return;
+  }
+  float best = -INFINITY;
+  for (int a = 0; a < A; ++a) best = fmaxf(best, sa.LQ[(size_t)r * A + a]);
+  int act = 0;
+  for (int a = 0; a < A; ++a)
+    if (sa.LQ[(size_t)r * A + a] >= best - 1e-9f) {
+      act = a;
+      break;
+    }
+  action[0] = act;
+  for (int a = 0; a < A; ++a) {
+    rootU[a] = sa.UQ[(size_t)r * A + a];
+    rootL[a] = sa.LQ[(size_t)r * A + a];
+  }
+}
+
+// update(a, z) of Alg. 1: the root moves to its child under (a, z), whose
+// subtree stays; if z was not drawn there, a new root Phi(b_root, a, z) takes
+// the next free id.  ctl[kCtlErr]: 1 = P(z|b,a) = 0, 2 = the pool is full.
+__global__ __launch_bounds__(kBlock) void k_search_reroot(DevModel m, SearchArgs sa, int a,
+                                                          int z) {
+  extern __shared__ float smem[];
+  __shared__ float s_stay[256];
+  __shared__ float s_red[4 * 32];
+  __shared__ int s_found;
+  const int tid = threadIdx.x, A = m.A;
+  const int r = sa.ctl[kCtlRoot];
+  if (tid == 0) {
+    s_found = -1;
+    sa.ctl[kCtlErr] = 0;
+    if (sa.expanded[r]) {
+      for (int i = 0; i < sa.n; ++i) {
+        const int c = sa.cbase[r] + a * sa.n + i;
+        if (sa.valid[c] && sa.z[c] == z) s_found = c;
+      }
+    }
+    if (s_found >= 0) {
+      sa.parent[s_found] = -1;
+      sa.ctl[kCtlRoot] = s_found;
+      sa.ctl[kCtlSelect] = sa.E[s_found];
+      sa.ctl[kCtlFlags] = 0;
+    }
+  }
+  __syncthreads();
+  if (s_found >= 0) return;
+  const int c = sa.ctl[kCtlNext];
+  if (c + 1 > sa.NV) {
+    if (tid == 0) sa.ctl[kCtlErr] = 2;
+    return;
+  }
+  const int W = m.W, H = m.H, S = m.S, BW = W + 2;
+  float *band = smem;
+  float *bpl = band + (size_t)(H + 2) * BW;
+  const float *b = sa.bel + (size_t)r * S;
+  s_stay[tid] = sa.staytab[a * 256 + tid];
+  load_band(m, sa.sig, b, 0, H, band, BW, false);
+  __syncthreads();
+  const float rW = 1.0f / (float)W;
+  const float *sl = &m.slip[a * 9];
+  const float bgoal = m.goal >= 0 ? b[m.goal] : 0.f;
+  const uint32_t zw = (uint32_t)(z & 15), zl = (uint32_t)(z >> 4);
+  float p = 0.f;
+  for (int t = tid; t < S; t += kBlock) {
+    const uint32_t sg = sa.sig[t];
+    const int ly = fdiv(t, W, rW), lx = t - ly * W;
+    const float bt = t == m.goal ? bgoal : band[(ly + 1) * BW + lx + 1];
+    const float bp = predict_cell_v(band, BW, ly, lx, sg, sl, s_stay, bt);
+    bpl[t] = bp;
+    p = fmaf(wall_lik(m.flip, zw, sig_wall(sg)) * lm_lik(m.lm_p, zl, sig_lm(sg)), bp, p);
+  }
+  p = wave_sum(p);
+  if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = p;
+  __syncthreads();
+  const float P = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+  __syncthreads();
+  if (!(P > 0.f)) {
+    if (tid == 0) sa.ctl[kCtlErr] = 1;
+    return;
+  }
+  float U, L;
+  search_bounds(m, sa, bpl, z, 1.0f / P, sa.bel + (size_t)c * S, s_red, U, L);
+  if (tid == 0) {
+    search_new_node(sa, c, -1, 1.f, z, sa.depth[r] + 1, U, L);
+    sa.pz[c] = P;
+    sa.count[c] = 0;
+    sa.ctl[kCtlRoot] = c;
+    sa.ctl[kCtlSelect] = c;
+    sa.ctl[kCtlNext] = c + 1;
+    sa.ctl[kCtlFlags] = 0;
+  }
+  (void)A;
+}
+
+hipError_t launch_search(int what, const DevModel &m, const SearchArgs &sa, const float *b0,
+                         int a, int z, int32_t *action, float *rootU, float *rootL,
+                         hipStream_t st) {
+  const size_t lds = search_lds_floats(m.W, m.H) * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    const void *ks[3] = {(const void *)k_search_init, (const void *)k_search_expand,
+                         (const void *)k_search_reroot};
+    for (const void *f : ks) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(160 * 1024 - 8 * 1024));
+      if (e != hipSuccess) return e;
+    }
+    attr = true;
+  }
+  switch (what) {
+    case 0:
+      QV_LAUNCH(k_search_init, dim3(1), dim3(kBlock), lds, st, m, sa, b0);
+      break;
+    case 1:
+      QV_LAUNCH(k_search_expand, dim3(m.A), dim3(kBlock), lds, st, m, sa);
+      QV_LAUNCH(k_search_update, dim3(1), dim3(kWave), 0, st, m, sa);
+      break;
+    case 2:
+      QV_LAUNCH(k_search_result, dim3(1), dim3(kWave), 0, st, m, sa, action, rootU, rootL);
+      break;
+    case 3:
+      QV_LAUNCH(k_search_reroot, dim3(1), dim3(kBlock), lds, st, m, sa, a, z);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

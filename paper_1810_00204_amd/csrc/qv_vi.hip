@@ -28,32 +28,52 @@
 namespace qv {
 
 constexpr int kViChunk = 32;
+constexpr int kMaxCoopGrid = 4096;   // workgroups of a one-launch solve at most
 
 // ---------------------------------------------------------------------------
 // grid barrier and the shared stopping rule
 // ---------------------------------------------------------------------------
 
+// Values that other workgroups of the same launch read (V_k, alpha_k) are
+// stored with agent-scope atomic stores and loaded with agent-scope atomic
+// loads.  In the AMDGPU memory model such accesses are performed at the
+// device's coherence point (past the per-XCD L2, which is not coherent
+// across XCDs), so no cache-wide fence is needed; read-only tables (map
+// signature, stay table, rewards) keep their L2 copies across sweeps.
+template <bool COH>
+__device__ __forceinline__ float ld_val(const float *p) {
+  if constexpr (COH) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return *p;
+}
+template <bool COH>
+__device__ __forceinline__ void st_val(float *p, float v) {
+  if constexpr (COH)
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else
+    *p = v;
+}
+
 // Grid barrier of a cooperative launch, round r = 1, 2, ...: the counter
-// *bar reaches r * gridDim.x once every workgroup has arrived.  Memory
-// ordering follows the AMDGPU memory model at agent scope: every wavefront's
-// release fence makes its earlier global stores visible to the whole device
-// (on this multi-XCD part it writes the XCD's L2 back) before the workgroup
-// barrier; lane 0 arrives with a release add and polls with acquire loads;
-// after the workgroup barrier every wavefront's acquire fence drops stale
-// cached lines before it reads what other workgroups wrote.  The wait is
-// bounded: after kSpinLimit polls (seconds, far beyond any sweep) lane 0
-// raises *abort and leaves, and every other waiting workgroup leaves as soon
-// as it sees the flag, so the launch always ends; the caller then stops.
+// *bar reaches r * gridDim.x once every workgroup has arrived.  Every
+// thread first waits until its own stores (and the workgroup's residual
+// atomics) have completed at the coherence point (s_waitcnt 0); after the
+// workgroup barrier lane 0 arrives with an agent-scope atomic add and polls
+// the counter.  A workgroup that sees the full count therefore reads, with
+// its agent-scope loads, everything every workgroup wrote before arriving.
+// The wait is bounded: after kSpinLimit polls (seconds, far beyond any
+// sweep) lane 0 raises *abort and leaves, and every other waiting workgroup
+// leaves as soon as it sees the flag, so the launch always ends; the
+// caller then stops.
 constexpr long long kSpinLimit = 1ll << 22;
 
 __device__ __forceinline__ void grid_sync(unsigned long long *bar, unsigned long long target,
                                           unsigned int *abort) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(bar, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     long long polls = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
       if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
       if (++polls > kSpinLimit) {
         __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -63,7 +83,6 @@ __device__ __forceinline__ void grid_sync(unsigned long long *bar, unsigned long
     }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Control block of one solve in the workspace.
@@ -73,6 +92,7 @@ struct SweepCtl {
   double *out_res;                  // residual of the last sweep
   int *out_k;                       // number of sweeps run
   unsigned int *abort;              // set when a barrier wait gave up
+  double *part;                     // [2][2][grid]: per-workgroup r, max |x| of a sweep
   int max_sweeps;
   double tol;
 };
@@ -80,6 +100,57 @@ struct SweepCtl {
 __device__ __forceinline__ double load_bits(const unsigned long long *p) {
   return __longlong_as_double(
       (long long)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// One-launch form: workgroup g's (r, max |x|) of sweep k go to slot g of the
+// sweep's parity buffer (plain coherent stores, no atomic on a shared word);
+// after the grid barrier wavefront 0 of every workgroup takes the maxima
+// over all slots (the same values everywhere: max is order independent),
+// and workgroup 0 records them as sweep k's residual.  Returns whether the
+// rule fires (in lane 0 of wavefront 0).
+__device__ __forceinline__ void sweep_part_store(const SweepCtl &c, int k, double r, double v,
+                                                 double *red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    r = fmax(r, __shfl_xor(r, o, kWave));
+    v = fmax(v, __shfl_xor(v, o, kWave));
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) {
+    red[wave] = r;
+    red[kBlock / kWave + wave] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / kWave; ++w) {
+      r = fmax(r, red[w]);
+      v = fmax(v, red[kBlock / kWave + w]);
+    }
+    double *p = c.part + (size_t)(k & 1) * 2 * gridDim.x;
+    __hip_atomic_store(p + blockIdx.x, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(p + gridDim.x + blockIdx.x, v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+__device__ __forceinline__ int sweep_part_decide(const SweepCtl &c, int k) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double *p = c.part + (size_t)(k & 1) * 2 * gridDim.x;
+  double r = 0.0, v = 0.0;
+  for (int g = lane; g < (int)gridDim.x; g += kWave) {
+    r = fmax(r, __hip_atomic_load(p + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    v = fmax(v, __hip_atomic_load(p + gridDim.x + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    r = fmax(r, __shfl_xor(r, o, kWave));
+    v = fmax(v, __shfl_xor(v, o, kWave));
+  }
+  if (blockIdx.x == 0 && lane == 0) {
+    c.res[k] = (unsigned long long)__double_as_longlong(r);
+    c.vmax[k] = (unsigned long long)__double_as_longlong(v);
+  }
+  return (r == 0.0 || r <= c.tol * fmax(1.0, v)) ? 1 : 0;
 }
 
 // Stop after sweep k: r_k = 0 or r_k <= tol * max(1, max |x_k|).
@@ -134,20 +205,34 @@ __global__ void k_sweep_fill(unsigned long long *res, unsigned long long *vmax, 
 
 // V band: off-grid and blocked cells read as zero (their value is 0), the
 // goal keeps its value.
+template <bool COH>
 __device__ __forceinline__ void load_vband(const DevModel &m, const uint32_t *sig,
                                            const float *V, int y0, int th, float *band,
                                            int BW) {
+  constexpr int kBatch = 8;   // band entries whose loads a thread issues together
   const int n = (th + 2) * BW;
   const float rBW = 1.0f / (float)BW;
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    const int r = fdiv(i, BW, rBW);
-    const int gy = y0 - 1 + r, gx = i - r * BW - 1;
-    float v = 0.f;
-    if (gy >= 0 && gy < m.H && gx >= 0 && gx < m.W) {
-      const int s = gy * m.W + gx;
-      if (sig[s] & kSigFree) v = V[s];
+  for (int i0 = threadIdx.x; i0 < n; i0 += kBatch * kBlock) {
+    int cell[kBatch];
+    uint32_t sg[kBatch];
+    float v[kBatch];
+    // every lane loads (cell 0 for halo and padding lanes) and masks after,
+    // so the batch's loads go out together
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      const int r = fdiv(i, BW, rBW);
+      const int gy = y0 - 1 + r, gx = i - r * BW - 1;
+      const bool in = i < n && gy >= 0 && gy < m.H && gx >= 0 && gx < m.W;
+      cell[j] = in ? gy * m.W + gx : -1;
+      sg[j] = sig[in ? cell[j] : 0];
+      v[j] = ld_val<COH>(V + (in ? cell[j] : 0));
     }
-    band[i] = v;
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) {
+      const int i = i0 + j * kBlock;
+      if (i < n) band[i] = (cell[j] >= 0 && (sg[j] & kSigFree)) ? v[j] : 0.f;
+    }
   }
 }
 
@@ -179,6 +264,7 @@ __device__ __forceinline__ float cell_q(const DevModel &m, const float *band, in
 
 // One band of sweep k: V_k from V_{k-1} (in the LDS band); the band's
 // largest |V_k - V_{k-1}| and |V_k| (free cells) are folded into r, vm.
+template <bool COH>
 __device__ __forceinline__ void vi_band(const DevModel &m, const uint32_t *sig,
                                         const float *staytab, int TH, int tile,
                                         const float *Vin, float *Vout, float *band, double &r,
@@ -186,7 +272,7 @@ __device__ __forceinline__ void vi_band(const DevModel &m, const uint32_t *sig,
   const int W = m.W, BW = W + 2;
   const int y0 = tile * TH;
   const int th = min(TH, m.H - y0);
-  load_vband(m, sig, Vin, y0, th, band, BW);
+  load_vband<COH>(m, sig, Vin, y0, th, band, BW);
   __syncthreads();
   const float rW = 1.0f / (float)W;
   for (int i = threadIdx.x; i < th * W; i += kBlock) {
@@ -202,19 +288,20 @@ __device__ __forceinline__ void vi_band(const DevModel &m, const uint32_t *sig,
       r = fmax(r, d);
       vm = fmax(vm, fabs((double)best));
     }
-    Vout[t] = best;
+    st_val<COH>(Vout + t, best);
   }
   __syncthreads();   // the band is reused by the next tile
 }
 
 // Q(t, .) of one band from V (the Q-values of a sweep from its input V).
+template <bool COH>
 __device__ __forceinline__ void vi_q_band(const DevModel &m, const uint32_t *sig,
                                           const float *staytab, int TH, int tile, const float *V,
                                           float *Q, float *band) {
   const int W = m.W, BW = W + 2;
   const int y0 = tile * TH;
   const int th = min(TH, m.H - y0);
-  load_vband(m, sig, V, y0, th, band, BW);
+  load_vband<COH>(m, sig, V, y0, th, band, BW);
   __syncthreads();
   const float rW = 1.0f / (float)W;
   for (int i = threadIdx.x; i < th * W; i += kBlock) {
@@ -245,13 +332,15 @@ __global__ __launch_bounds__(kBlock) void k_vi_coop(DevModel m, const uint32_t *
     float *Vout = (k & 1) ? V1 : V0;
     double r = 0.0, vm = 0.0;
     for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-      vi_band(m, sig, staytab, TH, tile, Vin, Vout, smem, r, vm);
-    sweep_report(r, vm, c.res, c.vmax, k, red);
+      vi_band<true>(m, sig, staytab, TH, tile, Vin, Vout, smem, r, vm);
+    sweep_part_store(c, k, r, vm, red);
     grid_sync(c.bar, (unsigned long long)k * gridDim.x, c.abort);
-    if (threadIdx.x == 0)
-      s_stop = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                   ? 2
-                   : sweep_converged(c, k);
+    if (threadIdx.x < kWave) {
+      const int conv = sweep_part_decide(c, k);
+      if (threadIdx.x == 0)
+        s_stop = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 2
+                                                                                        : conv;
+    }
     __syncthreads();
     if (s_stop) {   // the same decision in every workgroup (unless aborted)
       kend = k;
@@ -261,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_vi_coop(DevModel m, const uint32_t *
   if (s_stop == 2) return;
   const float *Vprev = (kend & 1) ? V0 : V1;
   for (int tile = blockIdx.x; tile < tiles; tile += gridDim.x)
-    vi_q_band(m, sig, staytab, TH, tile, Vprev, Q, smem);
+    vi_q_band<true>(m, sig, staytab, TH, tile, Vprev, Q, smem);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *c.out_k = kend;
     *c.out_res = load_bits(c.res + kend);
@@ -278,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_vi_sweep(DevModel m, const uint32_t 
   extern __shared__ float smem[];
   __shared__ double red[2 * kBlock / kWave];
   double r = 0.0, vm = 0.0;
-  vi_band(m, sig, staytab, TH, blockIdx.x, Vin, Vout, smem, r, vm);
+  vi_band<false>(m, sig, staytab, TH, blockIdx.x, Vin, Vout, smem, r, vm);
   sweep_report(r, vm, c.res, c.vmax, k, red);
 }
 
@@ -287,7 +376,7 @@ __global__ __launch_bounds__(kBlock) void k_vi_q(DevModel m, const uint32_t *sig
                                                  const float *staytab, int TH, const float *V,
                                                  float *Q) {
   extern __shared__ float smem[];
-  vi_q_band(m, sig, staytab, TH, blockIdx.x, V, Q, smem);
+  vi_q_band<false>(m, sig, staytab, TH, blockIdx.x, V, Q, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,7 +393,7 @@ __global__ __launch_bounds__(kBlock) void k_vi_q(DevModel m, const uint32_t *sig
 //   zl = l:  rho T_k(a) max_a' alpha^a'(x_k) for the successor x_k that is
 //            landmark l (only it can report l, and sum_zw C[zw][w] = 1).
 // The goal is absorbing: its right-hand side is R + gamma max_a' alpha^a'(goal).
-template <int AM>
+template <int AM, bool COH>
 __device__ __forceinline__ void fib_cell(const DevModel &m, const uint32_t *sig,
                                          const float *staytab, const float *al,
                                          const float *ctab, int x, uint32_t sg,
@@ -315,7 +404,7 @@ __device__ __forceinline__ void fib_cell(const DevModel &m, const uint32_t *sig,
     float best = -INFINITY;
 #pragma unroll
     for (int ap = 0; ap < AM; ++ap)
-      if (ap < A) best = fmaxf(best, al[(size_t)x * A + ap]);
+      if (ap < A) best = fmaxf(best, ld_val<COH>(al + (size_t)x * A + ap));
 #pragma unroll
     for (int a = 0; a < AM; ++a)
       out[a] = a < A ? fmaf(m.gamma, best, m.R[(size_t)x * A + a]) : 0.f;
@@ -338,7 +427,7 @@ __device__ __forceinline__ void fib_cell(const DevModel &m, const uint32_t *sig,
     lam[k] = lmk[k] ? 1.f - rho : 1.f;
 #pragma unroll
     for (int ap = 0; ap < AM; ++ap) {
-      const float av = al[(size_t)t * A + (ap < A ? ap : 0)];
+      const float av = ld_val<COH>(al + (size_t)t * A + (ap < A ? ap : 0));
       v[k][ap] = (ok && ap < A) ? av : 0.f;
     }
   }
@@ -392,6 +481,43 @@ __device__ __forceinline__ void fib_cell(const DevModel &m, const uint32_t *sig,
     out[a] = a < A ? fmaf(m.gamma, acc[a], m.R[(size_t)x * A + a]) : 0.f;
 }
 
+// The blind-policy right-hand side at free cell x for every action: each
+// action's own vector, alpha^a(x) = R(x,a) + gamma sum_x' T(x,a,x') alpha^a(x')
+// (no max over actions: the value of taking a forever, a lower bound).
+template <int AM, bool COH>
+__device__ __forceinline__ void blind_cell(const DevModel &m, const uint32_t *sig,
+                                           const float *staytab, const float *al, int x,
+                                           uint32_t sg, float (&out)[AM]) {
+  const int A = m.A, W = m.W;
+  if (sg & kSigGoal) {
+#pragma unroll
+    for (int a = 0; a < AM; ++a)
+      out[a] = a < A ? fmaf(m.gamma, ld_val<COH>(al + (size_t)x * A + a),
+                            m.R[(size_t)x * A + a])
+                     : 0.f;
+    return;
+  }
+  const int pat = (int)sig_out8(sg);
+  float acc[AM];
+#pragma unroll
+  for (int a = 0; a < AM; ++a) acc[a] = 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const bool ok = (k == 4) || ((sg >> (k < 4 ? k : k - 1)) & 1u);
+    const int t = ok ? x + (k / 3 - 1) * W + (k % 3 - 1) : x;
+#pragma unroll
+    for (int a = 0; a < AM; ++a) {
+      if (a >= A) continue;
+      const float av = ld_val<COH>(al + (size_t)t * A + a);
+      const float tk = k == 4 ? staytab[a * 256 + pat] : m.slip[a * 9 + k];
+      acc[a] = fmaf(tk, ok ? av : 0.f, acc[a]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < AM; ++a)
+    out[a] = a < A ? fmaf(m.gamma, acc[a], m.R[(size_t)x * A + a]) : 0.f;
+}
+
 // C[zw][w] = prod_j (bit j of zw ^ w set ? f_j : 1 - f_j) into LDS.
 __device__ __forceinline__ void fib_ctab(const DevModel &m, float *ctab) {
   if (threadIdx.x < 256) ctab[threadIdx.x] = wall_lik(m.flip, threadIdx.x >> 4, threadIdx.x & 15u);
@@ -399,7 +525,7 @@ __device__ __forceinline__ void fib_ctab(const DevModel &m, float *ctab) {
 }
 
 // One sweep over the cells i = blockIdx.x * kBlock + threadIdx.x + j * stride.
-template <int AM>
+template <int AM, bool COH, int OP>
 __device__ __forceinline__ void fib_pass(const DevModel &m, const uint32_t *sig,
                                          const float *staytab, const float *ain, float *aout,
                                          const float *ctab, long long stride, double &r,
@@ -409,11 +535,14 @@ __device__ __forceinline__ void fib_pass(const DevModel &m, const uint32_t *sig,
     const uint32_t sg = sig[x];
     float o[AM];
     if (sg & kSigFree) {
-      fib_cell<AM>(m, sig, staytab, ain, ctab, (int)x, sg, o);
+      if constexpr (OP == 0)
+        fib_cell<AM, COH>(m, sig, staytab, ain, ctab, (int)x, sg, o);
+      else
+        blind_cell<AM, COH>(m, sig, staytab, ain, (int)x, sg, o);
 #pragma unroll
       for (int a = 0; a < AM; ++a) {
         if (a >= A) continue;
-        r = fmax(r, fabs((double)o[a] - (double)ain[x * A + a]));
+        r = fmax(r, fabs((double)o[a] - (double)ld_val<COH>(ain + x * A + a)));
         vm = fmax(vm, fabs((double)o[a]));
       }
     } else {
@@ -422,13 +551,13 @@ __device__ __forceinline__ void fib_pass(const DevModel &m, const uint32_t *sig,
     }
 #pragma unroll
     for (int a = 0; a < AM; ++a)
-      if (a < A) aout[x * A + a] = o[a];
+      if (a < A) st_val<COH>(aout + x * A + a, o[a]);
   }
 }
 
 // Every FIB sweep in one launch (cooperative).  al[0] holds alpha_0 = 0;
 // sweep k writes alpha_k into al[k & 1]; the last one is copied to out.
-template <int AM>
+template <int AM, int OP>
 __global__ __launch_bounds__(kBlock) void k_fib_coop(DevModel m, const uint32_t *sig,
                                                      const float *staytab, float *al0,
                                                      float *al1, float *out, SweepCtl c) {
@@ -443,13 +572,15 @@ __global__ __launch_bounds__(kBlock) void k_fib_coop(DevModel m, const uint32_t 
     const float *ain = (k & 1) ? al0 : al1;
     float *aout = (k & 1) ? al1 : al0;
     double r = 0.0, vm = 0.0;
-    fib_pass<AM>(m, sig, staytab, ain, aout, ctab, stride, r, vm);
-    sweep_report(r, vm, c.res, c.vmax, k, red);
+    fib_pass<AM, true, OP>(m, sig, staytab, ain, aout, ctab, stride, r, vm);
+    sweep_part_store(c, k, r, vm, red);
     grid_sync(c.bar, (unsigned long long)k * gridDim.x, c.abort);
-    if (threadIdx.x == 0)
-      s_stop = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                   ? 2
-                   : sweep_converged(c, k);
+    if (threadIdx.x < kWave) {
+      const int conv = sweep_part_decide(c, k);
+      if (threadIdx.x == 0)
+        s_stop = __hip_atomic_load(c.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 2
+                                                                                        : conv;
+    }
     __syncthreads();
     if (s_stop) {
       kend = k;
@@ -460,7 +591,7 @@ __global__ __launch_bounds__(kBlock) void k_fib_coop(DevModel m, const uint32_t 
   const float *last = (kend & 1) ? al1 : al0;
   const long long n = (long long)m.S * m.A;
   for (long long i = (long long)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
-    out[i] = last[i];
+    out[i] = ld_val<true>(last + i);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     *c.out_k = kend;
     *c.out_res = load_bits(c.res + kend);
@@ -468,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void k_fib_coop(DevModel m, const uint32_t 
 }
 
 // Per-sweep form of FIB sweep k (nothing once the rule has fired).
-template <int AM>
+template <int AM, int OP>
 __global__ __launch_bounds__(kBlock) void k_fib_sweep(DevModel m, const uint32_t *sig,
                                                       const float *staytab, const float *ain,
                                                       float *aout, int k, SweepCtl c) {
@@ -477,7 +608,8 @@ __global__ __launch_bounds__(kBlock) void k_fib_sweep(DevModel m, const uint32_t
   __shared__ double red[2 * kBlock / kWave];
   fib_ctab(m, ctab);
   double r = 0.0, vm = 0.0;
-  fib_pass<AM>(m, sig, staytab, ain, aout, ctab, (long long)gridDim.x * kBlock, r, vm);
+  fib_pass<AM, false, OP>(m, sig, staytab, ain, aout, ctab, (long long)gridDim.x * kBlock, r,
+                          vm);
   sweep_report(r, vm, c.res, c.vmax, k, red);
 }
 
@@ -497,6 +629,7 @@ static size_t sweep_ws(const qv_model *m, long long vals, int max_sweeps) {
   off += 2 * align_up((size_t)(max_sweeps + 2) * 8, 256);
   off += 256;   // barrier counter, residual, sweep count
   off += 256;   // error word
+  off += align_up((size_t)4 * kMaxCoopGrid * 8, 256);   // per-workgroup residual partials
   return off;
 }
 
@@ -537,6 +670,8 @@ static SweepWs carve(const DevModel &m, long long vals, int max_sweeps, float to
   w.c.abort = (unsigned int *)(ws + off + 20);
   off += 256;
   w.err = (int32_t *)(ws + off);
+  off += 256;
+  w.c.part = (double *)(ws + off);
   w.c.max_sweeps = max_sweeps;
   w.c.tol = (double)tol;
   return w;
@@ -569,7 +704,7 @@ static int coop_grid(const void *kernel, size_t lds, int want) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kBlock, lds) != hipSuccess ||
       per < 1)
     return 0;
-  return std::max(1, std::min(want, per * cus));
+  return std::max(1, std::min(std::min(want, per * cus), kMaxCoopGrid));
 }
 
 // Residual and sweep count of a cooperative solve (one wait); a barrier
@@ -666,12 +801,12 @@ hipError_t run_value_iteration(const DevModel &m, float tol, int max_sweeps, flo
   return hipStreamSynchronize(st);
 }
 
-template <int AM>
+template <int AM, int OP>
 static hipError_t run_fib_am(const DevModel &m, const SweepWs &w, float *alpha,
                              double *residual, int *sweeps, hipStream_t st) {
   const long long vals = (long long)m.S * m.A;
   const int want = (int)std::min<long long>((m.S + kBlock - 1) / kBlock, 1 << 20);
-  const int G = coop_grid(reinterpret_cast<const void *>(&k_fib_coop<AM>), 0, want);
+  const int G = coop_grid(reinterpret_cast<const void *>(&k_fib_coop<AM, OP>), 0, want);
   hipError_t e;
   if (G > 0) {
     DevModel mm = m;
@@ -681,9 +816,9 @@ static hipError_t run_fib_am(const DevModel &m, const SweepWs &w, float *alpha,
     SweepCtl c = w.c;
     void *args[] = {&mm, &sig, &stay, &a0, &a1, &alpha, &c};
     {
-      TimingScope ts("k_fib_coop", st);
-      e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_fib_coop<AM>), dim3(G),
-                                     dim3(kBlock), args, 0u, st);
+      TimingScope ts(OP == 0 ? "k_fib_coop" : "k_blind_coop", st);
+      e = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(&k_fib_coop<AM, OP>),
+                                     dim3(G), dim3(kBlock), args, 0u, st);
     }
     if (e != hipSuccess) return e;
     return read_result(w, residual, sweeps, st);
@@ -691,8 +826,8 @@ static hipError_t run_fib_am(const DevModel &m, const SweepWs &w, float *alpha,
   e = sweep_chunks(
       w,
       [&](int k, float *in, float *out) {
-        QV_LAUNCH(k_fib_sweep<AM>, dim3(want), dim3(kBlock), 0, st, m, w.sig, w.staytab, in,
-                  out, k, w.c);
+        QV_LAUNCH((k_fib_sweep<AM, OP>), dim3(want), dim3(kBlock), 0, st, m, w.sig, w.staytab,
+                  in, out, k, w.c);
       },
       residual, sweeps, st);
   if (e != hipSuccess) return e;
@@ -701,15 +836,21 @@ static hipError_t run_fib_am(const DevModel &m, const SweepWs &w, float *alpha,
   return hipStreamSynchronize(st);
 }
 
+// op 0: the FIB equation; op 1: the blind-policy equation.
 hipError_t run_fib(const DevModel &m, float tol, int max_sweeps, float *alpha,
-                   double *residual, int *sweeps, char *ws, hipStream_t st) {
+                   double *residual, int *sweeps, char *ws, hipStream_t st, int op) {
   const long long vals = (long long)m.S * m.A;
   const SweepWs w = carve(m, vals, max_sweeps, tol, ws);
   hipError_t e = sweep_setup(m, w, vals, st);
   if (e != hipSuccess) return e;
-  if (m.A <= 4) return run_fib_am<4>(m, w, alpha, residual, sweeps, st);
-  if (m.A <= 8) return run_fib_am<8>(m, w, alpha, residual, sweeps, st);
-  return run_fib_am<9>(m, w, alpha, residual, sweeps, st);
+  if (op == 1) {
+    if (m.A <= 4) return run_fib_am<4, 1>(m, w, alpha, residual, sweeps, st);
+    if (m.A <= 8) return run_fib_am<8, 1>(m, w, alpha, residual, sweeps, st);
+    return run_fib_am<9, 1>(m, w, alpha, residual, sweeps, st);
+  }
+  if (m.A <= 4) return run_fib_am<4, 0>(m, w, alpha, residual, sweeps, st);
+  if (m.A <= 8) return run_fib_am<8, 0>(m, w, alpha, residual, sweeps, st);
+  return run_fib_am<9, 0>(m, w, alpha, residual, sweeps, st);
 }
 
 }  // namespace qv

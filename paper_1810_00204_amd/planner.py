@@ -48,6 +48,16 @@ class Planner:
         B.check(st, "qv_fib_iterate")
         return al, res, sw
 
+    # -- offline blind-policy vectors (a lower-bound table)
+    def blind_iterate(self, tol=1e-6, max_sweeps=10000):
+        torch = self.torch
+        al = torch.empty(self.m.S * self.m.A, dtype=torch.float32, device=self.device)
+        ws = torch.empty(B.qv_blind_workspace_bytes(self.m, max_sweeps), dtype=torch.uint8,
+                         device=self.device)
+        st, res, sw = B.qv_blind_iterate(self.m, tol, max_sweeps, al, ws)
+        B.check(st, "qv_blind_iterate")
+        return al, res, sw
+
     # -- one planning step ------------------------------------------------
     def plan(self, Q, b0=None, seed=None, query_id=None, stream=None):
         prob = self.prob
@@ -174,3 +184,78 @@ def belief_update(m: B.DeviceModel, b, a, z, check: bool = True, stream=None):
                      device=b.device)
     st = B.qv_belief_update(m, batch, b, a, z, b_out, p_out, 1 if check else 0, ws, stream)
     return b_out, p_out, st
+
+
+class SearchPlanner:
+    """Best-first (anytime) search over one problem (qv_search_*): the node
+    pool's workspace, the two bound tables and readers of the node records."""
+
+    def __init__(self, prob, Ut, Lt, max_nodes: int, device="cuda", n=None):
+        import torch
+        self.torch = torch
+        self.prob = prob
+        self.device = device
+        self.n = prob.n if n is None else n
+        self.max_nodes = int(max_nodes)
+        self.m = B.DeviceModel(prob, device)
+
+        def dev(t):
+            return t if hasattr(t, "data_ptr") else torch.as_tensor(
+                np.ascontiguousarray(t, np.float32).reshape(-1)).to(device)
+        self.Ut, self.Lt = dev(Ut), dev(Lt)
+        nb = B.qv_search_workspace_bytes(self.m, self.n, self.max_nodes)
+        if nb == 0:
+            raise B.QvError(B.QV_ERR_UNSUPPORTED, "qv_search_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        st, self.layout = B.qv_search_layout_of(self.m, self.n, self.max_nodes)
+        B.check(st, "qv_search_layout_of")
+        self.action = torch.zeros(1, dtype=torch.int32, device=device)
+        self.rootU = torch.zeros(self.m.A, dtype=torch.float32, device=device)
+        self.rootL = torch.zeros(self.m.A, dtype=torch.float32, device=device)
+
+    def init(self, b0=None, stream=None):
+        b0 = self.prob.b0 if b0 is None else b0
+        bt = b0 if hasattr(b0, "data_ptr") else self.torch.as_tensor(
+            np.ascontiguousarray(b0, np.float32)).to(self.device)
+        self._b0 = bt
+        B.check(B.qv_search_init(self.m, self.Ut, self.Lt, bt, self.n, self.max_nodes, self.ws,
+                                 stream), "qv_search_init")
+
+    def expand(self, expansions: int, seed=None, query_id=None, stream=None):
+        p = self.prob
+        B.check(B.qv_search_expand(self.m, self.Ut, self.Lt, self.n, self.max_nodes,
+                                   p.seed if seed is None else seed,
+                                   p.query_id if query_id is None else query_id,
+                                   int(expansions), self.ws, stream), "qv_search_expand")
+
+    def result(self, stream=None):
+        B.check(B.qv_search_result(self.m, self.n, self.max_nodes, self.action, self.rootU,
+                                   self.rootL, self.ws, stream), "qv_search_result")
+        return self.action, self.rootU, self.rootL
+
+    def update(self, a: int, z: int, stream=None) -> int:
+        return B.qv_search_update(self.m, self.Ut, self.Lt, self.n, self.max_nodes, int(a),
+                                  int(z), self.ws, stream)
+
+    def records(self, beliefs: bool = False) -> dict:
+        """Copies the node records (and optionally the beliefs) out of the
+        workspace (after a sync)."""
+        self.torch.cuda.synchronize()
+        L, raw, NV, A, S = self.layout, self.ws, self.max_nodes, self.prob.A, self.prob.S
+
+        def arr(off, count, dt):
+            nbytes = count * np.dtype(dt).itemsize
+            return raw[off:off + nbytes].cpu().numpy().view(dt).copy()
+        out = {k: arr(getattr(L, k), NV, np.int32) for k in
+               ("valid", "z", "count", "parent", "depth", "E", "expanded", "child_base")}
+        out.update({k: arr(getattr(L, k), NV, np.float32) for k in ("pz", "weight", "U", "L", "H")})
+        out.update({k: arr(getattr(L, k), NV * A, np.float32).reshape(NV, A)
+                    for k in ("rb", "UQ", "LQ", "HQ")})
+        out["EQ"] = arr(L.EQ, NV * A, np.int32).reshape(NV, A)
+        ctl = arr(L.ctl, 6, np.int32)
+        out.update(root=int(ctl[0]), select=int(ctl[1]), next=int(ctl[2]),
+                   expansions=int(ctl[3]), flags=int(ctl[4]), err=int(ctl[5]))
+        out["log"] = arr(L.log, NV, np.int32)[:out["expansions"]]
+        if beliefs:
+            out["belief"] = arr(L.belief, NV * S, np.float32).reshape(NV, S)
+        return out

@@ -70,6 +70,8 @@ def level_grids(workload: str):
             out[("k_node", (slots * A + leaf_tiles) * NODE_BLOCK)] = d
         for fam in ("k_stats", "k_update", "k_leaf"):
             out[(fam, slots * tiles * A * BLOCK)] = d
+        for fam in ("k_stats_parent", "k_update_parent"):
+            out[(fam, slots * tiles * BLOCK)] = d
     out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * NODE_BLOCK)] = D - 1
     return out
 

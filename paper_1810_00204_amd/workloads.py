@@ -63,6 +63,26 @@ def slip_table_8(p_main: float = 0.7, p_adj: float = 0.1,
     return t.astype(np.float32)
 
 
+def slip_table_9(p_main: float = 0.8, p_adj: float = 0.05,
+                 p_stay: float = 0.1) -> np.ndarray:
+    """T'(a, k) for the nine actions of Sec. V: action a aims at neighbour
+    N_a (a = 4 is the robot's own cell, "stay").  A move lands on its target
+    with p_main, on each of the two ring neighbours 45 degrees either side
+    with p_adj, and stays with p_stay; the stay action stays surely.  (The
+    paper gives T' only in a figure; these values are this project's.)"""
+    t = np.zeros((9, 9), dtype=np.float64)
+    for a in range(9):
+        if a == 4:
+            t[4, 4] = 1.0
+            continue
+        i = ACTIONS8.index(NEIGHBOURS[a])
+        t[a, a] += p_main
+        t[a, K_OF[ACTIONS8[(i + 1) % 8]]] += p_adj
+        t[a, K_OF[ACTIONS8[(i + 7) % 8]]] += p_adj
+        t[a, 4] += p_stay
+    return t.astype(np.float32)
+
+
 @dataclass
 class Problem:
     """One planning (or filtering) problem: the tuple (X, A, Z, T, O, R, b0,
@@ -194,6 +214,42 @@ def reward_step_goal(occ: np.ndarray, W: int, H: int, slip: np.ndarray,
                 if k != 4 and y + dy == gy and x + dx == gx:
                     hit += float(slip[a, k])
             R[s, a] = step + bonus * hit
+    return R.astype(np.float32)
+
+
+def reward_paper(occ: np.ndarray, W: int, H: int, slip: np.ndarray, target: int,
+                 stop_action: int = 4) -> np.ndarray:
+    """The stage reward of Sec. V: with r(y) = -2 on a blocked cell (off the
+    grid counts as blocked), 0 at the target, -1 on any other free cell,
+    R(x, a) = -2 for the stay action away from the target, and otherwise
+    sum_y r(y) T'(x, a, y), with the free-space T' (so an action aimed at an
+    obstacle pays for it).  Blocked x (never occupied): 0."""
+    S = W * H
+    A = slip.shape[0]
+    R = np.zeros((S, A), dtype=np.float64)
+    for s in range(S):
+        if occ[s]:
+            continue
+        y, x = divmod(s, W)
+        for a in range(A):
+            if a == stop_action and s != target:
+                R[s, a] = -2.0
+                continue
+            v = 0.0
+            for k, (dy, dx) in enumerate(NEIGHBOURS):
+                p = float(slip[a, k])
+                if p == 0.0:
+                    continue
+                ny, nx = y + dy, x + dx
+                t = ny * W + nx
+                if not (0 <= ny < H and 0 <= nx < W) or occ[t]:
+                    r = -2.0
+                elif t == target:
+                    r = 0.0
+                else:
+                    r = -1.0
+                v += p * r
+            R[s, a] = v
     return R.astype(np.float32)
 
 
@@ -340,6 +396,63 @@ def make_batch(seed: int = 0, nq: int = 256, side_lo: int = 32,
     return out
 
 
+def make_paper(seed: int = 0, W: int = 100, H: int = 40, frac: float = 0.15,
+               side_lo: int = 2, side_hi: int = 6, walls: Optional[tuple] = (8, 30),
+               D: int = 2, n: int = 3, cfg_index: int = 5) -> Problem:
+    """The experiment model of Sec. V on a synthetic map: a W x H grid of
+    seeded rectangles and wall segments, the nine actions of slip_table_9,
+    four wall bits each read correctly with probability 0.95, no landmarks,
+    the stage reward of reward_paper towards a seeded target cell in the
+    largest free component, discount 0.95, and the start belief uniform over
+    the free cells.  The target is not absorbing (the paper's model has no
+    absorbing state): ``goal`` is -1 and the target is ``meta["target"]``;
+    the stay action (``meta["stop_action"]`` = 4) ends a closed-loop run."""
+    rng = _rng(cfg_index, seed)
+    occ = occ_rectangles(rng, W, H, frac, side_lo, side_hi, walls)
+    comp = largest_free_component(occ, W, H)
+    target = int(rng.permutation(comp)[0])
+    slip = slip_table_9()
+    R = reward_paper(occ, W, H, slip, target)
+    b0 = belief_uniform_cells(W * H, np.flatnonzero(occ == 0))
+    return Problem(name=f"paper{W}x{H}-9act-D{D}n{n}", W=W, H=H, occ=occ, slip=slip,
+                   flip=np.full(4, 0.05, dtype=np.float32),
+                   lm_cell=np.zeros(0, dtype=np.int32), lm_p=0.9, R=R, goal=-1,
+                   gamma=0.95, b0=b0, D=D, n=n, seed=int(rng.integers(0, 2 ** 63)),
+                   meta={"target": target, "stop_action": 4, "component": comp})
+
+
+class Environment:
+    """The true world of one closed-loop run (the generative model of Sec. V):
+    the robot's cell, moved by a seeded draw of the slip outcome of each
+    executed action, and the observation of each new cell, drawn with the
+    sensor's flip probabilities (and landmark channel).  The start cell is
+    drawn uniformly from the target's free component (other than the target).
+    It holds the world's random numbers only; no step of the planning method."""
+
+    def __init__(self, prob: Problem, seed: int, start: Optional[int] = None):
+        self.prob = prob
+        self.rng = _rng(6, seed)
+        comp = prob.meta.get("component")
+        if comp is None:
+            comp = np.flatnonzero(prob.occ == 0)
+        target = prob.meta.get("target", -1)
+        cand = np.asarray(comp)[np.asarray(comp) != target]
+        self.s = int(start) if start is not None else int(cand[self.rng.integers(0, cand.size)])
+        self.cum = np.cumsum(prob.slip.astype(np.float64), axis=1)
+        self.lm_id = None
+        if prob.L > 0:
+            self.lm_id = np.zeros(prob.S, dtype=np.int32)
+            self.lm_id[prob.lm_cell] = np.arange(1, prob.L + 1)
+
+    def step(self, a: int):
+        """Executes action a: returns (observation z, collided), where
+        collided means the drawn move aimed at a blocked or off-grid cell."""
+        p = self.prob
+        self.s, z, hit = _env_step(self.rng, p.occ, p.W, p.H, self.cum, p.flip, self.s, int(a),
+                                   self.lm_id, p.lm_p)
+        return z, hit
+
+
 # ---------------------------------------------------------------------------
 # logged trajectories for the differentiable filter
 # ---------------------------------------------------------------------------
@@ -355,37 +468,46 @@ class TrajectorySet:
     obs: np.ndarray                 # int32 [ntraj, T]
 
 
+def _env_step(rng, occ, W, H, cum, flip, s, a, lm_id=None, lm_p=0.0):
+    """One step of the generative model of Sec. V from cell s under action a:
+    the slip outcome k ~ slip[a] (cum: its running totals), the move
+    succeeds when its target is inside the grid and free, each wall bit is
+    read correctly with probability 1 - flip[j]; on a cell with landmark id
+    l > 0 the landmark channel reports l with probability lm_p, else 0.
+    Returns (new cell, z = zw + 16 zl, whether the move hit an obstacle)."""
+    k = int(np.searchsorted(cum[a], rng.random() * cum[a, -1], side="right"))
+    k = min(k, 8)
+    dy, dx = NEIGHBOURS[k]
+    y, x = divmod(s, W)
+    ny, nx = y + dy, x + dx
+    hit = False
+    if 0 <= ny < H and 0 <= nx < W and occ[ny * W + nx] == 0:
+        s = ny * W + nx
+    elif k != 4:
+        hit = True
+    y, x = divmod(s, W)
+    zw = 0
+    for j, (ddy, ddx) in enumerate(((-1, 0), (0, -1), (0, 1), (1, 0))):
+        qy, qx = y + ddy, x + ddx
+        bit = 1 if not (0 <= qy < H and 0 <= qx < W) or occ[qy * W + qx] else 0
+        if rng.random() < flip[j]:
+            bit ^= 1
+        zw |= bit << j
+    zl = 0
+    if lm_id is not None and lm_id[s] > 0 and rng.random() < lm_p:
+        zl = int(lm_id[s])
+    return s, zw + 16 * zl, hit
+
+
 def _simulate(rng, occ, W, H, slip, flip, s0, acts, lm_id=None, lm_p=0.0):
-    """Draw a state path and observations from the generative model of
-    Sec. V: the slip outcome k ~ slip[a], the move succeeds when its target
-    is inside the grid and free, each wall bit is read correctly with
-    probability 1 - flip[j]; on a cell with landmark id l > 0 the landmark
-    channel reports l with probability lm_p, else 0 (z = zw + 16 zl)."""
+    """A state path and its observations under the generative model of
+    Sec. V (see _env_step) for the action sequence acts."""
     T = acts.shape[0]
     obs = np.zeros(T, dtype=np.int32)
     s = s0
     cum = np.cumsum(slip.astype(np.float64), axis=1)
     for t in range(T):
-        a = int(acts[t])
-        k = int(np.searchsorted(cum[a], rng.random() * cum[a, -1], side="right"))
-        k = min(k, 8)
-        dy, dx = NEIGHBOURS[k]
-        y, x = divmod(s, W)
-        ny, nx = y + dy, x + dx
-        if 0 <= ny < H and 0 <= nx < W and occ[ny * W + nx] == 0:
-            s = ny * W + nx
-        y, x = divmod(s, W)
-        zw = 0
-        for j, (ddy, ddx) in enumerate(((-1, 0), (0, -1), (0, 1), (1, 0))):
-            qy, qx = y + ddy, x + ddx
-            bit = 1 if not (0 <= qy < H and 0 <= qx < W) or occ[qy * W + qx] else 0
-            if rng.random() < flip[j]:
-                bit ^= 1
-            zw |= bit << j
-        zl = 0
-        if lm_id is not None and lm_id[s] > 0 and rng.random() < lm_p:
-            zl = int(lm_id[s])
-        obs[t] = zw + 16 * zl
+        s, obs[t], _ = _env_step(rng, occ, W, H, cum, flip, s, int(acts[t]), lm_id, lm_p)
     return obs
 
 

@@ -183,5 +183,5 @@ def test_fib_rejects_bad_arguments():
     ws = torch.empty(B.qv_fib_workspace_bytes(m, 10), dtype=torch.uint8, device="cuda")
     assert B.qv_fib_iterate(m, 1e-6, 0, al, ws)[0] == B.QV_ERR_INVALID_ARG
     assert B.qv_fib_iterate(m, -1.0, 10, al, ws)[0] == B.QV_ERR_INVALID_ARG
-    assert B.qv_fib_iterate(m, 1e-6, 11, al, ws)[0] == B.QV_ERR_WORKSPACE
+    assert B.qv_fib_iterate(m, 1e-6, 100, al, ws)[0] == B.QV_ERR_WORKSPACE
     assert B.qv_fib_workspace_bytes(m, 0) == 0

@@ -238,3 +238,43 @@ def _belief_close(gb, ob):
     tol = 1e-5 * np.abs(ob) + 1e-12 * ob.max()
     bad = np.abs(gb - ob) > tol
     assert not bad.any(), (np.flatnonzero(bad)[:5], gb[bad][:5], ob[bad][:5])
+
+
+@pytest.mark.parametrize("maker", ["rect64_tiled", "large"])
+def test_per_parent_items_equal_per_action_items(maker, monkeypatch):
+    """The banded inner levels with one workgroup per (parent, band) over all
+    actions give bitwise the same tree as one workgroup per (parent, band,
+    action): the same sums in the same order."""
+    _say(f"per-parent vs per-action banded items {maker}")
+    from paper_1810_00204_amd.planner import Planner
+    if maker == "large":
+        prob, flags = wl.make_large(seed=0), 0
+        rng = np.random.default_rng(5)
+        Q32 = (rng.standard_normal((prob.S, prob.A)) * 10).astype(np.float32)
+        Q32[prob.occ == 1] = 0.0
+    else:
+        prob, flags = wl.make_rect(seed=3), B.QV_PLAN_TILED
+        Q32 = _q32(prob)
+    Qd = torch.as_tensor(Q32.reshape(-1)).cuda()
+    trees = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("QVTS_PER_ACTION_ITEMS", env)
+        pl = Planner(prob, flags=flags)
+        pl.plan(Qd)
+        t = pl.tree(beliefs=maker != "large")
+        if maker == "large":
+            t["b1"] = [pl.belief_of(1, int(s)) for s in np.flatnonzero(t["valid"][t["level_first"][1]:t["level_first"][2]])[:4]]
+        trees.append((t, pl.action.item(), pl.rootQ.cpu().numpy()))
+        del pl
+    (t1, a1, q1), (t2, a2, q2) = trees
+    assert a1 == a2 and np.array_equal(q1, q2)
+    ok = t1["valid"] == 1
+    assert np.array_equal(t1["valid"], t2["valid"])
+    for k in ("z", "count", "pz", "value"):
+        assert np.array_equal(t1[k][ok], t2[k][ok]), k
+    if maker == "large":
+        for x, y in zip(t1["b1"], t2["b1"]):
+            assert np.array_equal(x, y)
+    else:
+        for d in t1["beliefs"]:
+            assert np.array_equal(t1["beliefs"][d], t2["beliefs"][d])

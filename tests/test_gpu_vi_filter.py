@@ -58,8 +58,11 @@ def test_value_iteration_matches_fp64(maker):
     err = np.abs(Q32 - Q64).max()
     vmax = np.abs(Q64).max()
     print(f"max |Q32 - Q64| = {err:.3g} (|V|max {vmax:.3g}), sweeps {sw} (fp64 {sw64})")
-    # error bound ~ c * u * |V| / (1 - gamma) with a safety factor
-    assert err <= 50 * 2 ** -24 * max(1.0, vmax) / (1 - 0.95)
+    # the stopping rule leaves |V_k - V*| <= r_k gamma / (1 - gamma) with
+    # r_k <= tol * |V|, plus FP32 rounding of a few ulp per sweep, damped by
+    # 1 / (1 - gamma): (tol + 8u) |V| / (1 - gamma), about 1.6 times the
+    # largest error measured on these maps (1.8e-3 on the 50 x 100 one)
+    assert err <= (1e-6 + 8 * 2 ** -24) * max(1.0, vmax) / (1 - 0.95)
     assert np.all(Q32[prob.occ == 1] == 0)
     # the FP32 run stopped by its own rule
     assert sw < 20000
