@@ -9,15 +9,15 @@
 // of two FP32 values) and max-reduced with an integer atomic on its bit
 // pattern, which is order independent.
 //
-// All sweeps of a solve run in one cooperative launch: every workgroup is
-// resident, and after each sweep the workgroups meet at a grid barrier, read
-// the sweep's residual and max |value| and so all stop after the same sweep
-// (the stopping rule sees the same numbers everywhere).  The host waits once,
-// at the end.  Where a cooperative launch is not possible (or
-// QVTS_SWEEP_LAUNCHES=1), value iteration launches its sweeps one by one,
-// each doing nothing once the rule has fired, and reads the residuals every
-// kViChunk sweeps; FIB then runs the same per-sweep form.  Both forms do the
-// same arithmetic per cell, so their results are bitwise equal.
+// On small and medium grids all sweeps of a solve run in one cooperative
+// launch: every workgroup is resident, and after each sweep the workgroups
+// meet at a grid barrier, read the sweep's residual and max |value| and so
+// all stop after the same sweep (the stopping rule sees the same numbers
+// everywhere); the host waits once, at the end.  On large grids (and where a
+// cooperative launch is not possible) the sweeps are launched one by one,
+// each doing nothing once the rule has fired, and the host reads the
+// residuals every kViChunk sweeps.  Both forms do the same arithmetic per
+// cell, so their results are bitwise equal.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -688,12 +688,24 @@ static hipError_t sweep_setup(const DevModel &m, const SweepWs &w, long long val
   return hipGetLastError();
 }
 
+// Grids up to this many cells take the one-launch form; larger ones the
+// per-sweep launches.  Measured on MI355X (a sweep, one-launch vs
+// per-sweep): 4096 cells, value iteration 12.3 vs 15.3 us, FIB 44.7 vs 46.4;
+// 262144 cells, value iteration 20.4 vs 16.4, FIB 138 vs 123, blind bound
+// 162 vs 46 -- at that size the coherent loads of the gathered values (past
+// the L2) cost more than the launches they save.
+constexpr long long kCoopMaxCells = 16384;
+
 // Workgroups of a cooperative launch of `kernel`: at most `want`, and no
-// more than can be resident at once; 0 if a cooperative launch is not
-// possible here (or QVTS_SWEEP_LAUNCHES=1 asks for the per-sweep form).
-static int coop_grid(const void *kernel, size_t lds, int want) {
+// more than can be resident at once; 0 for the per-sweep form: a grid of
+// more than kCoopMaxCells cells, no cooperative launch on this device, or
+// QVTS_SWEEP_LAUNCHES=1.  QVTS_SWEEP_COOP=1 takes the one-launch form at
+// any size.
+static int coop_grid(const void *kernel, size_t lds, int want, long long cells) {
   const char *e = std::getenv("QVTS_SWEEP_LAUNCHES");
   if (e && std::atoi(e) == 1) return 0;
+  const char *f = std::getenv("QVTS_SWEEP_COOP");
+  if (!(f && std::atoi(f) == 1) && cells > kCoopMaxCells) return 0;
   int dev = 0, coop = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
@@ -768,7 +780,7 @@ hipError_t run_value_iteration(const DevModel &m, float tol, int max_sweeps, flo
   const int TH = tile_rows(m.W, m.H);
   const int tiles = (m.H + TH - 1) / TH;
   const size_t lds = (size_t)(TH + 2) * (m.W + 2) * sizeof(float);
-  const int G = coop_grid(reinterpret_cast<const void *>(&k_vi_coop), lds, tiles);
+  const int G = coop_grid(reinterpret_cast<const void *>(&k_vi_coop), lds, tiles, m.S);
   if (G > 0) {
     DevModel mm = m;
     const uint32_t *sig = w.sig;
@@ -806,7 +818,7 @@ static hipError_t run_fib_am(const DevModel &m, const SweepWs &w, float *alpha,
                              double *residual, int *sweeps, hipStream_t st) {
   const long long vals = (long long)m.S * m.A;
   const int want = (int)std::min<long long>((m.S + kBlock - 1) / kBlock, 1 << 20);
-  const int G = coop_grid(reinterpret_cast<const void *>(&k_fib_coop<AM, OP>), 0, want);
+  const int G = coop_grid(reinterpret_cast<const void *>(&k_fib_coop<AM, OP>), 0, want, m.S);
   hipError_t e;
   if (G > 0) {
     DevModel mm = m;

@@ -197,5 +197,9 @@ def summarize(runs) -> dict:
             "collisions": ms([r["collisions"] for r in runs]),
             "steps": ms([r["steps"] for r in ok]),
             "failure_rate": 1.0 - len(ok) / max(1, len(runs)),
+            "stopped": sum(1 for r in runs if r["stopped"]),
+            "stopped_off_target": sum(1 for r in runs if r["stopped"] and not r["success"]),
+            "lost": sum(1 for r in runs if r["lost"]),
+            "steps_all_runs": ms([r["steps"] for r in runs]),
             "planning_ms_per_step": ms(plan)}
 

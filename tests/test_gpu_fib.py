@@ -48,6 +48,15 @@ def _vi(prob, tol=1e-6, max_sweeps=20000):
     return Q.cpu().numpy().reshape(m.S, m.A), res, sw
 
 
+def _blind(prob, tol=1e-6, max_sweeps=20000):
+    m = B.DeviceModel(prob)
+    al = torch.empty(m.S * m.A, dtype=torch.float32, device="cuda")
+    ws = torch.empty(B.qv_blind_workspace_bytes(m, max_sweeps), dtype=torch.uint8, device="cuda")
+    st, res, sw = B.qv_blind_iterate(m, tol, max_sweeps, al, ws)
+    B.check(st, "qv_blind_iterate")
+    return al.cpu().numpy().reshape(m.S, m.A), res, sw
+
+
 def _problem(maker):
     return {"small": lambda: wl.make_small(seed=1),
             "rect32": lambda: wl.make_rect(seed=2, side=32, n_landmarks=8, D=2, n=2),
@@ -125,13 +134,14 @@ def test_fib_is_a_fixed_point_at_full_size(maker):
     assert np.all(al[free] <= Q[free] + 40 * U32 * amax / (1 - float(prob.gamma)))
 
 
-@pytest.mark.parametrize("solver", ["fib", "vi"])
+@pytest.mark.parametrize("solver", ["fib", "vi", "blind"])
 def test_one_launch_equals_per_sweep_launches(solver, monkeypatch):
     """The cooperative one-launch driver and the per-sweep launches do the
     same arithmetic: bitwise equal results, same sweep count and residual."""
     _say(f"{solver}: one launch vs per-sweep launches")
     prob = wl.make_rect(seed=6, side=40, n_landmarks=6, D=1, n=1)
-    run = _fib if solver == "fib" else _vi
+    run = {"fib": _fib, "vi": _vi, "blind": _blind}[solver]
+    monkeypatch.setenv("QVTS_SWEEP_COOP", "1")
     a1, r1, s1 = run(prob)
     monkeypatch.setenv("QVTS_SWEEP_LAUNCHES", "1")
     a2, r2, s2 = run(prob)
@@ -139,6 +149,7 @@ def test_one_launch_equals_per_sweep_launches(solver, monkeypatch):
     assert np.array_equal(a1, a2)
     # a capped run stops at the cap in both forms
     monkeypatch.delenv("QVTS_SWEEP_LAUNCHES")
+    monkeypatch.setenv("QVTS_SWEEP_COOP", "1")
     a3, r3, s3 = run(prob, tol=0.0, max_sweeps=5)
     monkeypatch.setenv("QVTS_SWEEP_LAUNCHES", "1")
     a4, r4, s4 = run(prob, tol=0.0, max_sweeps=5)
