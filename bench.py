@@ -61,7 +61,8 @@ def parse():
     ap.add_argument("--side-steps", type=int, default=200)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--filter-steps", type=int, default=5)
-    ap.add_argument("--loop-runs", type=int, default=20)
+    ap.add_argument("--loop-runs", type=int, default=10)
+    ap.add_argument("--loop-expansions", type=int, default=128)
     return ap.parse_args()
 
 
@@ -380,21 +381,57 @@ def bench_closed_loop(args, B, wl, torch, dev):
     """Closed-loop runs of the experiment model of Sec. V on the synthetic
     100 x 40 map (nine actions, 0.95 sensor, the paper's stage reward):
     plan, act in the simulated world, observe, update the belief, until the
-    robot stops or 300 steps; the comparison-table quantities over the runs."""
-    from paper_1810_00204_amd.experiment import ClosedLoop, summarize
+    robot stops or 400 steps; the comparison-table quantities over the runs,
+    for the anytime search (FIB upper bound, blind-policy lower bound, a
+    budget of expansions per step) and for the fixed-depth plan (Q-MDP
+    leaves).  Runs r use world seed 1000 + r and draw seed 2000 + r."""
+    from paper_1810_00204_amd.experiment import ClosedLoop, SearchLoop, summarize
+    from paper_1810_00204_amd.planner import Planner
     prob = wl.make_paper(seed=0)
-    Q, sweeps = gpu_q(B, torch, prob, dev)
-    cl = ClosedLoop(prob, Q)
-    cl.run(wl.Environment(prob, seed=999), seed=999, max_steps=5)   # warm-up
-    runs = [cl.run(wl.Environment(prob, seed=1000 + r), seed=2000 + r, max_steps=300)
+    pl = Planner(prob, device=dev)
+    Q, _, qs = pl.value_iterate(tol=1e-6)
+    F, _, fs = pl.fib_iterate(tol=1e-6)
+    Lb, _, ls = pl.blind_iterate(tol=1e-6)
+    desc = (f"{prob.name}: synthetic {prob.W}x{prob.H} map, 9 actions, wall bits read correctly "
+            "w.p. 0.95, r in {-2,-1,0}, gamma 0.95, start belief uniform over free cells, "
+            "stop on the stay action, 400-step cap")
+    sl = SearchLoop(prob, F, Lb, expansions=args.loop_expansions, n=prob.n)
+    runs = [sl.run(wl.Environment(prob, seed=1000 + r), seed=2000 + r, max_steps=400)
             for r in range(args.loop_runs)]
-    out = summarize(runs)
-    out.update({"workload": f"{prob.name}: synthetic {prob.W}x{prob.H} map, 9 actions, "
-                            "wall bits read correctly w.p. 0.95, r in {-2,-1,0}, gamma 0.95, "
-                            "start belief uniform over free cells, stop on the stay action",
-                "depth": prob.D, "samples_per_action": prob.n, "max_steps": 300,
-                "value_iteration_sweeps": sweeps})
-    return out
+    search = summarize(runs)
+    search.update({"planner": f"best-first search, {args.loop_expansions} expansions per step, "
+                              f"n {prob.n}, U = FIB, L = blind policies, action = argmax L_Q"})
+    cl = ClosedLoop(prob, Q)
+    runs = [cl.run(wl.Environment(prob, seed=1000 + r), seed=2000 + r, max_steps=400)
+            for r in range(args.loop_runs)]
+    plan = summarize(runs)
+    plan.update({"planner": f"fixed-depth plan, D {prob.D}, n {prob.n}, Q-MDP leaves"})
+    return {"workload": desc, "search": search, "plan": plan,
+            "sweeps": {"value_iteration": qs, "fib": fs, "blind": ls}}
+
+
+def bench_search(B, torch, dev, wl, expansions=256):
+    """Best-first expansions/s on the 100 x 40 experiment map (9 actions,
+    n 3): one search of `expansions` expansions from the uniform belief."""
+    from paper_1810_00204_amd.planner import Planner, SearchPlanner
+    prob = wl.make_paper(seed=0)
+    pl = Planner(prob, device=dev)
+    F, _, _ = pl.fib_iterate(tol=1e-6)
+    Lb, _, _ = pl.blind_iterate(tol=1e-6)
+    sp = SearchPlanner(prob, F, Lb, max_nodes=1 + expansions * prob.A * prob.n, device=dev)
+    sp.init()
+    sp.expand(8, seed=1, query_id=0)
+    torch.cuda.synchronize()
+    sp.init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sp.expand(expansions, seed=1, query_id=0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g = sp.records()
+    return {"workload": f"{prob.name}, uniform start belief", "expansions": g["expansions"],
+            "ms": dt * 1e3, "expansions_per_s": g["expansions"] / dt,
+            "nodes": int(g["next"]), "child_nodes_per_s": (int(g["next"]) - 1) / dt}
 
 
 def bench_fib(B, torch, dev, prob):
@@ -490,9 +527,11 @@ def main():
         progress(f"filter: {line['filter']['ms_per_eval']:.3f} ms per evaluation")
         line["fib"] = bench_fib(B, torch, dev, prob)
         progress(f"fib: {line['fib']['sweeps']} sweeps in {line['fib']['ms']:.2f} ms")
+        line["search"] = bench_search(B, torch, dev, wl)
+        progress(f"search: {line['search']['expansions_per_s']:.0f} expansions/s")
         line["closed_loop"] = bench_closed_loop(args, B, wl, torch, dev)
-        progress(f"closed loop: {line['closed_loop']['runs']} runs, failure rate "
-                 f"{line['closed_loop']['failure_rate']:.2f}")
+        progress(f"closed loop: failure rate search {line['closed_loop']['search']['failure_rate']:.2f}, "
+                 f"plan {line['closed_loop']['plan']['failure_rate']:.2f}")
     if cpu is not None:
         line["cpu_baseline"] = cpu
     print(json.dumps(line), flush=True)
