@@ -490,3 +490,134 @@ def search(prob, Ut, Lt, expansions, n=None, seed=None, qid=None, b0=None):
         if not t.expand():
             break
     return t
+
+
+# ---------------------------------------------------------------------------
+# Point-based value iteration (Sec. IV-B), FP64, numpy on the oracle's own
+# model pieces (prediction, likelihood, observation probabilities, draws).
+# ---------------------------------------------------------------------------
+
+def _successor_table(prob):
+    """dest[x, k]: the cell that neighbour move k leads to from x (the cell
+    itself when the target is blocked or off the grid; the goal and blocked
+    cells keep every move at themselves)."""
+    W, H = prob.W, prob.H
+    occ = np.asarray(prob.occ).reshape(-1)
+    dest = np.zeros((W * H, 9), dtype=np.int64)
+    for x in range(W * H):
+        y0, x0 = divmod(x, W)
+        for k in range(9):
+            dy, dx = k // 3 - 1, k % 3 - 1
+            yy, xx = y0 + dy, x0 + dx
+            t = yy * W + xx
+            ok = 0 <= yy < H and 0 <= xx < W and not occ[t]
+            dest[x, k] = t if ok and not occ[x] and x != prob.goal else x
+    return dest
+
+
+def _obs_table(prob):
+    """O[x, z] = P(z | x) for every cell and observation."""
+    m = Model(prob)
+    O = np.zeros((m.S, m.Z))
+    for x in range(m.S):
+        if prob.occ[x]:
+            continue
+        for z in range(m.Z):
+            O[x, z] = lib().qvo_obs_prob(m.ref, int(z), int(x))
+    return O
+
+
+class PBVI:
+    """Point-based value iteration of Sec. IV-B: a set of belief points, one
+    alpha vector per point, backed up with the PBVI Bellman equation:
+      for every action a and observation z, the vector of Gamma best at the
+      point's predicted belief weighted by O(z|.) (first maximum on ties);
+      alpha_a = R_a + gamma sum_z T_a (O_z * alpha_{a,z});
+      the point's new vector is the alpha_a of largest b.alpha_a.
+    The set grows by the expansion the paper follows (Pineau et al.): every
+    point draws one observation per action (inverse CDF on P(z|b,a), uniform
+    from the Philox stream with counter (a, point, 64 + round, query)) and
+    adds the posterior farthest in L1 from the current set (first maximum;
+    not added at distance 0).  Gamma starts from `init` [S, k] (a lower
+    bound, e.g. the blind-policy vectors); every backed-up vector is a
+    policy's value, so V(b) = max_alpha b.alpha stays a lower bound."""
+
+    def __init__(self, prob, init, seed, qid=0):
+        self.prob, self.seed, self.qid = prob, seed, qid
+        self.g = float(np.float32(prob.gamma))
+        self.R = _f64(prob.R).reshape(prob.S, prob.A)
+        self.dest = _successor_table(prob)
+        self.slip = _f64(prob.slip).reshape(prob.A, 9)
+        self.O = _obs_table(prob)
+        self.free = np.asarray(prob.occ).reshape(-1) == 0
+        self.B = [_f64(prob.b0)]
+        self.Gamma = _f64(init).reshape(prob.S, -1).copy()
+        self.rounds = 0
+        self.draw_margins = []
+        self.pick_gaps = []
+
+    def _apply_T(self, a, v):
+        """(T_a v)(x) = sum_x' T(x, a, x') v(x'); the goal is absorbing."""
+        out = (v[self.dest] * self.slip[a][None, :]).sum(1)
+        if self.prob.goal >= 0:
+            out[self.prob.goal] = v[self.prob.goal]
+        return out
+
+    def expand(self):
+        prob, A = self.prob, self.prob.A
+        cur = np.array(self.B)
+        new = []
+        for i, b in enumerate(self.B):
+            best, bd = None, 0.0
+            for a in range(A):
+                bp = predict(prob, b, a)
+                p = likelihood(prob, bp)
+                u = obs_uniform(self.seed, self.qid, 64 + self.rounds, i, a, 1, 0)
+                z, mg = draw_obs(p, u)
+                self.draw_margins.append(mg)
+                post = self.O[:, z] * bp / p[z]
+                d = float(np.abs(cur - post[None, :]).sum(1).min())
+                if d > bd:
+                    best, bd = post, d
+            if best is not None:
+                new.append(best)
+        self.B.extend(new)
+        self.rounds += 1
+        return len(new)
+
+    def backup(self):
+        prob, A, g = self.prob, self.prob.A, self.g
+        G = self.Gamma
+        out = np.zeros((prob.S, len(self.B)))
+        for i, b in enumerate(self.B):
+            vals, cands = np.zeros(A), []
+            for a in range(A):
+                bp = predict(prob, b, a)
+                # values of every vector at every observation: (O_z * b') . alpha
+                V = (self.O * bp[:, None]).T @ G          # [Z, |Gamma|]
+                idx = V.argmax(1)
+                srt = np.sort(V, axis=1)
+                if V.shape[1] > 1:
+                    top = srt[:, -1]
+                    self.pick_gaps.append(float(((top - srt[:, -2]) / np.maximum(np.abs(top), 1e-300)).min()))
+                # sum_z T_a (O_z * alpha_{a,z}) = T_a (sum_z O_z * alpha_{a,z})
+                acc = self._apply_T(a, (self.O * G[:, idx]).sum(1))
+                al = np.where(self.free, self.R[:, a] + g * acc, 0.0)
+                vals[a] = b @ al
+                cands.append(al)
+            out[:, i] = cands[int(np.argmax(vals))]
+        self.Gamma = out
+        return out
+
+    def value(self, b):
+        return float(np.max(_f64(b) @ self.Gamma))
+
+
+def pbvi(prob, init, expansions, sweeps, seed, qid=0):
+    """`expansions` rounds of (expand the point set, then `sweeps` backups)."""
+    t = PBVI(prob, init, seed, qid)
+    for _ in range(expansions):
+        t.expand()
+        for _ in range(sweeps):
+            t.backup()
+    return t
