@@ -56,6 +56,7 @@ extern "C" {
 #define QV_MAX_LANDMARKS 511
 #define QV_MAX_SIDE 2048      /* W and H */
 #define QV_WORKSPACE_ALIGN 256
+#define QV_MAX_BOUND_COLS 1024 /* columns of a lower-bound table (qv_search_*, qv_pbvi) */
 
 /* ---- plan flags -------------------------------------------------------- */
 /* Store the depth-D (leaf) beliefs in the workspace and score them in a
@@ -242,9 +243,11 @@ int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
  * A QV-tree grown one V-node expansion at a time, always at the node the
  * root's heuristic points to (findVNodeToExpand), in a node pool held in
  * the workspace.  A new V-node (Alg. 5) takes U = max_a' b.U_table[.,a']
- * and L = max_a' b.L_table[.,a'] (U_table, L_table: device [S*A] FP32,
- * e.g. the FIB vectors of qv_fib_iterate and the blind-policy vectors of
- * qv_blind_iterate), H = U - L and E = itself.  Expanding V-node v runs,
+ * and L = max_j b.L_table[.,j] (U_table: device [S*A] FP32, e.g. the FIB
+ * vectors of qv_fib_iterate; L_table: device [S*l_cols] FP32, row-major by
+ * cell, e.g. the blind-policy vectors of qv_blind_iterate (l_cols = A) or
+ * the PBVI vectors of qv_pbvi (l_cols = its point capacity)), H = U - L and
+ * E = itself.  Expanding V-node v runs,
  * per action a, the prediction, P(z|b,a), n draws keyed by (node id, depth,
  * query_id) as in qv_plan_step, the distinct children Phi(b,a,z) with weight
  * f/n and their bounds (Alg. 2-5); then every ancestor is updated (Alg. 6:
@@ -289,17 +292,18 @@ size_t qv_search_workspace_bytes(const qv_model *m, int32_t n, int32_t max_nodes
 int32_t qv_search_layout_of(const qv_model *m, int32_t n, int32_t max_nodes,
                             qv_search_layout *out /* host */);
 int32_t qv_search_init(const qv_model *m, const float *U_table, const float *L_table,
-                       const float *b0, int32_t n, int32_t max_nodes, void *ws, size_t ws_bytes,
-                       void *stream);
+                       int32_t l_cols, const float *b0, int32_t n, int32_t max_nodes, void *ws,
+                       size_t ws_bytes, void *stream);
 int32_t qv_search_expand(const qv_model *m, const float *U_table, const float *L_table,
-                         int32_t n, int32_t max_nodes, uint64_t seed, uint32_t query_id,
-                         int32_t expansions, void *ws, size_t ws_bytes, void *stream);
+                         int32_t l_cols, int32_t n, int32_t max_nodes, uint64_t seed,
+                         uint32_t query_id, int32_t expansions, void *ws, size_t ws_bytes,
+                         void *stream);
 int32_t qv_search_result(const qv_model *m, int32_t n, int32_t max_nodes, int32_t *action_out,
                          float *rootU_out, float *rootL_out, void *ws, size_t ws_bytes,
                          void *stream);
 int32_t qv_search_update(const qv_model *m, const float *U_table, const float *L_table,
-                         int32_t n, int32_t max_nodes, int32_t a, int32_t z, void *ws,
-                         size_t ws_bytes, void *stream);
+                         int32_t l_cols, int32_t n, int32_t max_nodes, int32_t a, int32_t z,
+                         void *ws, size_t ws_bytes, void *stream);
 
 /* ---- batched planning ------------------------------------------------------
  * Many independent planning steps (Alg. 1 inner loop, as qv_plan_step), each

@@ -137,15 +137,16 @@ def lib():
         L.qv_search_workspace_bytes.restype = C.c_size_t
         L.qv_search_layout_of.argtypes = [mp, C.c_int32, C.c_int32, C.POINTER(qv_search_layout)]
         L.qv_search_layout_of.restype = C.c_int32
-        L.qv_search_init.argtypes = [mp, vp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+        L.qv_search_init.argtypes = [mp, vp, vp, C.c_int32, vp, C.c_int32, C.c_int32, vp,
+                                     C.c_size_t, vp]
         L.qv_search_init.restype = C.c_int32
-        L.qv_search_expand.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
-                                       C.c_int32, vp, C.c_size_t, vp]
+        L.qv_search_expand.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                       C.c_uint32, C.c_int32, vp, C.c_size_t, vp]
         L.qv_search_expand.restype = C.c_int32
         L.qv_search_result.argtypes = [mp, C.c_int32, C.c_int32, vp, vp, vp, vp, C.c_size_t, vp]
         L.qv_search_result.restype = C.c_int32
         L.qv_search_update.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                       vp, C.c_size_t, vp]
+                                       C.c_int32, vp, C.c_size_t, vp]
         L.qv_search_update.restype = C.c_int32
         L.qv_fib_workspace_bytes.argtypes = [mp, C.c_int32]
         L.qv_fib_workspace_bytes.restype = C.c_size_t
@@ -282,14 +283,15 @@ def qv_search_layout_of(model, n: int, max_nodes: int):
     return int(st), out
 
 
-def qv_search_init(model, Ut, Lt, b0, n, max_nodes, ws, stream=None) -> int:
-    return int(lib().qv_search_init(C.byref(model.c), _ptr(Ut), _ptr(Lt), _ptr(b0), int(n),
-                                    int(max_nodes), _ptr(ws), _nbytes(ws), _stream(stream)))
+def qv_search_init(model, Ut, Lt, l_cols, b0, n, max_nodes, ws, stream=None) -> int:
+    return int(lib().qv_search_init(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(l_cols), _ptr(b0),
+                                    int(n), int(max_nodes), _ptr(ws), _nbytes(ws),
+                                    _stream(stream)))
 
 
-def qv_search_expand(model, Ut, Lt, n, max_nodes, seed, query_id, expansions, ws,
+def qv_search_expand(model, Ut, Lt, l_cols, n, max_nodes, seed, query_id, expansions, ws,
                      stream=None) -> int:
-    return int(lib().qv_search_expand(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(n),
+    return int(lib().qv_search_expand(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(l_cols), int(n),
                                       int(max_nodes), C.c_uint64(int(seed) & (2 ** 64 - 1)),
                                       C.c_uint32(int(query_id) & (2 ** 32 - 1)),
                                       int(expansions), _ptr(ws), _nbytes(ws), _stream(stream)))
@@ -302,8 +304,8 @@ def qv_search_result(model, n, max_nodes, action_out, rootU_out, rootL_out, ws,
                                       _ptr(ws), _nbytes(ws), _stream(stream)))
 
 
-def qv_search_update(model, Ut, Lt, n, max_nodes, a, z, ws, stream=None) -> int:
-    return int(lib().qv_search_update(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(n),
+def qv_search_update(model, Ut, Lt, l_cols, n, max_nodes, a, z, ws, stream=None) -> int:
+    return int(lib().qv_search_update(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(l_cols), int(n),
                                       int(max_nodes), int(a), int(z), _ptr(ws), _nbytes(ws),
                                       _stream(stream)))
 

@@ -135,7 +135,8 @@ struct BatchPrep {
 struct SearchArgs {
   int n, K, NV;                 // samples per action, |A| n, node capacity
   uint32_t key0, key1, qid;     // Philox key and query id of the draws
-  const float *Ut, *Lt;         // upper / lower bound tables [S*A]
+  const float *Ut, *Lt;         // upper [S*A] / lower [S*lcols] bound tables
+  int lcols;                    // columns of the lower-bound table
   const uint32_t *sig;
   const float *staytab;
   const uint32_t *lm_wall;

@@ -2872,41 +2872,54 @@ __host__ __device__ inline size_t search_lds_floats(int W, int H) {
 }
 
 // Bounds of a belief held as v(t) = scale * o(t) * bp(t) over all cells:
-// block sums of v(t) Ut(t, a') and v(t) Lt(t, a') (FP32, fixed order), then
-// the maxima over a' (lane 0 of thread 0 gets them).  o(t) = 1 when zr < 0.
+// block sums of v(t) Ut(t, a') (A columns) and v(t) Lt(t, j) (sa.lcols
+// columns), each in a fixed order, then the maxima U and L (every thread gets
+// them).  o(t) = 1 when zr < 0.  The first pass also writes v to out_b and
+// takes the U columns with the first 16 L columns; further passes take 32 L
+// columns each.
 __device__ void search_bounds(const DevModel &m, const SearchArgs &sa, const float *bpl,
                               int zr, float scale, float *out_b, float *red, float &U,
                               float &L) {
-  const int A = m.A, S = m.S;
-  float acc[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) acc[i] = 0.f;
+  const int A = m.A, S = m.S, LC = sa.lcols;
   const uint32_t zw = (uint32_t)(zr & 15), zl = (uint32_t)(zr >> 4);
-  for (int t = threadIdx.x; t < S; t += kBlock) {
-    const uint32_t sg = sa.sig[t];
-    float o = 1.f;
-    if (zr >= 0) o = wall_lik(m.flip, zw, sig_wall(sg)) * lm_lik(m.lm_p, zl, sig_lm(sg));
-    const float v = o * bpl[t] * scale;
-    if (out_b) out_b[t] = v;
-#pragma unroll
-    for (int c = 0; c < QV_MAX_ACTIONS; ++c) {
-      if (c < A) {
-        acc[c] = fmaf(v, sa.Ut[(size_t)t * A + c], acc[c]);
-        acc[16 + c] = fmaf(v, sa.Lt[(size_t)t * A + c], acc[16 + c]);
-      }
-    }
-  }
-  const float tot = block_sum32(acc, red);
-  // thread c < 32 holds the total of value c; the maxima through LDS
-  if (threadIdx.x < 32) red[threadIdx.x] = tot;
-  __syncthreads();
   U = -INFINITY;
   L = -INFINITY;
-  for (int c = 0; c < A; ++c) {
-    U = fmaxf(U, red[c]);
-    L = fmaxf(L, red[16 + c]);
+  for (int c0 = -16; c0 < LC; c0 += 32) {
+    // c0 < 0: values 0..15 are the U columns, 16..31 the L columns 0..15;
+    // else values 0..31 are the L columns c0 .. c0+31
+    float acc[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) acc[i] = 0.f;
+    for (int t = threadIdx.x; t < S; t += kBlock) {
+      const uint32_t sg = sa.sig[t];
+      float o = 1.f;
+      if (zr >= 0) o = wall_lik(m.flip, zw, sig_wall(sg)) * lm_lik(m.lm_p, zl, sig_lm(sg));
+      const float v = o * bpl[t] * scale;
+      if (c0 < 0) {
+        if (out_b) out_b[t] = v;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          if (c < A) acc[c] = fmaf(v, sa.Ut[(size_t)t * A + c], acc[c]);
+          if (c < LC) acc[16 + c] = fmaf(v, sa.Lt[(size_t)t * LC + c], acc[16 + c]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 32; ++c)
+          if (c0 + c < LC) acc[c] = fmaf(v, sa.Lt[(size_t)t * LC + c0 + c], acc[c]);
+      }
+    }
+    const float tot = block_sum32(acc, red);
+    // thread c < 32 holds the total of value c; the maxima through LDS
+    if (threadIdx.x < 32) red[threadIdx.x] = tot;
+    __syncthreads();
+    if (c0 < 0) {
+      for (int c = 0; c < A; ++c) U = fmaxf(U, red[c]);
+      for (int c = 0; c < 16 && c < LC; ++c) L = fmaxf(L, red[16 + c]);
+    } else {
+      for (int c = 0; c < 32 && c0 + c < LC; ++c) L = fmaxf(L, red[c]);
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // The new node c's records (its belief is already in place).

@@ -68,7 +68,7 @@ static bool search_layout_impl(const qv_model *m, int n, int max_nodes, qv_searc
 }
 
 static SearchArgs search_args(const qv_search_layout &L, const float *Ut, const float *Lt,
-                              uint64_t seed, uint32_t qid, char *ws) {
+                              int lcols, uint64_t seed, uint32_t qid, char *ws) {
   SearchArgs sa;
   std::memset(&sa, 0, sizeof sa);
   sa.n = L.n;
@@ -79,6 +79,7 @@ static SearchArgs search_args(const qv_search_layout &L, const float *Ut, const 
   sa.qid = qid;
   sa.Ut = Ut;
   sa.Lt = Lt;
+  sa.lcols = lcols;
   sa.sig = (const uint32_t *)(ws + L.sig);
   sa.staytab = (const float *)(ws + L.staytab);
   sa.lm_wall = (const uint32_t *)(ws + L.lm_wall);
@@ -140,16 +141,17 @@ int32_t qv_search_layout_of(const qv_model *m, int32_t n, int32_t max_nodes,
 }
 
 int32_t qv_search_init(const qv_model *m, const float *U_table, const float *L_table,
-                       const float *b0, int32_t n, int32_t max_nodes, void *ws, size_t ws_bytes,
-                       void *stream) {
+                       int32_t l_cols, const float *b0, int32_t n, int32_t max_nodes, void *ws,
+                       size_t ws_bytes, void *stream) {
   qv_search_layout L;
   int32_t st = search_check(m, n, max_nodes, ws, ws_bytes, &L);
   if (st != QV_OK) return st;
-  if (!U_table || !L_table || !b0) return QV_ERR_INVALID_ARG;
+  if (!U_table || !L_table || !b0 || l_cols < 1 || l_cols > QV_MAX_BOUND_COLS)
+    return QV_ERR_INVALID_ARG;
   const DevModel dm = make_dev_model(m);
   char *w = (char *)ws;
   hipStream_t hs = (hipStream_t)stream;
-  const SearchArgs sa = search_args(L, U_table, L_table, 0, 0, w);
+  const SearchArgs sa = search_args(L, U_table, L_table, l_cols, 0, 0, w);
   st = hip_status(launch_prep_lm(dm, (uint32_t *)(w + L.sig), (float *)(w + L.staytab),
                                  (int32_t *)(w + L.err), (uint32_t *)(w + L.lm_wall), hs));
   if (st != QV_OK) return st;
@@ -157,14 +159,16 @@ int32_t qv_search_init(const qv_model *m, const float *U_table, const float *L_t
 }
 
 int32_t qv_search_expand(const qv_model *m, const float *U_table, const float *L_table,
-                         int32_t n, int32_t max_nodes, uint64_t seed, uint32_t query_id,
-                         int32_t expansions, void *ws, size_t ws_bytes, void *stream) {
+                         int32_t l_cols, int32_t n, int32_t max_nodes, uint64_t seed,
+                         uint32_t query_id, int32_t expansions, void *ws, size_t ws_bytes,
+                         void *stream) {
   qv_search_layout L;
   int32_t st = search_check(m, n, max_nodes, ws, ws_bytes, &L);
   if (st != QV_OK) return st;
-  if (!U_table || !L_table || expansions < 0) return QV_ERR_INVALID_ARG;
+  if (!U_table || !L_table || expansions < 0 || l_cols < 1 || l_cols > QV_MAX_BOUND_COLS)
+    return QV_ERR_INVALID_ARG;
   const DevModel dm = make_dev_model(m);
-  const SearchArgs sa = search_args(L, U_table, L_table, seed, query_id, (char *)ws);
+  const SearchArgs sa = search_args(L, U_table, L_table, l_cols, seed, query_id, (char *)ws);
   for (int e = 0; e < expansions; ++e) {
     st = hip_status(launch_search(1, dm, sa, nullptr, 0, 0, nullptr, nullptr, nullptr,
                                   (hipStream_t)stream));
@@ -181,22 +185,23 @@ int32_t qv_search_result(const qv_model *m, int32_t n, int32_t max_nodes, int32_
   if (st != QV_OK) return st;
   if (!action_out || !rootU_out || !rootL_out) return QV_ERR_INVALID_ARG;
   const DevModel dm = make_dev_model(m);
-  const SearchArgs sa = search_args(L, nullptr, nullptr, 0, 0, (char *)ws);
+  const SearchArgs sa = search_args(L, nullptr, nullptr, 1, 0, 0, (char *)ws);
   return hip_status(launch_search(2, dm, sa, nullptr, 0, 0, action_out, rootU_out, rootL_out,
                                   (hipStream_t)stream));
 }
 
 int32_t qv_search_update(const qv_model *m, const float *U_table, const float *L_table,
-                         int32_t n, int32_t max_nodes, int32_t a, int32_t z, void *ws,
-                         size_t ws_bytes, void *stream) {
+                         int32_t l_cols, int32_t n, int32_t max_nodes, int32_t a, int32_t z,
+                         void *ws, size_t ws_bytes, void *stream) {
   qv_search_layout L;
   int32_t st = search_check(m, n, max_nodes, ws, ws_bytes, &L);
   if (st != QV_OK) return st;
-  if (!U_table || !L_table || a < 0 || a >= m->A || z < 0 || z >= 16 * (m->L + 1))
+  if (!U_table || !L_table || a < 0 || a >= m->A || z < 0 || z >= 16 * (m->L + 1) ||
+      l_cols < 1 || l_cols > QV_MAX_BOUND_COLS)
     return QV_ERR_INVALID_ARG;
   const DevModel dm = make_dev_model(m);
   hipStream_t hs = (hipStream_t)stream;
-  const SearchArgs sa = search_args(L, U_table, L_table, 0, 0, (char *)ws);
+  const SearchArgs sa = search_args(L, U_table, L_table, l_cols, 0, 0, (char *)ws);
   st = hip_status(launch_search(3, dm, sa, nullptr, a, z, nullptr, nullptr, nullptr, hs));
   if (st != QV_OK) return st;
   int32_t err = 0;

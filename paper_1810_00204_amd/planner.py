@@ -203,6 +203,8 @@ class SearchPlanner:
             return t if hasattr(t, "data_ptr") else torch.as_tensor(
                 np.ascontiguousarray(t, np.float32).reshape(-1)).to(device)
         self.Ut, self.Lt = dev(Ut), dev(Lt)
+        # columns of the lower-bound table (blind: A; PBVI: its point capacity)
+        self.lcols = int(self.Lt.numel()) // prob.S
         nb = B.qv_search_workspace_bytes(self.m, self.n, self.max_nodes)
         if nb == 0:
             raise B.QvError(B.QV_ERR_UNSUPPORTED, "qv_search_workspace_bytes")
@@ -218,12 +220,12 @@ class SearchPlanner:
         bt = b0 if hasattr(b0, "data_ptr") else self.torch.as_tensor(
             np.ascontiguousarray(b0, np.float32)).to(self.device)
         self._b0 = bt
-        B.check(B.qv_search_init(self.m, self.Ut, self.Lt, bt, self.n, self.max_nodes, self.ws,
-                                 stream), "qv_search_init")
+        B.check(B.qv_search_init(self.m, self.Ut, self.Lt, self.lcols, bt, self.n, self.max_nodes,
+                                 self.ws, stream), "qv_search_init")
 
     def expand(self, expansions: int, seed=None, query_id=None, stream=None):
         p = self.prob
-        B.check(B.qv_search_expand(self.m, self.Ut, self.Lt, self.n, self.max_nodes,
+        B.check(B.qv_search_expand(self.m, self.Ut, self.Lt, self.lcols, self.n, self.max_nodes,
                                    p.seed if seed is None else seed,
                                    p.query_id if query_id is None else query_id,
                                    int(expansions), self.ws, stream), "qv_search_expand")
@@ -234,8 +236,8 @@ class SearchPlanner:
         return self.action, self.rootU, self.rootL
 
     def update(self, a: int, z: int, stream=None) -> int:
-        return B.qv_search_update(self.m, self.Ut, self.Lt, self.n, self.max_nodes, int(a),
-                                  int(z), self.ws, stream)
+        return B.qv_search_update(self.m, self.Ut, self.Lt, self.lcols, self.n, self.max_nodes,
+                                  int(a), int(z), self.ws, stream)
 
     def records(self, beliefs: bool = False) -> dict:
         """Copies the node records (and optionally the beliefs) out of the
