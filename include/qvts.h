@@ -246,7 +246,7 @@ int32_t qv_plan_layout(const qv_model *m, int32_t D, int32_t n, int32_t flags,
  * and L = max_j b.L_table[.,j] (U_table: device [S*A] FP32, e.g. the FIB
  * vectors of qv_fib_iterate; L_table: device [S*l_cols] FP32, row-major by
  * cell, e.g. the blind-policy vectors of qv_blind_iterate (l_cols = A) or
- * the PBVI vectors of qv_pbvi (l_cols = its point capacity)), H = U - L and
+ * the PBVI vectors of qv_pbvi_result (l_cols = its ld_out)), H = U - L and
  * E = itself.  Expanding V-node v runs,
  * per action a, the prediction, P(z|b,a), n draws keyed by (node id, depth,
  * query_id) as in qv_plan_step, the distinct children Phi(b,a,z) with weight
@@ -304,6 +304,67 @@ int32_t qv_search_result(const qv_model *m, int32_t n, int32_t max_nodes, int32_
 int32_t qv_search_update(const qv_model *m, const float *U_table, const float *L_table,
                          int32_t l_cols, int32_t n, int32_t max_nodes, int32_t a, int32_t z,
                          void *ws, size_t ws_bytes, void *stream);
+
+/* ---- point-based value iteration: Sec. IV-B ----------------------------
+ * A lower bound V(b) = max_j b.alpha_j from a set of belief points and one
+ * alpha vector per point, held in the workspace (vectors row-major by cell,
+ * a table [S][ld] as the search's L_table).  The set starts as {b0} and the
+ * vectors as `init` (device [S*init_cols] FP32 row-major by cell; a lower
+ * bound such as the blind-policy vectors of qv_blind_iterate, so that every
+ * later vector is a policy's value and V stays a lower bound).
+ *   qv_pbvi_expand: every point draws one observation per action (P(z|b,a)
+ *     by inverse CDF on one uniform from the Philox stream of qv_plan_step
+ *     with counter (a, point, 64 + round, query_id)), and the posterior
+ *     farthest in L1 from the set joins it (first maximum over actions; none
+ *     at distance 0), in point order while fewer than max_points are held.
+ *     The round counts the calls since qv_pbvi_init.  Synchronous; the number
+ *     of points added goes to *added_out (host).
+ *   qv_pbvi_backup: `sweeps` PBVI backups of every point: per action a and
+ *     observation z the vector j of largest sum_x O(z|x) b'(x) alpha_j(x)
+ *     (b' = T_a^T b; first maximum), alpha_a = R_a + gamma sum_z T_a
+ *     (O_z * alpha_{a,z}) on free cells (0 on blocked ones), and the point's
+ *     new vector is the alpha_a of largest b.alpha_a (first maximum); after
+ *     a backup there is one vector per point.  Async after reading 20 bytes.
+ *   qv_pbvi_result: the vectors into gamma_out (device [S][ld_out] FP32,
+ *     columns beyond the vector count repeat column 0, which leaves the
+ *     maximum unchanged) and the point count into *npoints_out (host).
+ *     Synchronous.
+ * Grids whose belief, prediction and bins fit in LDS only (as the search);
+ * max_points and init_cols in 1..QV_PBVI_MAX_POINTS; otherwise
+ * QV_ERR_UNSUPPORTED / QV_ERR_INVALID_ARG.  The same (m, max_points,
+ * init_cols) must be passed to every call on one workspace.
+ *   qv_pbvi_layout_of: where the points and the last backup's choices are. */
+#define QV_PBVI_MAX_POINTS 256
+typedef struct qv_pbvi_layout {
+  int32_t A, S, ZC, max_points, ld;   /* ZC = 16 (L + 1) observations; ld = table columns */
+  size_t sig, staytab, lm_wall;
+  size_t points;      /* float [max_points][S] */
+  size_t pred;        /* float [max_points][A][S]: b' = T_a^T b */
+  size_t cand;        /* float [max_points][A][S]: alpha_a of the last backup */
+  size_t idx;         /* int32 [max_points][A][ZC]: vector chosen per observation */
+  size_t vals;        /* float [max_points][A]: b.alpha_a of the last backup */
+  size_t dist;        /* float [max_points][A]: L1 distance of the last expansion's posteriors */
+  size_t dvalid, dz, dcount, dpz;   /* [max_points][A]: that expansion's draws */
+  size_t src;         /* int32 [max_points]: point * A + action of each added point */
+  size_t pick;        /* int32 [max_points]: action picked by the last backup */
+  size_t gamma0, gamma1;            /* float [S][ld] vector tables */
+  size_t ctl;         /* int32: points, round, current table (0/1), vectors, added */
+  size_t err;
+  size_t total_bytes;
+} qv_pbvi_layout;
+size_t qv_pbvi_workspace_bytes(const qv_model *m, int32_t max_points, int32_t init_cols);
+int32_t qv_pbvi_layout_of(const qv_model *m, int32_t max_points, int32_t init_cols,
+                          qv_pbvi_layout *out /* host */);
+int32_t qv_pbvi_init(const qv_model *m, const float *b0, const float *init, int32_t init_cols,
+                     int32_t max_points, void *ws, size_t ws_bytes, void *stream);
+int32_t qv_pbvi_expand(const qv_model *m, int32_t init_cols, int32_t max_points, uint64_t seed,
+                       uint32_t query_id, int32_t *added_out /* host */, void *ws,
+                       size_t ws_bytes, void *stream);
+int32_t qv_pbvi_backup(const qv_model *m, int32_t init_cols, int32_t max_points, int32_t sweeps,
+                       void *ws, size_t ws_bytes, void *stream);
+int32_t qv_pbvi_result(const qv_model *m, int32_t init_cols, int32_t max_points, float *gamma_out,
+                       int32_t ld_out, int32_t *npoints_out /* host */, void *ws,
+                       size_t ws_bytes, void *stream);
 
 /* ---- batched planning ------------------------------------------------------
  * Many independent planning steps (Alg. 1 inner loop, as qv_plan_step), each

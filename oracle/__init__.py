@@ -377,7 +377,9 @@ class SearchTree:
     def __init__(self, prob, Ut, Lt, n, seed, qid, b0, tie=1e-9):
         self.prob, self.n, self.seed, self.qid = prob, n, seed, qid
         self.Ut = _f64(Ut).reshape(prob.S, prob.A)
-        self.Lt = _f64(Lt).reshape(prob.S, prob.A)
+        # V_L(b) = max over the lower table's columns (A blind vectors, or
+        # one vector per point of a point-based bound)
+        self.Lt = _f64(Lt).reshape(prob.S, -1)
         # gamma as the model carries it (an FP32 input, widened exactly)
         self.A, self.K, self.g = prob.A, prob.A * n, float(np.float32(prob.gamma))
         self.nodes = {}

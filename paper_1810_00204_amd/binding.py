@@ -31,6 +31,8 @@ QV_MAX_SAMPLES = 16
 QV_PLAN_STORE_LEAVES = 1
 QV_PLAN_TILED = 2
 QV_PLAN_CHECK = 4
+QV_MAX_BOUND_COLS = 1024
+QV_PBVI_MAX_POINTS = 256
 QV_BATCH_GRAPH = 1
 
 # every function the header declares
@@ -43,6 +45,8 @@ EXPORTS = [
     "qv_blind_workspace_bytes", "qv_blind_iterate",
     "qv_search_workspace_bytes", "qv_search_layout_of", "qv_search_init", "qv_search_expand",
     "qv_search_result", "qv_search_update",
+    "qv_pbvi_workspace_bytes", "qv_pbvi_layout_of", "qv_pbvi_init", "qv_pbvi_expand",
+    "qv_pbvi_backup", "qv_pbvi_result",
     "qv_plan_workspace_bytes", "qv_plan_step", "qv_plan_layout",
     "qv_timing_enable", "qv_timing_read",
     "qv_filter_workspace_bytes", "qv_filter_nll_grad",
@@ -84,6 +88,14 @@ class qv_search_layout(C.Structure):
                     "sig", "staytab", "lm_wall", "belief", "valid", "z", "count", "pz",
                     "weight", "parent", "depth", "U", "L", "H", "E", "expanded", "child_base",
                     "rb", "UQ", "LQ", "HQ", "EQ", "ctl", "log", "err", "total_bytes")]
+
+
+class qv_pbvi_layout(C.Structure):
+    _fields_ = [("A", C.c_int32), ("S", C.c_int32), ("ZC", C.c_int32),
+                ("max_points", C.c_int32), ("ld", C.c_int32)] + [(f, C.c_size_t) for f in (
+                    "sig", "staytab", "lm_wall", "points", "pred", "cand", "idx", "vals",
+                    "dist", "dvalid", "dz", "dcount", "dpz", "src", "pick", "gamma0", "gamma1",
+                    "ctl", "err", "total_bytes")]
 
 
 class qv_kernel_time(C.Structure):
@@ -148,6 +160,20 @@ def lib():
         L.qv_search_update.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                        C.c_int32, vp, C.c_size_t, vp]
         L.qv_search_update.restype = C.c_int32
+        L.qv_pbvi_workspace_bytes.argtypes = [mp, C.c_int32, C.c_int32]
+        L.qv_pbvi_workspace_bytes.restype = C.c_size_t
+        L.qv_pbvi_layout_of.argtypes = [mp, C.c_int32, C.c_int32, C.POINTER(qv_pbvi_layout)]
+        L.qv_pbvi_layout_of.restype = C.c_int32
+        L.qv_pbvi_init.argtypes = [mp, vp, vp, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+        L.qv_pbvi_init.restype = C.c_int32
+        L.qv_pbvi_expand.argtypes = [mp, C.c_int32, C.c_int32, C.c_uint64, C.c_uint32,
+                                     C.POINTER(C.c_int32), vp, C.c_size_t, vp]
+        L.qv_pbvi_expand.restype = C.c_int32
+        L.qv_pbvi_backup.argtypes = [mp, C.c_int32, C.c_int32, C.c_int32, vp, C.c_size_t, vp]
+        L.qv_pbvi_backup.restype = C.c_int32
+        L.qv_pbvi_result.argtypes = [mp, C.c_int32, C.c_int32, vp, C.c_int32,
+                                     C.POINTER(C.c_int32), vp, C.c_size_t, vp]
+        L.qv_pbvi_result.restype = C.c_int32
         L.qv_fib_workspace_bytes.argtypes = [mp, C.c_int32]
         L.qv_fib_workspace_bytes.restype = C.c_size_t
         L.qv_fib_iterate.argtypes = [mp, C.c_float, C.c_int32, vp, C.POINTER(C.c_double),
@@ -308,6 +334,46 @@ def qv_search_update(model, Ut, Lt, l_cols, n, max_nodes, a, z, ws, stream=None)
     return int(lib().qv_search_update(C.byref(model.c), _ptr(Ut), _ptr(Lt), int(l_cols), int(n),
                                       int(max_nodes), int(a), int(z), _ptr(ws), _nbytes(ws),
                                       _stream(stream)))
+
+
+def qv_pbvi_workspace_bytes(model, max_points: int, init_cols: int) -> int:
+    return int(lib().qv_pbvi_workspace_bytes(C.byref(model.c), int(max_points), int(init_cols)))
+
+
+def qv_pbvi_layout_of(model, max_points: int, init_cols: int):
+    out = qv_pbvi_layout()
+    st = lib().qv_pbvi_layout_of(C.byref(model.c), int(max_points), int(init_cols),
+                                 C.byref(out))
+    return int(st), out
+
+
+def qv_pbvi_init(model, b0, init, init_cols, max_points, ws, stream=None) -> int:
+    return int(lib().qv_pbvi_init(C.byref(model.c), _ptr(b0), _ptr(init), int(init_cols),
+                                  int(max_points), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_pbvi_expand(model, init_cols, max_points, seed, query_id, ws, stream=None):
+    """-> (status, points added)."""
+    added = C.c_int32(0)
+    st = lib().qv_pbvi_expand(C.byref(model.c), int(init_cols), int(max_points),
+                              C.c_uint64(int(seed) & (2 ** 64 - 1)),
+                              C.c_uint32(int(query_id) & (2 ** 32 - 1)), C.byref(added),
+                              _ptr(ws), _nbytes(ws), _stream(stream))
+    return int(st), added.value
+
+
+def qv_pbvi_backup(model, init_cols, max_points, sweeps, ws, stream=None) -> int:
+    return int(lib().qv_pbvi_backup(C.byref(model.c), int(init_cols), int(max_points),
+                                    int(sweeps), _ptr(ws), _nbytes(ws), _stream(stream)))
+
+
+def qv_pbvi_result(model, init_cols, max_points, gamma_out, ld_out, ws, stream=None):
+    """-> (status, number of points)."""
+    npts = C.c_int32(0)
+    st = lib().qv_pbvi_result(C.byref(model.c), int(init_cols), int(max_points),
+                              _ptr(gamma_out), int(ld_out), C.byref(npts), _ptr(ws),
+                              _nbytes(ws), _stream(stream))
+    return int(st), npts.value
 
 
 def qv_fib_workspace_bytes(model, max_sweeps: int) -> int:

@@ -149,6 +149,39 @@ struct SearchArgs {
   int32_t *log;                 // [NV] node expanded by each expansion
 };
 
+// Point-based value iteration state in its workspace (device pointers).
+struct PbviArgs {
+  int np_max, ZC, ld;             // point capacity, |Z| = 16 (L + 1), table columns
+  uint32_t key0, key1, qid;       // Philox key and query id of the draws
+  const uint32_t *sig;
+  const float *staytab;
+  const uint32_t *lm_wall;
+  float *pts;                     // [np_max][S] belief points
+  float *pred;                    // [np_max][A][S] b' = T_a^T b
+  float *cand;                    // [np_max][A][S] posteriors, then alpha_a
+  int32_t *idx;                   // [np_max][A][ZC] chosen vector per observation
+  float *vals, *dist;             // [np_max][A] b.alpha_a, L1 distance to the set
+  int32_t *dvalid, *dz, *dcount;  // [np_max][A] draw records
+  float *dpz;
+  int32_t *src;                   // [np_max] source (point * A + action) of a new point
+  int32_t *pick;                  // [np_max] action whose alpha_a became the point's vector
+  float *G0, *G1;                 // [S][ld] vector tables
+  int32_t *ctl;                   // points, round, current table, columns, added
+};
+
+// Control words of the PBVI workspace.
+constexpr int kPbviCtlPoints = 0, kPbviCtlRound = 1, kPbviCtlCur = 2, kPbviCtlCols = 3,
+              kPbviCtlAdded = 4;
+
+// Per-call arguments of launch_pbvi.
+struct PbviLaunch {
+  const float *b0 = nullptr;
+  const float *Gc = nullptr;      // current table (init: the caller's [S][cols])
+  float *Gn = nullptr;            // next table
+  float *out = nullptr;
+  int np = 0, count = 0, round = 0, cols = 0, cur = 0, ldo = 0;
+};
+
 int tile_rows(int W, int H);
 DevModel make_dev_model(const qv_model *m);
 int32_t check_model(const qv_model *m);
@@ -178,6 +211,11 @@ hipError_t launch_prep(const DevModel &dm, uint32_t *sig, float *staytab, int32_
 hipError_t launch_prep_lm(const DevModel &dm, uint32_t *sig, float *staytab, int32_t *err,
                           uint32_t *lm_wall, hipStream_t st);
 // what: 0 init (b0), 1 one expansion (expand + update), 2 result, 3 update(a, z)
+hipError_t launch_pbvi(int what, const DevModel &m, const PbviArgs &pa, const PbviLaunch &pl,
+                       hipStream_t st);
+size_t pbvi_predict_lds_bytes(int W, int H);
+size_t pbvi_select_lds_bytes(int cols);
+size_t pbvi_backup_lds_bytes(int W, int H, int ZC);
 hipError_t launch_search(int what, const DevModel &m, const SearchArgs &sa, const float *b0,
                          int a, int z, int32_t *action, float *rootU, float *rootL,
                          hipStream_t st);

@@ -3274,3 +3274,512 @@ hipError_t launch_search(int what, const DevModel &m, const SearchArgs &sa, cons
 }
 
 }  // namespace qv
+
+namespace qv {
+
+// ===========================================================================
+// Point-based value iteration (Sec. IV-B).  The state lives in the workspace:
+// a set of belief points, each with its predictions b' = T_a^T b, and the
+// vector set Gamma as a table [S][ld] (one column per vector, the layout of a
+// bound table).  Two vector tables alternate between backups.
+//   expansion (the paper follows Pineau et al.): every point draws one
+//     observation per action (sample_draws with n = 1, counter (a, point,
+//     64 + round, query)), forms the posterior, and the posterior farthest in
+//     L1 from the current set joins it (first maximum over actions, not at
+//     distance 0), in point order while there is room;
+//   backup (the PBVI Bellman equation): per (point, action) and observation
+//     z, the vector j maximising sum_x O(z|x) b'(x) alpha_j(x) (first maximum);
+//     alpha_a(x) = R(x,a) + gamma sum_x' T(x,a,x') G(x') with
+//     G(y) = sum_z O(z|y) alpha_{a,z}(y) on free cells (0 on blocked ones);
+//     the point's new vector is the alpha_a of largest b.alpha_a.
+// The observations z = zw + 16 zl factor: O(z|x) = O_w(zw|w(x)) O_l(zl|x),
+// so the value of vector j at z with zl = 0 is sum_w O_w(zw|w) HW[w][j] with
+// HW[w][j] = sum over cells of true wall reading w of lambda(x) b'(x)
+// alpha_j(x) (lambda = 1 - rho on landmark cells, else 1); at zl = l >= 1 only
+// landmark l's cell counts.
+// ===========================================================================
+__global__ void k_pbvi_init(DevModel m, PbviArgs pa, const float *b0, const float *init,
+                            int init_cols) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)m.S * init_cols;
+  if (i < m.S) pa.pts[i] = (pa.sig[i] & kSigFree) ? b0[i] : 0.f;
+  if (i < n) {
+    const long long x = i / init_cols;
+    const int j = (int)(i - x * init_cols);
+    pa.G0[x * pa.ld + j] = init[i];
+  }
+  if (i == 0) {
+    pa.ctl[kPbviCtlPoints] = 1;
+    pa.ctl[kPbviCtlRound] = 0;
+    pa.ctl[kPbviCtlCur] = 0;
+    pa.ctl[kPbviCtlCols] = init_cols;
+    pa.ctl[kPbviCtlAdded] = 0;
+  }
+}
+
+// Points p0 .. p0 + gridDim.x / A - 1, one workgroup per (point, action).
+// !EXPAND: the prediction b' into pred.  EXPAND: b', the draw of one
+// observation and the posterior into cand (pred is not rewritten).
+template <bool EXPAND>
+__global__ __launch_bounds__(kBlock) void k_pbvi_predict(DevModel m, PbviArgs pa, int p0,
+                                                         int round) {
+  extern __shared__ float smem[];
+  __shared__ float s_stay[256];
+  __shared__ float s_H[17];
+  __shared__ DrawOut s_draw;
+  const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2, tid = threadIdx.x;
+  const int b = p0 + blockIdx.x / A, a = blockIdx.x % A;
+  float *band = smem;
+  float *bpl = band + (size_t)(H + 2) * BW;
+  float *hist = bpl + ((S + 3) & ~3);
+  const float *bb = pa.pts + (size_t)b * S;
+  s_stay[tid] = pa.staytab[a * 256 + tid];
+  load_band(m, pa.sig, bb, 0, H, band, BW, false);
+  if (EXPAND) {
+#pragma unroll
+    for (int w = 1; w < 16; ++w) hist[w * kBlock + tid] = 0.f;
+  }
+  __syncthreads();
+  const float rW = 1.0f / (float)W;
+  const float *sl = &m.slip[a * 9];
+  const float rho = m.lm_p;
+  const float bgoal = m.goal >= 0 ? bb[m.goal] : 0.f;
+  float *out = pa.pred + ((size_t)b * A + a) * S;
+  float h0 = 0.f;
+  for (int t = tid; t < S; t += kBlock) {
+    const uint32_t sg = pa.sig[t];
+    const int ly = fdiv(t, W, rW), lx = t - ly * W;
+    const float bt = t == m.goal ? bgoal : band[(ly + 1) * BW + lx + 1];
+    const float bp = predict_cell_v(band, BW, ly, lx, sg, sl, s_stay, bt);
+    if (!EXPAND) {
+      out[t] = bp;
+    } else {
+      bpl[t] = bp;
+      const uint32_t lm = sig_lm(sg);
+      const float contrib = (lm && lm <= (uint32_t)m.L) ? bp * (1.f - rho) : bp;
+      const uint32_t w = sig_wall(sg);
+      if (w == 0u)
+        h0 += contrib;
+      else
+        hist[w * kBlock + tid] += contrib;
+    }
+  }
+  if (!EXPAND) return;
+  hist[tid] = h0;
+  __syncthreads();
+  {
+    const int k = tid & 15, rot = (tid >> 4) & 3;
+    const float *hb = hist + (tid >> 4) * kBlock;
+    float sum = 0.f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) sum += hb[k + 16 * ((i + rot) & 15)];
+    sum = group_sum<16>(sum);
+    if ((tid & 15) == 15) s_H[tid >> 4] = sum;
+    if (tid == 0) s_H[16] = 0.f;
+  }
+  __syncthreads();
+  if (tid < kWave) {
+    LevelArgs lv{};
+    lv.d = 64 + round;
+    lv.n = 1;
+    lv.K = A;
+    lv.key0 = pa.key0;
+    lv.key1 = pa.key1;
+    lv.qid = pa.qid;
+    lv.cvalid = pa.dvalid;
+    lv.cz = pa.dz;
+    lv.ccount = pa.dcount;
+    lv.cpz = pa.dpz;
+    uint32_t *lw = (uint32_t *)hist;
+    float *lvv = hist + m.L;
+    for (int l = tid; l < m.L; l += kWave) {
+      lw[l] = pa.lm_wall[l];
+      const int c = m.lm_cell[l];
+      lvv[l] = (c >= 0 && c < S) ? bpl[c] : 0.f;
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    sample_draws(m, lv, b, a, tid < 17 ? s_H[tid] : 0.f, lw, lvv, hist + 2 * m.L, &s_draw,
+                 b * A);
+  }
+  __syncthreads();
+  if (s_draw.U < 1) return;
+  const int z = s_draw.z[0];
+  const float inv = s_draw.inv[0];
+  const uint32_t zw = (uint32_t)(z & 15), zl = (uint32_t)(z >> 4);
+  float *c = pa.cand + ((size_t)b * A + a) * S;
+  for (int t = tid; t < S; t += kBlock) {
+    const uint32_t sg = pa.sig[t];
+    c[t] = wall_lik(m.flip, zw, sig_wall(sg)) * lm_lik(rho, zl, sig_lm(sg)) * bpl[t] * inv;
+  }
+}
+
+// L1 distance of each drawn posterior to the nearest point of the set
+// (points 0 .. np-1); -1 where no observation was drawn.
+__global__ __launch_bounds__(kBlock) void k_pbvi_dist(DevModel m, PbviArgs pa, int np) {
+  __shared__ float s_red[kBlock / kWave];
+  const int A = m.A, S = m.S, tid = threadIdx.x;
+  const int b = blockIdx.x / A, a = blockIdx.x % A;
+  if (!pa.dvalid[b * A + a]) {
+    if (tid == 0) pa.dist[b * A + a] = -1.f;
+    return;
+  }
+  const float *c = pa.cand + ((size_t)b * A + a) * S;
+  float best = INFINITY;
+  for (int j = 0; j < np; ++j) {
+    const float *q = pa.pts + (size_t)j * S;
+    float d = 0.f;
+    for (int t = tid; t < S; t += kBlock) d += fabsf(c[t] - q[t]);
+    d = wave_sum(d);
+    if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = d;
+    __syncthreads();
+    best = fminf(best, (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]));
+    __syncthreads();
+  }
+  if (tid == 0) pa.dist[b * A + a] = best;
+}
+
+// Each point's farthest posterior (first maximum over actions, distance > 0)
+// joins the set, in point order, while there is room; one thread.
+__global__ void k_pbvi_add(DevModel m, PbviArgs pa, int np) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int added = 0;
+  for (int b = 0; b < np; ++b) {
+    int best = -1;
+    float bd = 0.f;
+    for (int a = 0; a < m.A; ++a) {
+      const float d = pa.dist[b * m.A + a];
+      if (d > bd) {
+        bd = d;
+        best = a;
+      }
+    }
+    if (best >= 0 && np + added < pa.np_max) pa.src[added++] = b * m.A + best;
+  }
+  pa.ctl[kPbviCtlAdded] = added;
+  pa.ctl[kPbviCtlPoints] = np + added;
+  pa.ctl[kPbviCtlRound] += 1;
+}
+
+__global__ void k_pbvi_copy(DevModel m, PbviArgs pa, int np) {
+  const int i = blockIdx.y;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pa.ctl[kPbviCtlAdded] || t >= m.S) return;
+  pa.pts[(size_t)(np + i) * m.S + t] = pa.cand[(size_t)pa.src[i] * m.S + t];
+}
+
+// First maximum of (value, column) over the workgroup: the largest value,
+// the lowest column among equal values; every thread gets the column.
+__device__ __forceinline__ int pbvi_block_argmax(float v, int j, float *rv, int *rj) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const float ov = __shfl_xor(v, o, kWave);
+    const int oj = __shfl_xor(j, o, kWave);
+    if (ov > v || (ov == v && oj < j)) {
+      v = ov;
+      j = oj;
+    }
+  }
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  if (lane == 0) {
+    rv[wave] = v;
+    rj[wave] = j;
+  }
+  __syncthreads();
+  float bv = rv[0];
+  int bj = rj[0];
+  for (int w = 1; w < kBlock / kWave; ++w)
+    if (rv[w] > bv || (rv[w] == bv && rj[w] < bj)) {
+      bv = rv[w];
+      bj = rj[w];
+    }
+  __syncthreads();
+  return bj;
+}
+
+// Slices of cells that the workgroup's threads split for `cols` columns.
+__host__ __device__ inline int pbvi_slices(int cols) {
+  int cp = 1;
+  while (cp < cols) cp <<= 1;
+  return cp >= kBlock ? 1 : kBlock / cp;
+}
+
+// Per (point, action): HW[w][j] (cells split into slices, each summed in
+// cell order, the slices then added in order), then the chosen vector of
+// every observation into idx.
+__global__ __launch_bounds__(kBlock) void k_pbvi_select(DevModel m, PbviArgs pa, const float *G,
+                                                        int gcols) {
+  extern __shared__ float smem[];   // [SL][16][gcols] slice sums
+  __shared__ float rv[kBlock / kWave];
+  __shared__ int rj[kBlock / kWave];
+  __shared__ float ctab[256];       // O_w(zw | w) at [zw * 16 + w]
+  const int A = m.A, S = m.S, tid = threadIdx.x, ld = pa.ld;
+  const int b = blockIdx.x / A, a = blockIdx.x % A;
+  const float *bp = pa.pred + ((size_t)b * A + a) * S;
+  const int SL = pbvi_slices(gcols);
+  const int CW = kBlock / SL;
+  ctab[tid] = wall_lik(m.flip, (uint32_t)(tid >> 4), (uint32_t)(tid & 15));
+  const float rho = m.lm_p;
+  const int slice = tid / CW, jl = tid - slice * CW;
+  const int c0 = (int)(((long long)S * slice) / SL), c1 = (int)(((long long)S * (slice + 1)) / SL);
+  for (int j0 = 0; j0 < gcols; j0 += CW) {
+    const int j = j0 + jl;
+    const int jc = j < gcols ? j : 0;
+    float h[16];
+#pragma unroll
+    for (int w = 0; w < 16; ++w) h[w] = 0.f;
+    constexpr int NB = 8;
+    for (int t0 = c0; t0 < c1; t0 += NB) {
+      float v[NB], g[NB];
+      uint32_t sg[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const bool in = t0 + k < c1;
+        const int t = in ? t0 + k : c0;
+        v[k] = in ? bp[t] : 0.f;
+        sg[k] = pa.sig[t];
+        g[k] = G[(size_t)t * ld + jc];
+      }
+#pragma unroll
+      for (int k = 0; k < NB; ++k) {
+        const uint32_t lm = sig_lm(sg[k]);
+        const float x = ((lm && lm <= (uint32_t)m.L) ? v[k] * (1.f - rho) : v[k]) * g[k];
+        const uint32_t w = sig_wall(sg[k]);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) h[q] += (w == (uint32_t)q) ? x : 0.f;
+      }
+    }
+    if (j < gcols) {
+#pragma unroll
+      for (int w = 0; w < 16; ++w) smem[((size_t)slice * 16 + w) * gcols + j] = h[w];
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < 16 * gcols; i += kBlock) {
+    float s = smem[i];
+    for (int q = 1; q < SL; ++q) s += smem[(size_t)q * 16 * gcols + i];
+    smem[i] = s;
+  }
+  __syncthreads();
+  int32_t *idx = pa.idx + ((size_t)b * A + a) * pa.ZC;
+  for (int zw = 0; zw < 16; ++zw) {
+    float best = -INFINITY;
+    int bj = 0x7fffffff;
+    for (int j = tid; j < gcols; j += kBlock) {
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < 16; ++w) v = fmaf(ctab[zw * 16 + w], smem[w * gcols + j], v);
+      if (v > best) {
+        best = v;
+        bj = j;
+      }
+    }
+    const int r = pbvi_block_argmax(best, bj, rv, rj);
+    if (tid == 0) idx[zw] = r;
+  }
+  // zl = l: the value of vector j is O_w(zw | w_l) rho b'(x_l) alpha_j(x_l):
+  // the largest alpha_j(x_l) when that factor is positive, else all are 0
+  // and the first vector is taken
+  for (int l = 0; l < m.L; ++l) {
+    const int cell = m.lm_cell[l];
+    const bool on = cell >= 0 && cell < S;
+    const float coef = on ? rho * bp[cell] : 0.f;
+    int r = 0;
+    if (coef > 0.f) {
+      float best = -INFINITY;
+      int bj = 0x7fffffff;
+      for (int j = tid; j < gcols; j += kBlock) {
+        const float v = G[(size_t)cell * ld + j];
+        if (v > best) {
+          best = v;
+          bj = j;
+        }
+      }
+      r = pbvi_block_argmax(best, bj, rv, rj);
+    }
+    if (tid < 16) {
+      const uint32_t wl = pa.lm_wall[l];
+      const bool pos = coef > 0.f && wl <= 15u && ctab[tid * 16 + wl] > 0.f;
+      idx[16 * (l + 1) + tid] = pos ? r : 0;
+    }
+  }
+}
+
+// Per (point, action): alpha_a into cand and b.alpha_a into vals.
+__global__ __launch_bounds__(kBlock) void k_pbvi_backup(DevModel m, PbviArgs pa, const float *G) {
+  extern __shared__ float smem[];   // G(y) on a band with a zero halo, then idx
+  __shared__ float s_stay[256];
+  __shared__ float ctab[256];
+  __shared__ float s_red[kBlock / kWave];
+  const int A = m.A, W = m.W, H = m.H, S = m.S, BW = W + 2, tid = threadIdx.x, ld = pa.ld;
+  const int b = blockIdx.x / A, a = blockIdx.x % A;
+  float *band = smem;
+  int *sidx = (int *)(smem + (size_t)(H + 2) * BW);
+  const int32_t *idx = pa.idx + ((size_t)b * A + a) * pa.ZC;
+  for (int i = tid; i < pa.ZC; i += kBlock) sidx[i] = idx[i];
+  s_stay[tid] = pa.staytab[a * 256 + tid];
+  ctab[tid] = wall_lik(m.flip, (uint32_t)(tid >> 4), (uint32_t)(tid & 15));
+  for (int i = tid; i < (H + 2) * BW; i += kBlock) band[i] = 0.f;
+  __syncthreads();
+  const float rho = m.lm_p;
+  const float rW = 1.0f / (float)W;
+  for (int y = tid; y < S; y += kBlock) {
+    const uint32_t sg = pa.sig[y];
+    if (!(sg & kSigFree)) continue;
+    const uint32_t w = sig_wall(sg), lm = sig_lm(sg);
+    const bool isl = lm && lm <= (uint32_t)m.L;
+    const float lam0 = isl ? 1.f - rho : 1.f;
+    const float *gy = G + (size_t)y * ld;
+    float gsum = 0.f;
+    for (int zw = 0; zw < 16; ++zw) {
+      const float c = ctab[zw * 16 + w];
+      gsum = fmaf(c * lam0, gy[sidx[zw]], gsum);
+      if (isl) gsum = fmaf(c * rho, gy[sidx[16 * lm + zw]], gsum);
+    }
+    const int ly = fdiv(y, W, rW), lx = y - ly * W;
+    band[(ly + 1) * BW + lx + 1] = gsum;
+  }
+  __syncthreads();
+  const float *bb = pa.pts + (size_t)b * S;
+  float *out = pa.cand + ((size_t)b * A + a) * S;
+  const float *sl = &m.slip[a * 9];
+  float dot = 0.f;
+  for (int x = tid; x < S; x += kBlock) {
+    const uint32_t sg = pa.sig[x];
+    float v = 0.f;
+    if (sg & kSigFree) {
+      const int ly = fdiv(x, W, rW), lx = x - ly * W;
+      const float *c = band + (ly + 1) * BW + lx + 1;
+      const float r = m.R[(size_t)x * A + a];
+      float e;
+      if (sg & kSigGoal) {
+        e = c[0];   // the goal is absorbing
+      } else {
+        // the successor in direction j is x + d_j with probability slip[a][j];
+        // moves into blocked or off-grid cells stay (s_stay holds slip[a][4]
+        // plus their mass)
+        e = sl[0] * c[-BW - 1];
+        e = fmaf(sl[1], c[-BW], e);
+        e = fmaf(sl[2], c[-BW + 1], e);
+        e = fmaf(sl[3], c[-1], e);
+        e = fmaf(sl[5], c[1], e);
+        e = fmaf(sl[6], c[BW - 1], e);
+        e = fmaf(sl[7], c[BW], e);
+        e = fmaf(sl[8], c[BW + 1], e);
+        e = fmaf(s_stay[sig_out8(sg)], c[0], e);
+      }
+      v = fmaf(m.gamma, e, r);
+    }
+    out[x] = v;
+    dot = fmaf(bb[x], v, dot);
+  }
+  dot = wave_sum(dot);
+  if ((tid & (kWave - 1)) == 0) s_red[tid / kWave] = dot;
+  __syncthreads();
+  if (tid == 0) pa.vals[b * A + a] = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
+}
+
+// The point's new vector: the alpha_a of largest b.alpha_a (first maximum),
+// into column b of Gout.
+__global__ __launch_bounds__(kBlock) void k_pbvi_pick(DevModel m, PbviArgs pa, float *Gout) {
+  __shared__ int s_a;
+  const int b = blockIdx.x, A = m.A;
+  if (threadIdx.x == 0) {
+    int best = 0;
+    for (int a = 1; a < A; ++a)
+      if (pa.vals[b * A + a] > pa.vals[b * A + best]) best = a;
+    s_a = best;
+    pa.pick[b] = best;
+  }
+  __syncthreads();
+  const float *c = pa.cand + ((size_t)b * A + s_a) * m.S;
+  for (int x = threadIdx.x; x < m.S; x += kBlock) Gout[(size_t)x * pa.ld + b] = c[x];
+}
+
+__global__ void k_pbvi_setctl(int32_t *ctl, int cur, int cols) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl[kPbviCtlCur] = cur;
+    ctl[kPbviCtlCols] = cols;
+  }
+}
+
+// out[x][j] = G[x][j] for j < cols, else G[x][0]: a repeated column leaves
+// the maximum over columns unchanged.
+__global__ void k_pbvi_out(DevModel m, PbviArgs pa, const float *G, int cols, float *out,
+                           int ldo) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)m.S * ldo) return;
+  const long long x = i / ldo;
+  const int j = (int)(i - x * ldo);
+  out[i] = G[x * pa.ld + (j < cols ? j : 0)];
+}
+
+size_t pbvi_predict_lds_bytes(int W, int H) { return search_lds_floats(W, H) * sizeof(float); }
+size_t pbvi_select_lds_bytes(int cols) {
+  return (size_t)pbvi_slices(cols) * 16 * (size_t)cols * sizeof(float);
+}
+size_t pbvi_backup_lds_bytes(int W, int H, int ZC) {
+  return ((size_t)(H + 2) * (W + 2) + (size_t)ZC) * sizeof(float);
+}
+
+// what: 0 init (b0, init, init_cols), 1 expand (np, round; the host reads
+// back the count), 2 predict the points added (np = first new point,
+// count), 3 one backup sweep (Gc -> Gn, cols), 4 set ctl (cur, cols),
+// 5 result (Gc, cols, out, ldo).
+hipError_t launch_pbvi(int what, const DevModel &m, const PbviArgs &pa, const PbviLaunch &pl,
+                       hipStream_t st) {
+  static bool attr = false;
+  if (!attr) {
+    const void *ks[4] = {(const void *)k_pbvi_predict<true>, (const void *)k_pbvi_predict<false>,
+                         (const void *)k_pbvi_select, (const void *)k_pbvi_backup};
+    for (const void *f : ks) {
+      hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         (int)(152 * 1024));
+      if (e != hipSuccess) return e;
+    }
+    attr = true;
+  }
+  const int A = m.A, S = m.S;
+  const size_t lds_pred = pbvi_predict_lds_bytes(m.W, m.H);
+  switch (what) {
+    case 0: {
+      const long long n = std::max((long long)S, (long long)S * pl.cols);
+      QV_LAUNCH(k_pbvi_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, pa, pl.b0,
+                pl.Gc, pl.cols);
+      QV_LAUNCH(k_pbvi_predict<false>, dim3(A), dim3(kBlock), lds_pred, st, m, pa, 0, 0);
+      break;
+    }
+    case 1:
+      QV_LAUNCH(k_pbvi_predict<true>, dim3(pl.np * A), dim3(kBlock), lds_pred, st, m, pa, 0,
+                pl.round);
+      QV_LAUNCH(k_pbvi_dist, dim3(pl.np * A), dim3(kBlock), 0, st, m, pa, pl.np);
+      QV_LAUNCH(k_pbvi_add, dim3(1), dim3(kWave), 0, st, m, pa, pl.np);
+      QV_LAUNCH(k_pbvi_copy, dim3((S + 255) / 256, pl.np), dim3(256), 0, st, m, pa, pl.np);
+      break;
+    case 2:
+      QV_LAUNCH(k_pbvi_predict<false>, dim3(pl.count * A), dim3(kBlock), lds_pred, st, m, pa,
+                pl.np, 0);
+      break;
+    case 3:
+      QV_LAUNCH(k_pbvi_select, dim3(pl.np * A), dim3(kBlock), pbvi_select_lds_bytes(pl.cols), st,
+                m, pa, pl.Gc, pl.cols);
+      QV_LAUNCH(k_pbvi_backup, dim3(pl.np * A), dim3(kBlock),
+                pbvi_backup_lds_bytes(m.W, m.H, pa.ZC), st, m, pa, pl.Gc);
+      QV_LAUNCH(k_pbvi_pick, dim3(pl.np), dim3(kBlock), 0, st, m, pa, pl.Gn);
+      break;
+    case 4:
+      QV_LAUNCH(k_pbvi_setctl, dim3(1), dim3(kWave), 0, st, pa.ctl, pl.cur, pl.cols);
+      break;
+    case 5: {
+      const long long n = (long long)S * pl.ldo;
+      QV_LAUNCH(k_pbvi_out, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, m, pa, pl.Gc,
+                pl.cols, pl.out, pl.ldo);
+      break;
+    }
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace qv

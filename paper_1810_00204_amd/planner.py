@@ -261,3 +261,81 @@ class SearchPlanner:
         if beliefs:
             out["belief"] = arr(L.belief, NV * S, np.float32).reshape(NV, S)
         return out
+
+
+class PbviPlanner:
+    """Point-based value iteration over one problem (qv_pbvi_*): the
+    workspace holding the point set and the vector tables, and readers of
+    the state for tests and callers.  `init` is the starting vector table
+    [S, init_cols] (e.g. the blind-policy vectors)."""
+
+    def __init__(self, prob, init, max_points: int, device="cuda"):
+        import torch
+        self.torch = torch
+        self.prob = prob
+        self.device = device
+        self.max_points = int(max_points)
+        self.m = B.DeviceModel(prob, device)
+        self.init_t = init if hasattr(init, "data_ptr") else torch.as_tensor(
+            np.ascontiguousarray(init, np.float32).reshape(-1)).to(device)
+        self.init_cols = int(self.init_t.numel()) // prob.S
+        nb = B.qv_pbvi_workspace_bytes(self.m, self.max_points, self.init_cols)
+        if nb == 0:
+            raise B.QvError(B.QV_ERR_UNSUPPORTED, "qv_pbvi_workspace_bytes")
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        st, self.layout = B.qv_pbvi_layout_of(self.m, self.max_points, self.init_cols)
+        B.check(st, "qv_pbvi_layout_of")
+
+    def init(self, b0=None, stream=None):
+        b0 = self.prob.b0 if b0 is None else b0
+        bt = b0 if hasattr(b0, "data_ptr") else self.torch.as_tensor(
+            np.ascontiguousarray(b0, np.float32)).to(self.device)
+        self._b0 = bt
+        B.check(B.qv_pbvi_init(self.m, bt, self.init_t, self.init_cols, self.max_points, self.ws,
+                               stream), "qv_pbvi_init")
+
+    def expand(self, seed=None, query_id=0, stream=None) -> int:
+        st, added = B.qv_pbvi_expand(self.m, self.init_cols, self.max_points,
+                                     self.prob.seed if seed is None else seed, query_id, self.ws,
+                                     stream)
+        B.check(st, "qv_pbvi_expand")
+        return added
+
+    def backup(self, sweeps: int = 1, stream=None):
+        B.check(B.qv_pbvi_backup(self.m, self.init_cols, self.max_points, int(sweeps), self.ws,
+                                 stream), "qv_pbvi_backup")
+
+    def table(self, ld=None, stream=None):
+        """The vectors as a bound table [S * ld] (device; ld defaults to the
+        point capacity) and the number of points."""
+        ld = self.max_points if ld is None else int(ld)
+        out = self.torch.empty(self.prob.S * ld, dtype=self.torch.float32, device=self.device)
+        st, npts = B.qv_pbvi_result(self.m, self.init_cols, self.max_points, out, ld, self.ws,
+                                    stream)
+        B.check(st, "qv_pbvi_result")
+        return out, npts
+
+    def state(self) -> dict:
+        """Copies the point set, the current vectors and the last expansion's
+        and backup's records out of the workspace (after a sync)."""
+        self.torch.cuda.synchronize()
+        L, raw = self.layout, self.ws
+        P, A, S, ZC, ld = self.max_points, self.prob.A, self.prob.S, L.ZC, L.ld
+
+        def arr(off, count, dt):
+            nbytes = count * np.dtype(dt).itemsize
+            return raw[off:off + nbytes].cpu().numpy().view(dt).copy()
+        ctl = arr(L.ctl, 5, np.int32)
+        npts, rnd, cur, cols, added = (int(v) for v in ctl)
+        G = arr(L.gamma1 if cur else L.gamma0, S * ld, np.float32).reshape(S, ld)[:, :cols]
+        out = {"points": arr(L.points, P * S, np.float32).reshape(P, S)[:npts],
+               "gamma": G, "round": rnd, "added": added, "cols": cols,
+               "idx": arr(L.idx, P * A * ZC, np.int32).reshape(P, A, ZC)[:npts],
+               "vals": arr(L.vals, P * A, np.float32).reshape(P, A)[:npts],
+               "pick": arr(L.pick, P, np.int32)[:npts],
+               "alpha": arr(L.cand, P * A * S, np.float32).reshape(P, A, S)[:npts],
+               "dist": arr(L.dist, P * A, np.float32).reshape(P, A),
+               "draw_valid": arr(L.dvalid, P * A, np.int32).reshape(P, A),
+               "draw_z": arr(L.dz, P * A, np.int32).reshape(P, A),
+               "src": arr(L.src, P, np.int32)}
+        return out

@@ -141,3 +141,33 @@ def test_fib_and_check_arguments_are_checked_on_the_host():
     # the check flag is accepted by the plan call's flag test (bad depth still wins)
     assert lib.qv_plan_step(C.byref(m.c), 0x10, 0x20, 7, 2, 1, 0, B.QV_PLAN_CHECK, 0x30, 0x40, 0x100, 1 << 20, None) == B.QV_ERR_INVALID_ARG
     assert lib.qv_plan_step(C.byref(m.c), 0x10, 0x20, 2, 2, 1, 0, 16, 0x30, 0x40, 0x100, 1 << 20, None) == B.QV_ERR_INVALID_ARG
+
+
+def test_pbvi_layout_and_arguments_are_checked_on_the_host():
+    prob = wl.make_small(seed=1)
+    m = FakeModel(prob)
+    P, k = 16, prob.A
+    need = B.qv_pbvi_workspace_bytes(m, P, k)
+    st, L = B.qv_pbvi_layout_of(m, P, k)
+    assert st == 0 and need == L.total_bytes > 0
+    assert L.ZC == 16 * (len(prob.lm_cell) + 1) and L.ld == max(P, k) and L.max_points == P
+    # regions in order, 256-byte aligned, inside the workspace
+    offs = [getattr(L, f) for f, _ in B.qv_pbvi_layout._fields_[5:-1]]
+    assert offs == sorted(offs) and all(o % 256 == 0 for o in offs) and offs[-1] < need
+    assert L.gamma1 - L.gamma0 >= prob.S * L.ld * 4
+    assert L.pred - L.points >= P * prob.S * 4
+    # capacity and column limits
+    assert B.qv_pbvi_workspace_bytes(m, 0, k) == 0
+    assert B.qv_pbvi_workspace_bytes(m, B.QV_PBVI_MAX_POINTS + 1, k) == 0
+    assert B.qv_pbvi_workspace_bytes(m, P, 0) == 0
+    assert B.qv_pbvi_workspace_bytes(FakeModel(prob, W=400, H=400), P, k) == 0
+    lib = B.lib()
+    assert lib.qv_pbvi_init(C.byref(m.c), None, 0x10, k, P, 0x100, need, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_pbvi_init(C.byref(m.c), 0x10, 0x20, k, P, 0x100, need - 1, None) == B.QV_ERR_WORKSPACE
+    assert lib.qv_pbvi_init(C.byref(m.c), 0x10, 0x20, k, 0, 0x100, need, None) == B.QV_ERR_INVALID_ARG
+    added = C.c_int32()
+    assert lib.qv_pbvi_expand(C.byref(m.c), k, P, 1, 0, None, 0x100, need, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_pbvi_backup(C.byref(m.c), k, P, -1, 0x100, need, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_pbvi_backup(C.byref(m.c), k, P, 0, 0x100, need, None) == 0   # nothing to do
+    assert lib.qv_pbvi_result(C.byref(m.c), k, P, 0x10, 0, C.byref(added), 0x100, need, None) == B.QV_ERR_INVALID_ARG
+    assert lib.qv_pbvi_result(C.byref(m.c), k, P, None, P, C.byref(added), 0x100, need, None) == B.QV_ERR_INVALID_ARG

@@ -100,6 +100,9 @@ def test_values_lie_between_blind_and_fib(seed):
     for b in tests:
         b = b / b.sum()
         assert t.value(b) <= float(np.max(b @ U)) + 1e-9
+    # at corner beliefs: alpha_j(x) <= V*(e_x) <= max_a U(x, a) for every vector
+    free = np.asarray(prob.occ).reshape(-1) == 0
+    assert np.all(t.Gamma[free] <= U[free].max(1)[:, None] + 1e-9)
 
 
 def test_expansion_adds_posteriors_of_points():
