@@ -38,6 +38,11 @@ struct PlanLayout {
                           // present ones first (counts follow the node counters)
 };
 
+// Item queues of the per-parent last level: kQueueXcds int32 counters after
+// the visiting-list counts, cleared with them.
+constexpr int kQueueXcds = 8;
+constexpr size_t kQueueInts = kQueueXcds;
+
 // Per-level kernel arguments (passed by value).
 struct LevelArgs {
   int d, nslots, tiles, TH, n, K;
@@ -65,6 +70,10 @@ struct LevelArgs {
   int32_t *slot_list, *slot_n;
   int slot_cap;           // entries of slot_list
   const int32_t *porder;  // this level's parent slots in visiting order (null: slot order)
+  // kQueueXcds item counters (zero at launch) of the per-parent last level,
+  // whose resident workgroups take (parent, band) items from per-XCD queues
+  // (take_band_item)
+  int32_t *wq = nullptr;
 };
 
 // Whole-tree view for the expectimax backup (Alg. 6/7).

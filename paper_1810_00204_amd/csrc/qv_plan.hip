@@ -22,6 +22,7 @@
 // reproducible.
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 
 #include "qv_internal.h"
 
@@ -852,6 +853,43 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_local_id(int i, int n) {
   const int q = n / kXcds, r = n - q * kXcds, x = i % kXcds;
   return x * q + min(x, r) + i / kXcds;
+}
+
+// Dynamic (parent, band) items of the per-parent last level, whose
+// workgroups stay resident and take items until every queue is empty.  The
+// hardware deals workgroups to the XCDs in turn, and one XCD can run the
+// level's items markedly slower than the others (measured: up to twice the
+// time of the rest for an equal share), so only workgroups that loop over a
+// shared supply keep the XCDs finishing together (the grid is at most what
+// the CUs hold at once).  Queue x holds the bands of a contiguous eighth of
+// the map, [x T / 8, (x + 1) T / 8), of every parent j (j-major, parents in
+// visiting order); a workgroup takes from the queue of the XCD it runs on,
+// whose L2 then holds those bands' rows of Q and R and the halo rows
+// neighbouring bands share, and only when that queue is empty from the next
+// ones.  Each counter value is handed out once, so every item is taken
+// exactly once; a workgroup leaves after finding all queues empty.  Returns
+// j * tiles + band, or -1.  Thread 0 takes; s_item is LDS; ends with a
+// barrier.
+__device__ __forceinline__ int take_band_item(int32_t *wq, int nslots, int tiles, int *s_item) {
+  static_assert(kQueueXcds == kXcds, "one queue per XCD");
+  if (threadIdx.x == 0) {
+    // this wavefront's XCD (the XCC_ID hardware register, bits 0..3)
+    const int x0 = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1));
+    int item = -1;
+    for (int t = 0; t < kXcds && item < 0; ++t) {
+      const int x = (x0 + t) & (kXcds - 1);
+      const int lo = x * tiles / kXcds, nb = (x + 1) * tiles / kXcds - lo;
+      if (nb == 0) continue;
+      const int k = atomicAdd(&wq[x], 1);
+      if (k < nslots * nb) {
+        const int j = k / nb;
+        item = j * tiles + lo + (k - j * nb);
+      }
+    }
+    *s_item = item;
+  }
+  __syncthreads();
+  return *s_item;
 }
 
 // Work item idx = (p * tiles + tile) * A + a of a level.
@@ -2295,19 +2333,18 @@ __global__ __launch_bounds__(kLeafBlock, 4) void k_leaf_parent(DevModel m, Level
                                                                  TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ LeafParentShared sh;
-  // With a visiting order, the present parents come first: they are
-  // dispatched first, dealt to the XCDs in turn and spread over the CUs,
-  // while the workgroups of absent parents (which only mark their children
-  // absent) come last.  Without one, workgroup i runs on XCD i mod 8; slot
-  // p = node*K + a*n + r, and the low r (the first distinct draw of each
-  // Q-node, nearly always present) would all land on the same XCDs when K
-  // is a multiple of 8, so each group of 8 is rotated by its index.
-  int i = blockIdx.x;
-  const int grp8 = i >> 3;
-  if (!lv.porder && (grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
-  const int j = i / lv.tiles, band = i - j * lv.tiles;
-  const int p = lv.porder ? lv.porder[j] : j;
-  leaf_parent_item<AM, QV, kLeafBlock>(m, lv, tr, p, band, smem, sh);
+  __shared__ int s_item;
+  // Items come from the per-XCD band queues, parents in visiting order: with
+  // one (levels below the root) the present parents come first, and the
+  // items of absent parents (which only mark their children absent) last.
+  for (;;) {
+    const int i = take_band_item(lv.wq, lv.nslots, lv.tiles, &s_item);
+    if (i < 0) break;
+    const int j = i / lv.tiles, band = i - j * lv.tiles;
+    const int p = lv.porder ? lv.porder[j] : j;
+    leaf_parent_item<AM, QV, kLeafBlock>(m, lv, tr, p, band, smem, sh);
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2416,6 +2453,45 @@ __global__ __launch_bounds__(1024) void k_backup(TreeArgs g) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// Grid of a resident launch: the workgroups the CUs hold at once (occupancy
+// of kernel k at this block size and dynamic LDS), at most one per item.
+// Cached per (kernel, block, LDS bytes, device).
+static unsigned resident_grid(const void *k, int block, size_t lds, long long items) {
+  struct Entry {
+    const void *k;
+    int block;
+    size_t lds;
+    int dev;
+    long long cap;
+  };
+  static Entry cache[16];
+  static int ncache = 0;
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+  long long cap = 0;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    for (int i = 0; i < ncache; ++i)
+      if (cache[i].k == k && cache[i].block == block && cache[i].lds == lds && cache[i].dev == dev)
+        cap = cache[i].cap;
+  }
+  if (cap == 0) {
+    int cus = 0, per = 0;
+    if (dev >= 0 &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, block, lds) == hipSuccess &&
+        cus > 0 && per > 0) {
+      cap = (long long)cus * per;
+      std::lock_guard<std::mutex> g(mu);
+      if (ncache < 16) cache[ncache++] = {k, block, lds, dev, cap};
+    } else {
+      cap = items;   // no occupancy figure: one workgroup per item still drains the queues
+    }
+  }
+  return (unsigned)std::max<long long>(1, std::min(items, cap));
+}
+
 static size_t band_bytes(int W, int TH) { return (size_t)(TH + 2) * (W + 2) * sizeof(float); }
 size_t band_lds_bytes(int W, int TH) { return band_bytes(W, TH); }
 // k_leaf: the band, then the block_sum32 scratch or the backup scratch
@@ -2478,7 +2554,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
 
   uint32_t *lm_wall = (uint32_t *)(ws + L.lm_wall);
   const PrepExtra px = {valid, zrec, cnt, pz, ctr,
-                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2 * (QV_MAX_DEPTH + 1)),
+                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2 * (QV_MAX_DEPTH + 1) +
+                                    kQueueInts),
                         lm_wall};
   prep_plan_launch(m, sig, staytab, err, px, st);
 
@@ -2582,7 +2659,11 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
       lv.part = (float *)(ws + L.leafrec);
-      const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
+      // item queues after the visiting-list counts (cleared by the prep pass)
+      lv.wq = slot_n + 2 * (QV_MAX_DEPTH + 1);
+      const void *kfn = AM == 4 ? (q_vec ? (const void *)k_leaf_parent<4, 1> : (const void *)k_leaf_parent<4, 0>)
+                                : (q_vec ? (const void *)k_leaf_parent<8, 1> : (const void *)k_leaf_parent<8, 0>);
+      const unsigned nb = resident_grid(kfn, kLeafBlock, lds_lp, (long long)lv.nslots * L.leaf_tiles);
       if (AM == 4 && q_vec)
         QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else if (AM == 4)
