@@ -133,7 +133,7 @@ bool plan_layout_impl(const qv_model *m, int D, int n, int flags, PlanLayout *L,
   L->leafpart = take((size_t)T.level_slots[D] * T.tiles * A * 4);
   L->stats_ctr_len = (size_t)ps * A;
   L->node_ctr_len = (size_t)tot;
-  L->counters = take((L->stats_ctr_len + L->node_ctr_len + 2 * (QV_MAX_DEPTH + 1) + kQueueInts) * 4);
+  L->counters = take((L->stats_ctr_len + L->node_ctr_len + 2 * (QV_MAX_DEPTH + 1)) * 4);
   long long list_len = 1;
   for (int d = 1; d < D; ++d) list_len += T.level_slots[d];
   L->slot_list = take((size_t)list_len * 4);

@@ -38,11 +38,6 @@ struct PlanLayout {
                           // present ones first (counts follow the node counters)
 };
 
-// Item queues of the per-parent last level: kQueueXcds int32 counters after
-// the visiting-list counts, cleared with them.
-constexpr int kQueueXcds = 8;
-constexpr size_t kQueueInts = kQueueXcds;
-
 // Per-level kernel arguments (passed by value).
 struct LevelArgs {
   int d, nslots, tiles, TH, n, K;
@@ -61,6 +56,9 @@ struct LevelArgs {
   const uint32_t *lm_wall;  // [L] true wall reading of each landmark cell
   int32_t *ctr;           // [nslots*A] bands finished per Q-node
   int q_vec;              // Q rows can be read as float4 (A = 4 or 8, aligned)
+  int leaf_finish;        // per-parent last level with several bands: 1 = the band items
+                          // only write their records and k_leaf_finish completes each
+                          // parent; 0 = the last band of a parent to finish completes it
   // free cells in true-wall-reading order and their chunks (see k_prep_sort)
   const int32_t *sort_cells, *sort_chunk;
   int sort_bands, sort_tc;   // bands sorted by extra workgroups of this launch (0: none)
@@ -70,10 +68,6 @@ struct LevelArgs {
   int32_t *slot_list, *slot_n;
   int slot_cap;           // entries of slot_list
   const int32_t *porder;  // this level's parent slots in visiting order (null: slot order)
-  // kQueueXcds item counters (zero at launch) of the per-parent last level,
-  // whose resident workgroups take (parent, band) items from per-XCD queues
-  // (take_band_item)
-  int32_t *wq = nullptr;
 };
 
 // Whole-tree view for the expectimax backup (Alg. 6/7).

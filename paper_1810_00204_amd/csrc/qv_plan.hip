@@ -22,7 +22,6 @@
 // reproducible.
 #include <algorithm>
 #include <cstdlib>
-#include <mutex>
 
 #include "qv_internal.h"
 
@@ -601,36 +600,23 @@ __device__ __forceinline__ void obs_block(int blk, int L, const float *otab, flo
   }
 }
 
-// Running totals of one page of 64 blocks: lane j holds block 64 g + j and
-// gets F[i], the total of P(z|b,a) over every z up to and including its
-// entry i.  Totals grow in z order: within a lane entry by entry, across lanes
-// in lane order, across pages from `base`, which the call advances to the
-// page's end.  lastpos: the lane's last z of positive mass so far.
-__device__ __forceinline__ void obs_page(int g, int L, const float *otab, float lmp,
-                                         const float *p0, const uint32_t *lw, const float *lvv,
-                                         float &base, float (&F)[16], int &lastpos) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int blk = g * kWave + lane;
-  float v[16];
-  obs_block(blk, L, otab, lmp, p0, lw, lvv, v);
-  float run = 0.f;
+// The inverse-CDF search runs on integer masses: each P(z|b,a) times a
+// power of two 2^e, rounded to an integer, with e chosen from the total so
+// that the integer total lies in [2^30, 2^31) (each mass keeps a resolution
+// of about 2^-30 of the total).  Integer running totals are exact and their
+// order of addition does not matter, so the lanes' totals are prefixed on the
+// DPP network, and a z is drawn only where its integer mass is positive.
+constexpr int kObsPages = (QV_MAX_LANDMARKS + 1 + kWave - 1) / kWave;   // pages of 64 blocks
+
+// Integer masses of the 16 entries of one block and their total.
+__device__ __forceinline__ uint32_t block_masses(const float (&v)[16], int e, uint32_t (&q)[16]) {
+  uint32_t t = 0;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
-    run += v[i];
-    F[i] = run;
-    if (v[i] > 0.f) lastpos = blk * 16 + i;
+    q[i] = (uint32_t)rintf(ldexpf(v[i], e));
+    t += q[i];
   }
-  // exclusive prefix of the lane totals in lane order, from base
-  const int nl = min(kWave, L + 1 - g * kWave);
-  float P = base, exc = base;
-  for (int i = 0; i < nl; ++i) {
-    const float s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(run), i));
-    if (i == lane) exc = P;
-    P += s;
-  }
-#pragma unroll
-  for (int i = 0; i < 16; ++i) F[i] = exc + F[i];
-  base = P;
+  return t;
 }
 
 // Observation draws of Q-node (slot p, action a) of level lv.d from its
@@ -638,10 +624,11 @@ __device__ __forceinline__ void obs_page(int g, int L, const float *otab, float 
 // reading w (landmark cells weighted by their "no landmark" factor); lw/lvv
 // (LDS) hold each landmark's wall reading and predicted mass.  Forms P(z|b,a)
 // over all z in ascending order, draws n observations by inverse CDF with
-// Philox uniforms (the first z whose running total exceeds u P), and writes
-// one child record per distinct z (ascending) with its frequency (Alg. 3/4).
-// One full wavefront; out (LDS) optional; p0tab: 32 floats of LDS (P(zw, no
-// landmark), then the wall-likelihood table).
+// Philox uniforms (the first z whose running total exceeds u times the total,
+// on the integer masses above), and writes one child record per distinct z
+// (ascending) with its frequency (Alg. 3/4).  One full wavefront; out (LDS)
+// optional; p0tab: 32 floats of LDS (P(zw, no landmark), then the
+// wall-likelihood table).
 // cbase >= 0 places the child records at cbase + a*n instead of the
 // capacity slots p*K + a*n (p still keys the draws).
 __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a, float hs,
@@ -674,57 +661,89 @@ __device__ int sample_draws(const DevModel &m, const LevelArgs &lv, int p, int a
   wait_lds();
   __builtin_amdgcn_wave_barrier();
   const int npg = (L + 1 + kWave - 1) / kWave;
-  // the total P(z|b,a); a single page keeps its running totals for the search
-  float F[16];
-  float base = 0.f;
-  int lastpos = -1;
-  for (int g = 0; g < npg; ++g) obs_page(g, L, otab, lmp, p0tab, lw, lvv, base, F, lastpos);
-  const float P = base;
+  // the total mass, for the scale only: the no-landmark entries sum to that
+  // of H (O_w sums to 1 over readings), landmark l's block to rho b'(x_l)
+  float pa = lane < 16 ? p0 : 0.f;
+  for (int l = lane; l < L; l += kWave) pa += lw[l] > 15u ? 0.f : lmp * lvv[l];
+  pa = wave_sum(pa);
+  int ex = 0;
+  (void)frexpf(pa, &ex);   // pa = f 2^ex with f in [0.5, 1)
+  const int e = 31 - ex;   // pa 2^e in [2^30, 2^31)
+  // integer running totals: incl[g] = total up to the end of the lane's
+  // block of page g; pbase[g] = total before page g (uniform)
+  uint32_t incl[kObsPages], pbase[kObsPages];
+  uint32_t base = 0;
+#pragma unroll
+  for (int g = 0; g < kObsPages; ++g) {
+    incl[g] = base;
+    pbase[g] = base;
+    if (g < npg) {
+      float v[16];
+      uint32_t q[16];
+      obs_block(g * kWave + lane, L, otab, lmp, p0tab, lw, lvv, v);
+      const uint32_t t = block_masses(v, e, q);
+      const uint32_t c = wave_scan_incl_u32(t);
+      incl[g] = base + c;
+      base += (uint32_t)__builtin_amdgcn_readlane((int)c, kWave - 1);
+    }
+  }
+  const uint32_t total = base;   // < 2^32: at most 2^31 plus rounding
   // lane k < n: its uniform from the Philox counter (a*ceil(n/4) + k/4, slot,
-  // level, query), word k%4, and its target u P
-  float tgt = 0.f;
+  // level, query), word k%4, and its integer target floor(u total), u the
+  // word's top 24 bits over 2^24 (so target < total)
+  uint32_t tgt = 0u;
   if (lane < n) {
     const int ng = (n + 3) / 4;
     const uint4 r = philox4x32_10(
         make_uint4((uint32_t)(a * ng + (lane >> 2)), (uint32_t)p, (uint32_t)lv.d, lv.qid),
         lv.key0, lv.key1);
     const int q = lane & 3;
-    tgt = u24(q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w) * P;
+    const uint32_t w = q == 0 ? r.x : q == 1 ? r.y : q == 2 ? r.z : r.w;
+    tgt = (uint32_t)(((unsigned long long)(w >> 8) * total) >> 24);
   }
-  // draw k: the first lane (block) whose last running total exceeds the
-  // target, then the first entry of that lane that does (totals only grow at
-  // entries of positive mass, so that z has positive mass); lane k keeps it
+  // draw k: the block holding it is the first whose running total exceeds the
+  // target (totals only grow in page and lane order); lane k keeps the block
+  // and the target's offset into it
   constexpr int kNone = 0x7fffffff;
-  int zsel = kNone;
-  uint32_t found = 0u;
-  const uint32_t all = (n >= 32) ? 0xFFFFFFFFu : ((1u << n) - 1u);
-  float base2 = 0.f;
-  int lp2 = -1;
-  for (int g = 0; g < npg && found != all; ++g) {
-    if (npg > 1) obs_page(g, L, otab, lmp, p0tab, lw, lvv, base2, F, lp2);
-    const bool live = g * kWave + lane <= L;
+  int zsel = kNone, dblk = 0;
+  uint32_t doff = 0u;
+  if (total > 0u) {
     for (int k = 0; k < n; ++k) {
-      if ((found >> k) & 1u) continue;
-      const float tk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tgt), k));
-      const unsigned long long hit = __ballot(live && F[15] > tk);
-      if (hit == 0ull) continue;
-      const int js = __ffsll((long long)hit) - 1;
-      int below = 0;
+      const uint32_t tk = (uint32_t)__builtin_amdgcn_readlane((int)tgt, k);
+      bool done = false;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) below += (F[i] <= tk) ? 1 : 0;
-      const int c = __builtin_amdgcn_readlane(below, js);
-      if (lane == k) zsel = (g * kWave + js) * 16 + c;
-      found |= 1u << k;
+      for (int g = 0; g < kObsPages; ++g) {
+        if (done || g >= npg) continue;
+        const unsigned long long hit = __ballot(incl[g] > tk);
+        if (hit == 0ull) continue;
+        const int js = __ffsll((long long)hit) - 1;
+        const uint32_t before =
+            js > 0 ? (uint32_t)__builtin_amdgcn_readlane((int)incl[g], js - 1) : pbase[g];
+        if (lane == k) {
+          dblk = g * kWave + js;
+          doff = tk - before;
+        }
+        done = true;
+      }
+    }
+    // lane k < n: the first entry of its block whose running total within the
+    // block exceeds the offset (an entry of positive integer mass)
+    if (lane < n) {
+      float v[16];
+      uint32_t q[16];
+      obs_block(dblk, L, otab, lmp, p0tab, lw, lvv, v);
+      (void)block_masses(v, e, q);
+      uint32_t run = 0u;
+      int c = 16;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        run += q[i];
+        if (c == 16 && run > doff) c = i;
+      }
+      if (c < 16) zsel = dblk * 16 + c;
     }
   }
-  if (found != all) {
-    // a target that rounding left at or beyond the total takes the last z of
-    // positive mass
-    int lastz = lastpos;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) lastz = max(lastz, __shfl_xor(lastz, o, kWave));
-    if (lane < n && zsel == kNone) zsel = lastz;
-  }
+  if (zsel == kNone) zsel = -1;   // no mass at all: no draw
   // lane k < n: P(z_k) of its draw
   float pk = 0.f;
   if (lane < n && zsel >= 0) {
@@ -853,43 +872,6 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_local_id(int i, int n) {
   const int q = n / kXcds, r = n - q * kXcds, x = i % kXcds;
   return x * q + min(x, r) + i / kXcds;
-}
-
-// Dynamic (parent, band) items of the per-parent last level, whose
-// workgroups stay resident and take items until every queue is empty.  The
-// hardware deals workgroups to the XCDs in turn, and one XCD can run the
-// level's items markedly slower than the others (measured: up to twice the
-// time of the rest for an equal share), so only workgroups that loop over a
-// shared supply keep the XCDs finishing together (the grid is at most what
-// the CUs hold at once).  Queue x holds the bands of a contiguous eighth of
-// the map, [x T / 8, (x + 1) T / 8), of every parent j (j-major, parents in
-// visiting order); a workgroup takes from the queue of the XCD it runs on,
-// whose L2 then holds those bands' rows of Q and R and the halo rows
-// neighbouring bands share, and only when that queue is empty from the next
-// ones.  Each counter value is handed out once, so every item is taken
-// exactly once; a workgroup leaves after finding all queues empty.  Returns
-// j * tiles + band, or -1.  Thread 0 takes; s_item is LDS; ends with a
-// barrier.
-__device__ __forceinline__ int take_band_item(int32_t *wq, int nslots, int tiles, int *s_item) {
-  static_assert(kQueueXcds == kXcds, "one queue per XCD");
-  if (threadIdx.x == 0) {
-    // this wavefront's XCD (the XCC_ID hardware register, bits 0..3)
-    const int x0 = (int)(__builtin_amdgcn_s_getreg((3 << 11) | 20) & (kXcds - 1));
-    int item = -1;
-    for (int t = 0; t < kXcds && item < 0; ++t) {
-      const int x = (x0 + t) & (kXcds - 1);
-      const int lo = x * tiles / kXcds, nb = (x + 1) * tiles / kXcds - lo;
-      if (nb == 0) continue;
-      const int k = atomicAdd(&wq[x], 1);
-      if (k < nslots * nb) {
-        const int j = k / nb;
-        item = j * tiles + lo + (k - j * nb);
-      }
-    }
-    *s_item = item;
-  }
-  __syncthreads();
-  return *s_item;
 }
 
 // Work item idx = (p * tiles + tile) * A + a of a level.
@@ -1919,6 +1901,123 @@ __host__ __device__ inline size_t leaf_parent_lds_floats(int W, int TH, int L, i
   return x + (hist > lmt ? hist : lmt);
 }
 
+// The histograms HQ ([AM][16][AM + 1]) and R(b,a) (sh.rb) of parent p from
+// its band records, each entry summed in band order (records written with
+// device-scope stores by the band items).  Ends with the workgroup's loads done
+// (no barrier).
+template <int AM, int NT>
+__device__ void leaf_parent_sum_records(const LevelArgs &lv, int p, float *HQ,
+                                        LeafParentShared &sh) {
+  constexpr int NV = AM + 1;
+  constexpr int RECN = AM * 16 * NV + AM;
+  const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
+  for (int i = threadIdx.x; i < RECN; i += NT) {
+    float sum = 0.f;
+    int t0 = 0;
+    for (; t0 + 4 <= lv.tiles; t0 += 4) {
+      float x[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[k] = ld_coherent(rec0 + (size_t)(t0 + k) * RECN + i);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sum += x[k];
+    }
+    for (; t0 < lv.tiles; ++t0) sum += ld_coherent(rec0 + (size_t)t0 * RECN + i);
+    if (i < AM * 16 * NV)
+      HQ[i] = sum;
+    else
+      sh.rb[i - AM * 16 * NV] = sum;
+  }
+}
+
+// Completion of parent p of the last level from its whole-belief statistics
+// (HQ, sh.rb; the landmark cells' predicted masses in lv.lmv): the draws of
+// every action (Alg. 3/4), the leaf values of the drawn children (Alg. 5), the
+// Q-node values (Alg. 6), the node value, then the backup towards the root
+// (Alg. 7).  X: LDS scratch of at least (1 + NW) L + 32 NW floats and of the
+// backup's K + A.
+template <int AM, int NT>
+__device__ void leaf_parent_finish(const DevModel &m, const LevelArgs &lv, const TreeArgs &tr,
+                                   int p, float *X, const float *HQ, LeafParentShared &sh) {
+  constexpr int NV = AM + 1;
+  constexpr int NW = NT / kWave;
+  const int A = m.A, L = m.L, K = lv.K, n = lv.n;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const float rho = m.lm_p;
+  float *part = X;
+  // observation draws: wavefront w takes actions w, w + 4, ...
+  uint32_t *lw = (uint32_t *)X;
+  for (int l = tid; l < L; l += NT) lw[l] = lv.lm_wall[l];
+  wait_mem();
+  __syncthreads();
+  float *lvv = X + L + wave * L;
+  for (int a = wave; a < A; a += NW) {
+    for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    float hs = 0.f;
+    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
+    if (lane == 16) hs = sh.rb[a];
+    sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
+    // (after the draws: the wait before them need not cover this store)
+    if (lane == 16) lv.reward[p * A + a] = hs;
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // leaf values (Alg. 5) of every drawn child of every action:
+  //   zl = 0: (1/P(z)) sum_w O_w(zw|w) HQ_a[w][c];  zl = l: (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) Q(x_l,c)
+  for (int i = tid; i < A * n * AM; i += NT) {
+    const int a = i / (n * AM), r = (i / AM) - a * n, c = i - (i / AM) * AM;
+    float v = 0.f;
+    if (c < A && r < sh.draw[a].U) {
+      const int z = sh.draw[a].z[r];
+      const uint32_t zw = (uint32_t)(z & 15);
+      const int zl = z >> 4;
+      if (zl == 0) {
+#pragma unroll
+        for (int w = 0; w < 16; ++w)
+          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
+      } else {
+        const int cell = m.lm_cell[zl - 1];
+        v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
+            ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * lv.Q[(size_t)cell * A + c];
+      }
+      v *= sh.draw[a].inv[r];
+    }
+    sh.leaf[i] = v;
+  }
+  __syncthreads();
+  // Q-node values (Alg. 6), the node value, then the backup towards the root
+  const long long g = tr.first[lv.d] + p;
+  if (tid < A) {
+    const int a = tid;
+    float qv = sh.rb[a];
+    const long long lf = tr.first[lv.d + 1] + (long long)p * K + (long long)a * n;
+    for (int r = 0; r < sh.draw[a].U; ++r) {
+      float best = -INFINITY;
+      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(a * n + r) * AM + c]);
+      tr.value[lf + r] = best;
+      qv += tr.gamma * ((float)sh.draw[a].count[r] / (float)n) * best;
+    }
+    tr.qvalue[g * A + a] = qv;
+    sh.qn[a] = qv;
+  }
+  __syncthreads();
+  if (tid == 0) finish_node(tr, lv.d, g, sh.qn);
+  __syncthreads();
+  climb_wg(tr, lv.d, p, part, &sh.last);
+}
+
+// k_leaf_finish's LDS: the scratch X (landmark tables and sampler tables of
+// every wavefront, or the backup's K + A values), then the histograms HQ.
+__host__ __device__ inline size_t leaf_finish_x_floats(int L, int K, int A, int NT) {
+  const size_t lmk = (size_t)(1 + NT / kWave) * L + 32 * (NT / kWave);
+  const size_t bk = (size_t)K + A;
+  return lmk > bk ? lmk : bk;
+}
+__host__ __device__ inline size_t leaf_finish_lds_floats(int L, int K, int A, int AM) {
+  return leaf_finish_x_floats(L, K, A, kLeafBlock) + (size_t)AM * 16 * (AM + 1);
+}
+
 // QV: how Q rows are read (load_q_row).  AM: Q columns padded to 4 or 8.
 // NT threads (kBlock or 2 kBlock): with 2 kBlock, neighbouring lanes 2k and
 // 2k + 1 share sorted chunk k (alternate cells) and every wavefront draws for
@@ -1935,12 +2034,12 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   constexpr int LPB = NT == kBlock ? kLeafParentBatch : 1;
   constexpr int RECN = AM * 16 * NV + AM;   // band record: HQ, then R(b,a)
   const int A = m.A, W = m.W, BW = W + 2, S = m.S, L = m.L;
-  const int K = lv.K, n = lv.n;
+  const int K = lv.K;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   if (!lv.pvalid[p]) {
-    // children of an absent parent are absent; the parent takes no part in
-    // any backup
-    if (band == 0)
+    // children of an absent parent are absent (marked by k_leaf_finish when
+    // it completes the parents); the parent takes no part in any backup
+    if (band == 0 && !lv.leaf_finish)
       for (int i = tid; i < K; i += NT) {
         const int c = p * K + i;
         lv.cvalid[c] = 0;
@@ -2237,95 +2336,21 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   }
   __syncthreads();
   if (lv.tiles > 1) {
-    // band record out; the last band of the parent sums all records in band order
+    // band record out; k_leaf_finish, or else the last band of the parent,
+    // sums all records in band order
     float *rec = lv.part + ((size_t)p * lv.tiles + band) * RECN;
     for (int i = tid; i < RECN; i += NT) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
+    if (lv.leaf_finish) return;
     wait_mem();
     __syncthreads();
     if (tid == 0) sh.last = (count_arrival(&lv.ctr[p]) == lv.tiles - 1);
     __syncthreads();
     if (!sh.last) return;
-    const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
-    for (int i = tid; i < RECN; i += NT) {
-      float sum = 0.f;
-      int t0 = 0;
-      for (; t0 + 4 <= lv.tiles; t0 += 4) {
-        float x[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = ld_coherent(rec0 + (size_t)(t0 + k) * RECN + i);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) sum += x[k];
-      }
-      for (; t0 < lv.tiles; ++t0) sum += ld_coherent(rec0 + (size_t)t0 * RECN + i);
-      if (i < AM * 16 * NV)
-        HQ[i] = sum;
-      else
-        sh.rb[i - AM * 16 * NV] = sum;
-    }
+    leaf_parent_sum_records<AM, NT>(lv, p, HQ, sh);
     if (tid == 0) lv.ctr[p] = 0;
     __syncthreads();
   }
-  // observation draws: wavefront w takes actions w, w + 4, ...
-  uint32_t *lw = (uint32_t *)X;
-  for (int l = tid; l < L; l += NT) lw[l] = lv.lm_wall[l];
-  wait_mem();
-  __syncthreads();
-  float *lvv = X + L + wave * L;
-  for (int a = wave; a < A; a += NW) {
-    for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    float hs = 0.f;
-    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
-    if (lane == 16) hs = sh.rb[a];
-    sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
-    // (after the draws: the wait before them need not cover this store)
-    if (lane == 16) lv.reward[p * A + a] = hs;
-    __builtin_amdgcn_wave_barrier();
-  }
-  __syncthreads();
-  // leaf values (Alg. 5) of every drawn child of every action:
-  //   zl = 0: (1/P(z)) sum_w O_w(zw|w) HQ_a[w][c];  zl = l: (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) Q(x_l,c)
-  for (int i = tid; i < A * n * AM; i += NT) {
-    const int a = i / (n * AM), r = (i / AM) - a * n, c = i - (i / AM) * AM;
-    float v = 0.f;
-    if (c < A && r < sh.draw[a].U) {
-      const int z = sh.draw[a].z[r];
-      const uint32_t zw = (uint32_t)(z & 15);
-      const int zl = z >> 4;
-      if (zl == 0) {
-#pragma unroll
-        for (int w = 0; w < 16; ++w)
-          v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
-      } else {
-        const int cell = m.lm_cell[zl - 1];
-        v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
-            ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * lv.Q[(size_t)cell * A + c];
-      }
-      v *= sh.draw[a].inv[r];
-    }
-    sh.leaf[i] = v;
-  }
-  __syncthreads();
-  // Q-node values (Alg. 6), the node value, then the backup towards the root
-  const long long g = tr.first[lv.d] + p;
-  if (tid < A) {
-    const int a = tid;
-    float qv = sh.rb[a];
-    const long long lf = tr.first[lv.d + 1] + (long long)p * K + (long long)a * n;
-    for (int r = 0; r < sh.draw[a].U; ++r) {
-      float best = -INFINITY;
-      for (int c = 0; c < A; ++c) best = fmaxf(best, sh.leaf[(a * n + r) * AM + c]);
-      tr.value[lf + r] = best;
-      qv += tr.gamma * ((float)sh.draw[a].count[r] / (float)n) * best;
-    }
-    tr.qvalue[g * A + a] = qv;
-    sh.qn[a] = qv;
-  }
-  __syncthreads();
-  if (tid == 0) finish_node(tr, lv.d, g, sh.qn);
-  __syncthreads();
-  climb_wg(tr, lv.d, p, part, &sh.last);
+  leaf_parent_finish<AM, NT>(m, lv, tr, p, X, HQ, sh);
 }
 
 template <int AM, int QV>
@@ -2333,18 +2358,49 @@ __global__ __launch_bounds__(kLeafBlock, 4) void k_leaf_parent(DevModel m, Level
                                                                  TreeArgs tr) {
   extern __shared__ float smem[];
   __shared__ LeafParentShared sh;
-  __shared__ int s_item;
-  // Items come from the per-XCD band queues, parents in visiting order: with
-  // one (levels below the root) the present parents come first, and the
-  // items of absent parents (which only mark their children absent) last.
-  for (;;) {
-    const int i = take_band_item(lv.wq, lv.nslots, lv.tiles, &s_item);
-    if (i < 0) break;
-    const int j = i / lv.tiles, band = i - j * lv.tiles;
-    const int p = lv.porder ? lv.porder[j] : j;
-    leaf_parent_item<AM, QV, kLeafBlock>(m, lv, tr, p, band, smem, sh);
-    __syncthreads();
+  // With a visiting order, the present parents come first: they are
+  // dispatched first, dealt to the XCDs in turn and spread over the CUs,
+  // while the workgroups of absent parents (which only mark their children
+  // absent) come last.  Without one, workgroup i runs on XCD i mod 8; slot
+  // p = node*K + a*n + r, and the low r (the first distinct draw of each
+  // Q-node, nearly always present) would all land on the same XCDs when K
+  // is a multiple of 8, so each group of 8 is rotated by its index.
+  int i = blockIdx.x;
+  const int grp8 = i >> 3;
+  if (!lv.porder && (grp8 + 1) * 8 <= (int)gridDim.x) i = grp8 * 8 + ((i + grp8) & 7);
+  const int j = i / lv.tiles, band = i - j * lv.tiles;
+  const int p = lv.porder ? lv.porder[j] : j;
+  leaf_parent_item<AM, QV, kLeafBlock>(m, lv, tr, p, band, smem, sh);
+}
+
+// Completion of the parents of the per-parent last level when it runs in
+// several bands: one workgroup per parent, present parents first (with a
+// visiting order), after every band item has written its record.  Doing it
+// here rather than in the band item that arrives last keeps that work (the
+// draws, the leaf values, the backup) off the XCD whose items run slowest,
+// which otherwise collects most of it and falls further behind.  Absent
+// parents mark their children absent.
+template <int AM>
+__global__ __launch_bounds__(kLeafBlock) void k_leaf_finish(DevModel m, LevelArgs lv,
+                                                            TreeArgs tr) {
+  extern __shared__ float smem[];
+  __shared__ LeafParentShared sh;
+  const int p = lv.porder ? lv.porder[blockIdx.x] : (int)blockIdx.x;
+  if (!lv.pvalid[p]) {
+    for (int i = threadIdx.x; i < lv.K; i += kLeafBlock) {
+      const int c = p * lv.K + i;
+      lv.cvalid[c] = 0;
+      lv.cz[c] = -1;
+      lv.ccount[c] = 0;
+      lv.cpz[c] = 0.f;
+    }
+    return;
   }
+  float *X = smem;
+  float *HQ = smem + leaf_finish_x_floats(m.L, lv.K, m.A, kLeafBlock);
+  leaf_parent_sum_records<AM, kLeafBlock>(lv, p, HQ, sh);
+  __syncthreads();
+  leaf_parent_finish<AM, kLeafBlock>(m, lv, tr, p, X, HQ, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2453,45 +2509,6 @@ __global__ __launch_bounds__(1024) void k_backup(TreeArgs g) {
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-// Grid of a resident launch: the workgroups the CUs hold at once (occupancy
-// of kernel k at this block size and dynamic LDS), at most one per item.
-// Cached per (kernel, block, LDS bytes, device).
-static unsigned resident_grid(const void *k, int block, size_t lds, long long items) {
-  struct Entry {
-    const void *k;
-    int block;
-    size_t lds;
-    int dev;
-    long long cap;
-  };
-  static Entry cache[16];
-  static int ncache = 0;
-  static std::mutex mu;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = -1;
-  long long cap = 0;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    for (int i = 0; i < ncache; ++i)
-      if (cache[i].k == k && cache[i].block == block && cache[i].lds == lds && cache[i].dev == dev)
-        cap = cache[i].cap;
-  }
-  if (cap == 0) {
-    int cus = 0, per = 0;
-    if (dev >= 0 &&
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, block, lds) == hipSuccess &&
-        cus > 0 && per > 0) {
-      cap = (long long)cus * per;
-      std::lock_guard<std::mutex> g(mu);
-      if (ncache < 16) cache[ncache++] = {k, block, lds, dev, cap};
-    } else {
-      cap = items;   // no occupancy figure: one workgroup per item still drains the queues
-    }
-  }
-  return (unsigned)std::max<long long>(1, std::min(items, cap));
-}
-
 static size_t band_bytes(int W, int TH) { return (size_t)(TH + 2) * (W + 2) * sizeof(float); }
 size_t band_lds_bytes(int W, int TH) { return band_bytes(W, TH); }
 // k_leaf: the band, then the block_sum32 scratch or the backup scratch
@@ -2554,8 +2571,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
 
   uint32_t *lm_wall = (uint32_t *)(ws + L.lm_wall);
   const PrepExtra px = {valid, zrec, cnt, pz, ctr,
-                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2 * (QV_MAX_DEPTH + 1) +
-                                    kQueueInts),
+                        (long long)(L.stats_ctr_len + L.node_ctr_len + 2 * (QV_MAX_DEPTH + 1)),
                         lm_wall};
   prep_plan_launch(m, sig, staytab, err, px, st);
 
@@ -2636,6 +2652,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.lm_wall = lm_wall;
     lv.ctr = ctr;
     lv.q_vec = q_vec;
+    lv.leaf_finish = 0;
     lv.sort_cells = sort_cells;
     lv.sort_chunk = sort_chunk;
     lv.sort_bands = 0;
@@ -2659,11 +2676,10 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
       lv.part = (float *)(ws + L.leafrec);
-      // item queues after the visiting-list counts (cleared by the prep pass)
-      lv.wq = slot_n + 2 * (QV_MAX_DEPTH + 1);
-      const void *kfn = AM == 4 ? (q_vec ? (const void *)k_leaf_parent<4, 1> : (const void *)k_leaf_parent<4, 0>)
-                                : (q_vec ? (const void *)k_leaf_parent<8, 1> : (const void *)k_leaf_parent<8, 0>);
-      const unsigned nb = resident_grid(kfn, kLeafBlock, lds_lp, (long long)lv.nslots * L.leaf_tiles);
+      // several bands: the band items write records, k_leaf_finish completes
+      // the parents
+      lv.leaf_finish = L.leaf_tiles > 1 ? 1 : 0;
+      const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
       if (AM == 4 && q_vec)
         QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else if (AM == 4)
@@ -2672,6 +2688,13 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
         QV_LAUNCH_L(d, (k_leaf_parent<8, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else
         QV_LAUNCH_L(d, (k_leaf_parent<8, 0>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
+      if (lv.leaf_finish) {
+        const size_t lds_fin = leaf_finish_lds_floats(m.L, K, A, AM) * sizeof(float);
+        if (AM == 4)
+          QV_LAUNCH_L(d, k_leaf_finish<4>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv, tr);
+        else
+          QV_LAUNCH_L(d, k_leaf_finish<8>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv, tr);
+      }
       continue;
     }
     if (small) {
