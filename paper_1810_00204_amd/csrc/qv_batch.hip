@@ -277,6 +277,7 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
       lv.slot_cap = 0;
       lv.porder = nullptr;
       lv.leaf_finish = 0;   // the last band of a parent completes it
+      lv.draws_apart = 0;   // the last band of a Q-node draws
       if (d + 1 == D && bq.leaf_parent) {
         lv.TH = L.leaf_rows;
         lv.tiles = L.leaf_tiles;

@@ -59,6 +59,8 @@ struct LevelArgs {
   int leaf_finish;        // per-parent last level with several bands: 1 = the band items
                           // only write their records and k_leaf_finish completes each
                           // parent; 0 = the last band of a parent to finish completes it
+  int draws_apart;        // banded per-parent statistics: 1 = k_stats_draws draws after
+                          // the launch; 0 = the last band of a parent draws
   // free cells in true-wall-reading order and their chunks (see k_prep_sort)
   const int32_t *sort_cells, *sort_chunk;
   int sort_bands, sort_tc;   // bands sorted by extra workgroups of this launch (0: none)

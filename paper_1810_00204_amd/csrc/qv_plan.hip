@@ -1245,7 +1245,9 @@ __device__ void stats_parent_item(const DevModel &m, const LevelArgs &lv, int p,
     }
     __syncthreads();   // the bins are reused by the next action
   }
-  // the last band of this parent to finish draws for every action
+  // k_stats_draws draws for every action after the launch; else the last
+  // band of this parent to finish does
+  if (lv.draws_apart) return;
   wait_mem();
   __syncthreads();
   if (tid == 0) sh.last = (count_arrival(&lv.ctr[p * A]) == lv.tiles - 1);
@@ -1257,12 +1259,28 @@ __device__ void stats_parent_item(const DevModel &m, const LevelArgs &lv, int p,
   if (tid == 0) lv.ctr[p * A] = 0;
 }
 
+// Workgroup i takes band i mod tiles of parent i / tiles: consecutive bands of
+// a parent go to different XCDs (workgroups are dealt to the XCDs in turn),
+// so every XCD gets an equal share of every present parent's bands (a band
+// is read by one workgroup only, for all actions; the same bands recur on an
+// XCD, whose L2 then holds their rows of R).
 __global__ __launch_bounds__(kBlock) void k_stats_parent(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ ParentShared sh;
-  const int idx = xcd_local_id(blockIdx.x, gridDim.x);
-  const int p = idx / lv.tiles;
-  stats_parent_item(m, lv, p, idx - p * lv.tiles, smem, sh);
+  const int p = blockIdx.x / lv.tiles;
+  stats_parent_item(m, lv, p, blockIdx.x - p * lv.tiles, smem, sh);
+}
+
+// The draws of the Q-nodes of a banded level once every band has written its
+// partial sums: one wavefront per (parent, action).  Run apart from the band
+// items, the draws neither wait for the last band of each parent nor pile up
+// on the XCD whose bands arrive last.  Absent parents were handled by their
+// first band.  LDS: 2 L + 32 floats.
+__global__ __launch_bounds__(kWave) void k_stats_draws(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  const int p = blockIdx.x / m.A, a = blockIdx.x - p * m.A;
+  if (!lv.pvalid[p]) return;
+  sample_qnode(m, lv, p, a, smem);
 }
 
 __device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p, int tile,
@@ -1331,12 +1349,12 @@ __device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p
   }
 }
 
+// Workgroup i takes band i mod tiles of parent i / tiles (see k_stats_parent).
 __global__ __launch_bounds__(kBlock) void k_update_parent(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ ParentShared sh;
-  const int idx = xcd_local_id(blockIdx.x, gridDim.x);
-  const int p = idx / lv.tiles;
-  update_parent_item(m, lv, p, idx - p * lv.tiles, smem, sh);
+  const int p = blockIdx.x / lv.tiles;
+  update_parent_item(m, lv, p, blockIdx.x - p * lv.tiles, smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2653,6 +2671,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.ctr = ctr;
     lv.q_vec = q_vec;
     lv.leaf_finish = 0;
+    lv.draws_apart = 0;
     lv.sort_cells = sort_cells;
     lv.sort_chunk = sort_chunk;
     lv.sort_bands = 0;
@@ -2717,9 +2736,13 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     }
     const unsigned nblk = (unsigned)((long long)lv.nslots * tiles * A);
     const unsigned npar = (unsigned)((long long)lv.nslots * tiles);
-    if (per_parent)
+    if (per_parent) {
+      lv.draws_apart = 1;
       QV_LAUNCH_L(d, k_stats_parent, dim3(npar), dim3(kBlock), lds_spar, st, m, lv);
-    else
+      QV_LAUNCH_L(d, k_stats_draws, dim3((unsigned)((long long)lv.nslots * A)), dim3(kWave),
+                  (size_t)(2 * m.L + 32) * sizeof(float), st, m, lv);
+      lv.draws_apart = 0;
+    } else
       QV_LAUNCH_L(d, k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
     if ((!last || store_leaves) && per_parent) {
       QV_LAUNCH_L(d, k_update_parent, dim3(npar), dim3(kBlock), lds_band, st, m, lv);

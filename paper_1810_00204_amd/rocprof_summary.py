@@ -72,6 +72,7 @@ def level_grids(workload: str):
             out[(fam, slots * tiles * A * BLOCK)] = d
         for fam in ("k_stats_parent", "k_update_parent"):
             out[(fam, slots * tiles * BLOCK)] = d
+        out[("k_stats_draws", slots * A * 64)] = d
     out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * NODE_BLOCK)] = D - 1
     out[("k_leaf_finish", K ** (D - 1) * NODE_BLOCK)] = D - 1
     return out
