@@ -1350,9 +1350,22 @@ __device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p
 }
 
 // Workgroup i takes band i mod tiles of parent i / tiles (see k_stats_parent).
+// SORT: the launch carries lv.sort_bands extra workgroups at the end that sort
+// the last level's bands (as k_prep_sort); the level-0 launch, one workgroup
+// per CU, has room for them.
+template <bool SORT>
 __global__ __launch_bounds__(kBlock) void k_update_parent(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ ParentShared sh;
+  if constexpr (SORT) {
+    const int items = (int)gridDim.x - lv.sort_bands;
+    if ((int)blockIdx.x >= items) {
+      const int band = blockIdx.x - items, c_lo = band * lv.sort_tc;
+      sort_band(c_lo, min(m.S, c_lo + lv.sort_tc), m.L, lv.sig, (int32_t *)lv.sort_cells,
+                (int32_t *)lv.sort_chunk + (size_t)band * kSortChunkInts);
+      return;
+    }
+  }
   const int p = blockIdx.x / lv.tiles;
   update_parent_item(m, lv, p, blockIdx.x - p * lv.tiles, smem, sh);
 }
@@ -2628,7 +2641,10 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       if (e != hipSuccess) return e;
     }
   }
-  if (leaf_parent && !sort_in_l0) {
+  // on the banded path with D >= 2 the level-0 update launch sorts the leaf
+  // bands; otherwise a launch of its own does
+  const bool sort_in_update = leaf_parent && !small && per_parent && D >= 2;
+  if (leaf_parent && !sort_in_l0 && !sort_in_update) {
     QV_LAUNCH(k_prep_sort, dim3(L.leaf_tiles), dim3(kBlock), 0, st, m.S, L.leaf_rows * m.W, m.L,
               sig, sort_cells, sort_chunk);
   }
@@ -2744,8 +2760,15 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.draws_apart = 0;
     } else
       QV_LAUNCH_L(d, k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
-    if ((!last || store_leaves) && per_parent) {
-      QV_LAUNCH_L(d, k_update_parent, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
+    if ((!last || store_leaves) && per_parent && d == 0 && sort_in_update) {
+      lv.sort_bands = L.leaf_tiles;
+      lv.sort_tc = L.leaf_rows * m.W;
+      QV_LAUNCH_L(d, k_update_parent<true>, dim3(npar + L.leaf_tiles), dim3(kBlock), lds_band, st,
+                  m, lv);
+      lv.sort_bands = 0;
+      lv.sort_tc = 0;
+    } else if ((!last || store_leaves) && per_parent) {
+      QV_LAUNCH_L(d, k_update_parent<false>, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
     } else if (!last || store_leaves) {
       QV_LAUNCH_L(d, k_update, dim3(nblk), dim3(kBlock), lds_band, st, m, lv);
     } else if (A <= 4) {

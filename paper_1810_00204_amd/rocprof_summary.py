@@ -72,6 +72,8 @@ def level_grids(workload: str):
             out[(fam, slots * tiles * A * BLOCK)] = d
         for fam in ("k_stats_parent", "k_update_parent"):
             out[(fam, slots * tiles * BLOCK)] = d
+        if d == 0:   # the level-0 update launch also carries the leaf-band sort
+            out[("k_update_parent", (slots * tiles + leaf_tiles) * BLOCK)] = d
         out[("k_stats_draws", slots * A * 64)] = d
     out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * NODE_BLOCK)] = D - 1
     out[("k_leaf_finish", K ** (D - 1) * NODE_BLOCK)] = D - 1
