@@ -278,6 +278,8 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
       lv.porder = nullptr;
       lv.leaf_finish = 0;   // the last band of a parent completes it
       lv.draws_apart = 0;   // the last band of a Q-node draws
+      lv.own_reward = 1;    // every item forms R(b,a) of its own parent
+      lv.creward = nullptr;
       if (d + 1 == D && bq.leaf_parent) {
         lv.TH = L.leaf_rows;
         lv.tiles = L.leaf_tiles;

@@ -61,6 +61,11 @@ struct LevelArgs {
                           // parent; 0 = the last band of a parent to finish completes it
   int draws_apart;        // banded per-parent statistics: 1 = k_stats_draws draws after
                           // the launch; 0 = the last band of a parent draws
+  int own_reward;         // per-parent band items: 1 = they form R(b,a) of their parent
+                          // (an R(b,a) pass over the band); 0 = the level above wrote it
+                          // into `reward` (from its reward-weighted histograms)
+  float *creward;         // reward rows [slot][A] of the child level (level d+1), written by
+                          // k_inner_finish, or null
   // free cells in true-wall-reading order and their chunks (see k_prep_sort)
   const int32_t *sort_cells, *sort_chunk;
   int sort_bands, sort_tc;   // bands sorted by extra workgroups of this launch (0: none)

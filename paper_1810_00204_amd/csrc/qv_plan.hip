@@ -1975,6 +1975,11 @@ __device__ void leaf_parent_finish(const DevModel &m, const LevelArgs &lv, const
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const float rho = m.lm_p;
   float *part = X;
+  if (!lv.own_reward) {
+    // R(b,a) of this parent came from the level above
+    if (tid < A) sh.rb[tid] = lv.reward[p * A + tid];
+    __syncthreads();
+  }
   // observation draws: wavefront w takes actions w, w + 4, ...
   uint32_t *lw = (uint32_t *)X;
   for (int l = tid; l < L; l += NT) lw[l] = lv.lm_wall[l];
@@ -1990,7 +1995,7 @@ __device__ void leaf_parent_finish(const DevModel &m, const LevelArgs &lv, const
     if (lane == 16) hs = sh.rb[a];
     sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
     // (after the draws: the wait before them need not cover this store)
-    if (lane == 16) lv.reward[p * A + a] = hs;
+    if (lane == 16 && lv.own_reward) lv.reward[p * A + a] = hs;
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
@@ -2106,7 +2111,7 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
   float racc[AM];
 #pragma unroll
   for (int a = 0; a < AM; ++a) racc[a] = 0.f;
-  {
+  if (lv.own_reward) {
     const float *Rt = m.R;
     const bool r_vec = (A == AM) && ((reinterpret_cast<uintptr_t>(Rt) & 15u) == 0);
     const int ncell = th * W, t00 = y0 * W;
@@ -2366,9 +2371,9 @@ __device__ void leaf_parent_item(const DevModel &m, const LevelArgs &lv, const T
     sh.rb[tid] = sum_waves<NW>(r8);
   }
   __syncthreads();
-  if (lv.tiles > 1) {
-    // band record out; k_leaf_finish, or else the last band of the parent,
-    // sums all records in band order
+  if (lv.tiles > 1 || lv.leaf_finish) {
+    // band record out; k_leaf_finish / k_inner_finish, or else the last band
+    // of the parent, sums all records in band order
     float *rec = lv.part + ((size_t)p * lv.tiles + band) * RECN;
     for (int i = tid; i < RECN; i += NT) st_coherent(rec + i, i < AM * 16 * NV ? HQ[i] : sh.rb[i - AM * 16 * NV]);
     if (lv.leaf_finish) return;
@@ -2432,6 +2437,94 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_finish(DevModel m, LevelArg
   leaf_parent_sum_records<AM, kLeafBlock>(lv, p, HQ, sh);
   __syncthreads();
   leaf_parent_finish<AM, kLeafBlock>(m, lv, tr, p, X, HQ, sh);
+}
+
+// Completion of parent p of an inner level whose band items ran the basis
+// pass with R in place of Q (leaf_parent_item; own_reward as for the root):
+// HQ holds, per action, the predicted mass by wall reading (column AM) and the
+// reward-weighted sums RH_a[w][c] = sum over cells x of reading w of
+// lambda(x) b'_a(x) R(x,c).  Wavefront w draws for actions w, w + NW, ...
+// (Alg. 3/4), writes the child records and the next level's visiting order,
+// and (the parent's own R(b,a) when the items formed it); then every drawn
+// child's reward row follows from the same algebra as a leaf score (Sec. III
+// update, Alg. 5):
+//   R(Phi(b,a,z), c) = (1/P(z)) sum_w O_w(zw|w) RH_a[w][c]   (no landmark seen)
+//                    = (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) R(x_l,c)   (landmark l),
+// written to the child level's reward rows, so that level's band items need no
+// R(b,a) pass.  X: LDS scratch of (1 + NW) L + 32 NW floats.
+template <int AM, int NT>
+__device__ void inner_parent_finish(const DevModel &m, const LevelArgs &lv, int p, float *X,
+                                    const float *HQ, LeafParentShared &sh) {
+  constexpr int NV = AM + 1;
+  constexpr int NW = NT / kWave;
+  const int A = m.A, L = m.L, K = lv.K, n = lv.n;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const float rho = m.lm_p;
+  uint32_t *lw = (uint32_t *)X;
+  for (int l = tid; l < L; l += NT) lw[l] = lv.lm_wall[l];
+  wait_mem();
+  __syncthreads();
+  float *lvv = X + L + wave * L;
+  for (int a = wave; a < A; a += NW) {
+    for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    float hs = 0.f;
+    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
+    const int U = sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
+    if (lv.own_reward && lane == 0) lv.reward[p * A + a] = sh.rb[a];
+    if (lv.slot_list) {
+      ListPos lp = {0, 0};
+      if (lane == 0) lp = list_take(lv, U);
+      list_put(lv, p * K + a * n, U, lp);
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  for (int i = tid; i < A * n * A; i += NT) {
+    const int a = i / (n * A), r = (i / A) - a * n, c = i - (i / A) * A;
+    if (r >= sh.draw[a].U) continue;
+    const int z = sh.draw[a].z[r];
+    const uint32_t zw = (uint32_t)(z & 15);
+    const int zl = z >> 4;
+    float v = 0.f;
+    if (zl == 0) {
+#pragma unroll
+      for (int w = 0; w < 16; ++w)
+        v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
+    } else {
+      const int cell = m.lm_cell[zl - 1];
+      v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
+          ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * m.R[(size_t)cell * A + c];
+    }
+    lv.creward[((size_t)p * K + a * n + r) * A + c] = v * sh.draw[a].inv[r];
+  }
+}
+
+// Inner-level completion (inner_parent_finish), one workgroup per parent
+// after every band item has written its record.  Absent parents mark their
+// children absent and send them to the back of the visiting order.
+template <int AM>
+__global__ __launch_bounds__(kLeafBlock) void k_inner_finish(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ LeafParentShared sh;
+  const int p = blockIdx.x;
+  if (!lv.pvalid[p]) {
+    for (int i = threadIdx.x; i < lv.K; i += kLeafBlock) {
+      const int c = p * lv.K + i;
+      lv.cvalid[c] = 0;
+      lv.cz[c] = -1;
+      lv.ccount[c] = 0;
+      lv.cpz[c] = 0.f;
+    }
+    for (int a = 0; a < m.A; ++a) list_absent_children(lv, p * lv.K + a * lv.n);
+    return;
+  }
+  float *X = smem;
+  float *HQ = smem + leaf_finish_x_floats(m.L, lv.K, m.A, kLeafBlock);
+  leaf_parent_sum_records<AM, kLeafBlock>(lv, p, HQ, sh);
+  __syncthreads();
+  inner_parent_finish<AM, kLeafBlock>(m, lv, p, X, HQ, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2644,15 +2737,24 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
   // on the banded path with D >= 2 the level-0 update launch sorts the leaf
   // bands; otherwise a launch of its own does
   const bool sort_in_update = leaf_parent && !small && per_parent && D >= 2;
+  // banded path, D >= 3, default flags: levels 1..D-2 take their statistics
+  // from the basis pass over the sorted leaf bands with R in place of Q
+  // (k_leaf_parent + k_inner_finish), which also forms every child's reward;
+  // QV_PLAN_TILED keeps the per-action statistics of the batched path
+  const bool basis_inner = sort_in_update && D >= 3 && !(flags & QV_PLAN_TILED);
+  const bool r_vec = (A == 4 || A == 8) && ((uintptr_t)m.R % 16 == 0);
   if (leaf_parent && !sort_in_l0 && !sort_in_update) {
     QV_LAUNCH(k_prep_sort, dim3(L.leaf_tiles), dim3(kBlock), 0, st, m.S, L.leaf_rows * m.W, m.L,
               sig, sort_cells, sort_chunk);
   }
   if (leaf_parent) {
-    const void *kf = AM == 4 ? (q_vec ? (const void *)k_leaf_parent<4, 1> : (const void *)k_leaf_parent<4, 0>)
-                             : (q_vec ? (const void *)k_leaf_parent<8, 1> : (const void *)k_leaf_parent<8, 0>);
-    hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_lp);
-    if (e != hipSuccess) return e;
+    // every instance: the inner levels may read R with another vector width than Q
+    const void *kfs[2] = {AM == 4 ? (const void *)k_leaf_parent<4, 1> : (const void *)k_leaf_parent<8, 1>,
+                          AM == 4 ? (const void *)k_leaf_parent<4, 0> : (const void *)k_leaf_parent<8, 0>};
+    for (const void *kf : kfs) {
+      hipError_t e = hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_lp);
+      if (e != hipSuccess) return e;
+    }
   } else if (small && !store_leaves && D > 0) {
     QV_LAUNCH(k_prep_sort, dim3(1), dim3(kBlock), 0, st, m.S, m.S, m.L, sig, sort_cells,
               sort_chunk);
@@ -2688,6 +2790,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.q_vec = q_vec;
     lv.leaf_finish = 0;
     lv.draws_apart = 0;
+    lv.own_reward = 1;
+    lv.creward = nullptr;
     lv.sort_cells = sort_cells;
     lv.sort_chunk = sort_chunk;
     lv.sort_bands = 0;
@@ -2714,6 +2818,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       // several bands: the band items write records, k_leaf_finish completes
       // the parents
       lv.leaf_finish = L.leaf_tiles > 1 ? 1 : 0;
+      // with basis inner levels, R(b,a) of these parents came from the level above
+      lv.own_reward = basis_inner ? 0 : 1;
       const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
       if (AM == 4 && q_vec)
         QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
@@ -2752,6 +2858,40 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     }
     const unsigned nblk = (unsigned)((long long)lv.nslots * tiles * A);
     const unsigned npar = (unsigned)((long long)lv.nslots * tiles);
+    if (basis_inner && d >= 1) {
+      // statistics by the leaf kernel's basis pass over the sorted leaf bands,
+      // with the rows of R in place of those of Q: per action, the predicted
+      // mass and the reward-weighted sums by wall reading; k_inner_finish
+      // draws and forms the children's rewards; the update writes the children
+      lv.TH = L.leaf_rows;
+      lv.tiles = L.leaf_tiles;
+      lv.part = (float *)(ws + L.leafrec);
+      lv.leaf_finish = 1;
+      lv.own_reward = d == 1 ? 1 : 0;   // level 1's own R(b,a) is not formed above
+      lv.creward = reward + T.level_first[d + 1] * A;
+      lv.Q = m.R;
+      const unsigned nb = (unsigned)((long long)lv.nslots * L.leaf_tiles);
+      if (AM == 4 && r_vec)
+        QV_LAUNCH_L(d, (k_leaf_parent<4, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
+      else if (AM == 4)
+        QV_LAUNCH_L(d, (k_leaf_parent<4, 0>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
+      else if (r_vec)
+        QV_LAUNCH_L(d, (k_leaf_parent<8, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
+      else
+        QV_LAUNCH_L(d, (k_leaf_parent<8, 0>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
+      const size_t lds_fin = leaf_finish_lds_floats(m.L, K, A, AM) * sizeof(float);
+      if (AM == 4)
+        QV_LAUNCH_L(d, k_inner_finish<4>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv);
+      else
+        QV_LAUNCH_L(d, k_inner_finish<8>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv);
+      lv.TH = TH;
+      lv.tiles = tiles;
+      lv.part = part;
+      lv.leaf_finish = 0;
+      lv.Q = Q;
+      QV_LAUNCH_L(d, k_update_parent<false>, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
+      continue;
+    }
     if (per_parent) {
       lv.draws_apart = 1;
       QV_LAUNCH_L(d, k_stats_parent, dim3(npar), dim3(kBlock), lds_spar, st, m, lv);

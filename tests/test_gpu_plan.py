@@ -240,15 +240,35 @@ def _belief_close(gb, ob):
     assert not bad.any(), (np.flatnonzero(bad)[:5], gb[bad][:5], ob[bad][:5])
 
 
+@pytest.mark.parametrize("case", ["d3n2", "d4n1", "landmarks_goal"])
+def test_plan_basis_inner_levels_match_oracle(case):
+    """Grids beyond the one-workgroup-per-Q-node size with D >= 3 take the
+    statistics of levels 1..D-2 from the basis pass over the sorted leaf bands
+    with the rows of R in place of those of Q, and every child's reward from
+    its parent's reward-weighted histograms (the last level then forms no
+    R(b,a) of its own).  The whole tree against the oracle: draws, counts,
+    P(z), rewards, beliefs, values and the root action."""
+    _say(f"basis inner levels {case}")
+    prob = {"d3n2": lambda: wl.make_rect(seed=31, side=112, D=3, n=2),
+            "d4n1": lambda: wl.make_rect(seed=32, side=104, D=4, n=1),
+            "landmarks_goal": lambda: wl.make_rect(seed=33, side=120, n_landmarks=60,
+                                                   D=3, n=2, sigma=9.0)}[case]()
+    Q32 = _q32(prob)
+    rep = _check(prob, Q32, flags=0, beliefs=True)
+    assert len(rep.excused) <= 2, rep.excused
+
+
 @pytest.mark.parametrize("maker", ["rect64_tiled", "large"])
 def test_per_parent_items_equal_per_action_items(maker, monkeypatch):
     """The banded inner levels with one workgroup per (parent, band) over all
     actions give bitwise the same tree as one workgroup per (parent, band,
-    action): the same sums in the same order."""
+    action): the same sums in the same order.  (QV_PLAN_TILED keeps these
+    per-action statistics at every level; without it, levels 1..D-2 of a
+    large grid take the basis pass instead, tested against the oracle below.)"""
     _say(f"per-parent vs per-action banded items {maker}")
     from paper_1810_00204_amd.planner import Planner
     if maker == "large":
-        prob, flags = wl.make_large(seed=0), 0
+        prob, flags = wl.make_large(seed=0), B.QV_PLAN_TILED
         rng = np.random.default_rng(5)
         Q32 = (rng.standard_normal((prob.S, prob.A)) * 10).astype(np.float32)
         Q32[prob.occ == 1] = 0.0
