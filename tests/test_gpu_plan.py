@@ -296,5 +296,9 @@ def test_per_parent_items_equal_per_action_items(maker, monkeypatch):
         for x, y in zip(t1["b1"], t2["b1"]):
             assert np.array_equal(x, y)
     else:
+        # rows of absent nodes are never written: compare the existing ones
+        lf = t1["level_first"]
         for d in t1["beliefs"]:
-            assert np.array_equal(t1["beliefs"][d], t2["beliefs"][d])
+            live = ok[lf[d]:lf[d] + t1["beliefs"][d].shape[0]]
+            assert live.any()
+            assert np.array_equal(t1["beliefs"][d][live], t2["beliefs"][d][live])
