@@ -75,6 +75,9 @@ def level_grids(workload: str):
         if d == 0:   # the level-0 update launch also carries the leaf-band sort
             out[("k_update_parent", (slots * tiles + leaf_tiles) * BLOCK)] = d
         out[("k_stats_draws", slots * A * 64)] = d
+    for d in range(1, D - 1):   # basis inner levels (the leaf kernel with R for Q)
+        out[("k_leaf_parent", K ** d * leaf_tiles * NODE_BLOCK)] = d
+        out[("k_inner_finish", K ** d * NODE_BLOCK)] = d
     out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * NODE_BLOCK)] = D - 1
     out[("k_leaf_finish", K ** (D - 1) * NODE_BLOCK)] = D - 1
     return out
@@ -97,6 +100,21 @@ def cmd_stats(args):
                      f"{float(r['TotalDurationNs']) / 1e6:.3f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | "
                      f"{100.0 * float(r['TotalDurationNs']) / tot:.1f}% |")
+    if args.trace:
+        # the planning kernels by level, from the dispatches of the trace (a
+        # kernel that runs at several levels has one row per level)
+        grids = level_grids(args.workload)
+        per = collections.defaultdict(list)
+        for r in csv.DictReader(open(args.trace)):
+            name = short_name(r["Kernel_Name"])
+            lvl = grids.get((family(name), int(r["Grid_Size_X"])))
+            if lvl is not None:
+                per[f"{name}@L{lvl}"].append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        lines += ["", "Planning kernels by level (dispatch durations from the kernel trace):", "",
+                  "| kernel@level | calls | average us |", "|---|---|---|"]
+        for key, ds in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"| `{key}` | {len(ds)} | {sum(ds) / len(ds):.2f} |")
     open(args.out, "w").write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -149,6 +167,8 @@ def main():
     s.add_argument("--title", default="")
     s.add_argument("--top", type=int, default=12)
     s.add_argument("--out", required=True)
+    s.add_argument("--trace", default="", help="kernel trace csv: adds per-level rows")
+    s.add_argument("--workload", default="rect64")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
