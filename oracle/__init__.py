@@ -20,18 +20,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "qvo.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with AddressSanitizer and UndefinedBehaviorSanitizer;
+# loaded instead of the plain build when QVO_SANITIZED=1 (the process must
+# preload gcc's libasan and libubsan)
+_LIB_SAN = os.path.join(_HERE, "liboracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+             "-fno-omit-frame-pointer", "-g"]
 
 
-def build(force: bool = True) -> str:
+def build(force: bool = True, sanitize: bool = False) -> str:
     """Compile ``qvo.c`` with gcc (strict IEEE FP64: no fast-math, no FMA
-    contraction) into ``liboracle.so``."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+    contraction) into ``liboracle.so`` (``liboracle_san.so`` with the
+    sanitizers)."""
+    out = _LIB_SAN if sanitize else _LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared",
                                "-ffp-contract=off", "-fno-fast-math",
-                               "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-Wall", "-Wextra"] + (SAN_FLAGS if sanitize else []) +
+                              ["-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, out)
+    return out
 
 
 class _Model(C.Structure):
@@ -66,9 +75,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        san = os.environ.get("QVO_SANITIZED") == "1"
+        path = _LIB_SAN if san else _LIB
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            build(force=True, sanitize=san)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
         mp = C.POINTER(_Model)

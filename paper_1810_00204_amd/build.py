@@ -22,6 +22,10 @@ FLAGS = [
 ]
 
 
+# roctx ranges for rocprofv3's marker trace (QVTS_ROCTX=1)
+LIBS = ["-lrocprofiler-sdk-roctx"]
+
+
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
@@ -41,7 +45,7 @@ def source_hash() -> str:
 def build(verbose: bool = False) -> str:
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + sources()
+    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + sources() + LIBS
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

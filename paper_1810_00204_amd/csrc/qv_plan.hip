@@ -20,7 +20,10 @@
 // Beliefs stream through LDS in bands of whole rows with a one-cell halo;
 // all cross-workgroup sums run in a fixed order, so results are bitwise
 // reproducible.
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 
 #include "qv_internal.h"
@@ -2653,9 +2656,36 @@ static size_t small_lds_bytes(int W, int H, int A, int n, int L) {
          sizeof(float);
 }
 
+// Host-side ranges for rocprofv3 --marker-trace around a plan's launches and
+// around each level's, when QVTS_ROCTX=1 in the environment (read once).
+// They bracket the enqueueing on the host, which runs ahead of the GPU.
+static bool roctx_ranges_on() {
+  static const bool on = [] {
+    const char *e = std::getenv("QVTS_ROCTX");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+struct RoctxRange {
+  bool on;
+  explicit RoctxRange(const char *what, int d = -1) : on(roctx_ranges_on()) {
+    if (!on) return;
+    char msg[48];
+    if (d >= 0)
+      std::snprintf(msg, sizeof msg, "%s %d", what, d);
+    else
+      std::snprintf(msg, sizeof msg, "%s", what);
+    roctxRangePushA(msg);
+  }
+  ~RoctxRange() {
+    if (on) roctxRangePop();
+  }
+};
+
 hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int D, int n,
                        uint64_t seed, uint32_t qid, int flags, int32_t *action_out,
                        float *rootQ_out, char *ws, const PlanLayout &L, hipStream_t st) {
+  const RoctxRange plan_range("qv plan");
   const DevModel m = make_dev_model(mm);
   const qv_tree_layout &T = L.pub;
   const int A = m.A, K = A * n;
@@ -2760,6 +2790,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
               sort_chunk);
   }
   for (int d = 0; d < D; ++d) {
+    const RoctxRange level_range("qv plan level", d);
     LevelArgs lv;
     lv.d = d;
     lv.nslots = (int)T.level_slots[d];

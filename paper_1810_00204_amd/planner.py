@@ -3,6 +3,10 @@ problem, and readers for the tree records the library leaves in its
 workspace.  All computation happens in libqvts.so."""
 from __future__ import annotations
 
+import hashlib
+import json
+import os
+
 import numpy as np
 
 from . import binding as B
@@ -112,6 +116,53 @@ def read_tree(raw, L, beliefs: bool = True) -> dict:
     return out
 
 
+def batch_key(probs, n: int, flags: int, device_name: str, lib_hash: str) -> str:
+    """Key of a batch in the shape cache: what the batched launches' work
+    depends on (every query's grid, actions, landmarks and depth; n; the
+    flags), the device and the library build."""
+    h = hashlib.sha256()
+    h.update(json.dumps([int(n), int(flags), device_name, lib_hash]).encode())
+    for p in probs:
+        h.update(json.dumps([int(p.W), int(p.H), int(p.A), int(len(p.lm_cell)),
+                             int(p.D)]).encode())
+    return h.hexdigest()[:24]
+
+
+class ShapeCache:
+    """The batch shapes that autotuning chose, in a JSON file: {key:
+    {"tile_cells", "chunk", "ms_per_batch"}}.  Entries are merged into the
+    file and written through a temporary file, so concurrent writers lose at
+    most their own entry."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def _read(self) -> dict:
+        try:
+            with open(self.path) as f:
+                d = json.load(f)
+            return d if isinstance(d, dict) else {}
+        except (OSError, ValueError):
+            return {}
+
+    def get(self, key: str):
+        e = self._read().get(key)
+        if not isinstance(e, dict):
+            return None
+        try:
+            return int(e["tile_cells"]), int(e["chunk"]), float(e["ms_per_batch"])
+        except (KeyError, TypeError, ValueError):
+            return None
+
+    def put(self, key: str, tile_cells: int, chunk: int, ms: float):
+        d = self._read()
+        d[key] = {"tile_cells": int(tile_cells), "chunk": int(chunk), "ms_per_batch": float(ms)}
+        tmp = f"{self.path}.{os.getpid()}.tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
 class BatchPlanner:
     """Many planning queries planned together (qv_batch_*): the problems'
     device arrays, their Q tables and start beliefs, one workspace."""
@@ -128,6 +179,7 @@ class BatchPlanner:
         b0s = [p.b0 for p in probs] if b0s is None else b0s
         self.b0s = [torch.as_tensor(np.ascontiguousarray(b, np.float32)).to(device)
                     if not hasattr(b, "data_ptr") else b for b in b0s]
+        self.flags = flags
         st, self.h = B.qv_batch_create(self.models, [p.D for p in probs], self.n, flags)
         B.check(st, "qv_batch_create")
         nb = B.qv_batch_workspace_bytes(self.h)
@@ -161,10 +213,28 @@ class BatchPlanner:
         B.check(st, "qv_batch_plan")
         return self.actions, self.rootQ.view(-1, B.QV_MAX_ACTIONS)
 
-    def autotune(self, seed: int, reps: int = 3, stream=None) -> float:
+    def autotune(self, seed: int, reps: int = 3, stream=None, cache: str = None) -> float:
+        """Time the candidate shapes (qv_batch_autotune) and keep the fastest;
+        returns its ms per batch.  With `cache` (a JSON file path; default
+        $QVTS_TUNE_CACHE), a batch of the same key takes the stored shape
+        without timing, and a new choice is stored."""
+        cache = cache or os.environ.get("QVTS_TUNE_CACHE")
+        self.tuned_from_cache = False
+        if cache:
+            from .build import source_hash
+            key = batch_key(self.probs, self.n, self.flags,
+                            self.torch.cuda.get_device_name(self.device), source_hash())
+            hit = ShapeCache(cache).get(key)
+            if hit is not None:
+                self.set_shape(hit[0], hit[1])
+                self.tuned_from_cache = True
+                return hit[2]
         st, ms = B.qv_batch_autotune(self.h, self.Qs, self.b0s, seed, self.actions, self.rootQ,
                                      reps, self.ws, stream)
         B.check(st, "qv_batch_autotune")
+        if cache:
+            tc, ch = self.shape()
+            ShapeCache(cache).put(key, tc, ch, ms)
         return ms
 
     def tree(self, q: int, beliefs: bool = False) -> dict:

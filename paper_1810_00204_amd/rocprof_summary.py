@@ -119,6 +119,25 @@ def cmd_stats(args):
     print("\n".join(lines))
 
 
+def cmd_markers(args):
+    """Host time inside each roctx range (QVTS_ROCTX=1): the enqueueing of a
+    plan and of each of its levels."""
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(args.csv)):
+        per[r["Function"]].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = [f"# rocprofv3 marker trace: {args.title}", "",
+             "Command (from the repository root on the GPU host):", "",
+             "```", args.cmd, "```", "",
+             "Host time between the push and the pop of each range (the launches are",
+             "asynchronous: this is the cost of enqueueing, not of the kernels).", "",
+             "| range | count | mean us | max us |", "|---|---|---|---|"]
+    for name in sorted(per):
+        ds = per[name]
+        lines.append(f"| `{name}` | {len(ds)} | {sum(ds) / len(ds):.1f} | {max(ds):.1f} |")
+    open(args.out, "w").write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def _counter(path, copy_bytes):
     rows = list(csv.DictReader(open(path)))
     copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
@@ -169,6 +188,11 @@ def main():
     s.add_argument("--out", required=True)
     s.add_argument("--trace", default="", help="kernel trace csv: adds per-level rows")
     s.add_argument("--workload", default="rect64")
+    mk = sub.add_parser("markers")
+    mk.add_argument("csv")
+    mk.add_argument("--cmd", required=True)
+    mk.add_argument("--title", default="")
+    mk.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -178,7 +202,7 @@ def main():
     t.add_argument("--cmd-write", required=True)
     t.add_argument("--out", required=True)
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.mode](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "markers": cmd_markers}[a.mode](a)
 
 
 if __name__ == "__main__":

@@ -174,6 +174,30 @@ def test_batch_autotune_keeps_parity():
     assert np.array_equal(a2.cpu().numpy(), acts)
 
 
+def test_batch_autotune_shape_cache(tmp_path):
+    """A second batch of the same key takes the cached shape without timing
+    and plans exactly as the tuned one."""
+    _say("batch autotune cache")
+    from paper_1810_00204_amd.planner import BatchPlanner
+    probs = wl.make_batch(seed=6, nq=6, side_lo=16, side_hi=32)
+    Qs = [_q32(p) for p in probs]
+    cache = str(tmp_path / "shapes.json")
+    bp1 = BatchPlanner(probs, Qs, n=3, flags=B.QV_BATCH_GRAPH)
+    ms1 = bp1.autotune(SEED, reps=2, cache=cache)
+    assert not bp1.tuned_from_cache and ms1 > 0
+    a1, r1 = bp1.plan(SEED)
+    a1, r1 = a1.cpu().numpy().copy(), r1.cpu().numpy().copy()
+    bp2 = BatchPlanner(probs, Qs, n=3, flags=B.QV_BATCH_GRAPH)
+    ms2 = bp2.autotune(SEED, reps=2, cache=cache)
+    assert bp2.tuned_from_cache and ms2 == ms1
+    assert bp2.shape() == bp1.shape()
+    a2, r2 = bp2.plan(SEED)
+    assert np.array_equal(a2.cpu().numpy(), a1)
+    assert np.array_equal(r2.cpu().numpy(), r1)
+    for q in range(len(probs)):
+        _same_tree(bp2.tree(q), bp1.tree(q))
+
+
 @pytest.mark.parametrize("shape", [(256, 1), (4096, 4), (512, 2)])
 def test_batch_shapes_match_oracle(shape):
     _say(f"batch shape {shape}")

@@ -4,6 +4,8 @@ All calls go through the C ABI of libqvts.so.  Inputs are the seeded
 workloads; the oracle and the GPU receive identical values (the oracle
 widens the FP32 inputs exactly), and the Q table comes from the oracle's
 own FP64 value iteration rounded to FP32."""
+import os
+
 import numpy as np
 import pytest
 
@@ -11,6 +13,8 @@ import oracle
 from paper_1810_00204_amd import binding as B
 from paper_1810_00204_amd import workloads as wl
 from tests import parity
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.gpu
 
@@ -153,6 +157,36 @@ def test_plan_is_bitwise_deterministic(path):
         assert np.array_equal(t1[k], t2[k]), k
     for d in t1["beliefs"]:
         assert np.array_equal(t1["beliefs"][d], t2["beliefs"][d])
+
+
+def test_plan_with_roctx_ranges_is_unchanged(tmp_path):
+    """QVTS_ROCTX=1 brackets the plan and its levels with roctx ranges; the
+    plan it makes (in a process of its own, since the switch is read once)
+    is the one made without them."""
+    _say("plan with roctx ranges")
+    import subprocess
+    import sys
+    prob = wl.make_rect(seed=14, side=40, D=3, n=2)
+    Q32 = _q32(prob)
+    _, a1, q1 = _run(prob, Q32, flags=0)
+    np.save(tmp_path / "q.npy", Q32)
+    code = (
+        "import numpy as np, torch\n"
+        "from paper_1810_00204_amd import workloads as wl\n"
+        "from paper_1810_00204_amd.planner import Planner\n"
+        "prob = wl.make_rect(seed=14, side=40, D=3, n=2)\n"
+        f"Q = np.load({str(tmp_path / 'q.npy')!r})\n"
+        "pl = Planner(prob)\n"
+        "a, rq = pl.plan(torch.as_tensor(Q.reshape(-1)).cuda())\n"
+        "torch.cuda.synchronize()\n"
+        f"np.save({str(tmp_path / 'rq.npy')!r}, rq.cpu().numpy())\n"
+        "print('action', int(a.item()))\n")
+    env = dict(os.environ, QVTS_ROCTX="1")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                       text=True, timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert f"action {a1}" in r.stdout
+    assert np.array_equal(np.load(tmp_path / "rq.npy"), q1)
 
 
 def test_plan_seed_and_query_id_change_the_draws():

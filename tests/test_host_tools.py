@@ -35,3 +35,46 @@ def test_level_grids_of_the_64x64_workload():
     assert g[("k_node", (A + 1) * rs.NODE_BLOCK)] == 0
     # the last level: one workgroup per (parent, band); 64 x 64 is one band
     assert g[("k_leaf_parent", K ** (prob.D - 1) * rs.NODE_BLOCK)] == prob.D - 1
+
+
+def test_level_grids_of_the_512x512_workload():
+    """Level 1 of the 512x512 plan runs the leaf kernel over its parents'
+    bands (the basis inner level) and k_inner_finish; the last level runs the
+    same kernel over 32 bands of every slot."""
+    prob = wl.make_large(seed=0)
+    g = rs.level_grids("large512")
+    K = prob.A * prob.n
+    bands = (prob.H + 8192 // prob.W - 1) // (8192 // prob.W)
+    assert bands == 32
+    assert g[("k_leaf_parent", K * bands * rs.NODE_BLOCK)] == 1
+    assert g[("k_inner_finish", K * rs.NODE_BLOCK)] == 1
+    assert g[("k_leaf_parent", K ** 2 * bands * rs.NODE_BLOCK)] == 2
+    assert g[("k_leaf_finish", K ** 2 * rs.NODE_BLOCK)] == 2
+
+
+def test_shape_cache_round_trip(tmp_path):
+    from paper_1810_00204_amd.planner import ShapeCache, batch_key
+    probs = [wl.make_small(seed=1, W=12, H=9, D=2), wl.make_small(seed=2, W=20, H=20, D=3)]
+    k = batch_key(probs, 3, 0, "gfx950", "abc")
+    assert k == batch_key(probs, 3, 0, "gfx950", "abc")
+    # everything the launches' work depends on changes the key
+    assert k != batch_key(probs, 2, 0, "gfx950", "abc")
+    assert k != batch_key(probs, 3, 1, "gfx950", "abc")
+    assert k != batch_key(probs, 3, 0, "other", "abc")
+    assert k != batch_key(probs, 3, 0, "gfx950", "abd")
+    assert k != batch_key(probs[::-1], 3, 0, "gfx950", "abc")
+    deeper = [wl.make_small(seed=1, W=12, H=9, D=3), probs[1]]
+    assert k != batch_key(deeper, 3, 0, "gfx950", "abc")
+    path = str(tmp_path / "shapes.json")
+    c = ShapeCache(path)
+    assert c.get(k) is None                      # no file yet
+    c.put(k, 4096, 2, 5.25)
+    assert c.get(k) == (4096, 2, 5.25)
+    k2 = batch_key(deeper, 3, 0, "gfx950", "abc")
+    ShapeCache(path).put(k2, 512, 1, 1.5)        # merged, not replaced
+    assert c.get(k) == (4096, 2, 5.25) and c.get(k2) == (512, 1, 1.5)
+    with open(path, "w") as f:                   # a damaged file reads as empty
+        f.write("{not json")
+    assert c.get(k) is None
+    c.put(k, 256, 4, 2.0)
+    assert c.get(k) == (256, 4, 2.0)
