@@ -276,6 +276,7 @@ int32_t bind_ws(qv_batch *b, char *ws, hipStream_t st) {
       lv.slot_n = nullptr;
       lv.slot_cap = 0;
       lv.porder = nullptr;
+      lv.agroups = 1;
       lv.leaf_finish = 0;   // the last band of a parent completes it
       lv.draws_apart = 0;   // the last band of a Q-node draws
       lv.own_reward = 1;    // every item forms R(b,a) of its own parent

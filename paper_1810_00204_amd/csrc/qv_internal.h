@@ -75,6 +75,7 @@ struct LevelArgs {
   int32_t *slot_list, *slot_n;
   int slot_cap;           // entries of slot_list
   const int32_t *porder;  // this level's parent slots in visiting order (null: slot order)
+  int agroups;            // k_update_parent: action groups per (parent, band) item (0, 1: one)
 };
 
 // Whole-tree view for the expectimax backup (Alg. 6/7).

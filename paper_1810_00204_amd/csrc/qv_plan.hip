@@ -226,17 +226,42 @@ constexpr uint32_t kSortLandmark = 1u << 31;
 constexpr int kSortMaxCells = 16384;   // cells of one sorted band (leaf bands <= 8192)
 // per-cell summary kept in LDS while sorting: bits 0..7 move pattern, 8..11
 // wall reading, 12 free, 13 goal, 14 landmark
-template <int NT = kBlock>
+// DYN: the tables live in the caller's LDS at `lds` (sort_band_lds_bytes of
+// the band's cells) instead of static arrays sized for kSortMaxCells, so a
+// kernel that sorts in a few of its workgroups keeps its other workgroups
+// small.
+template <int NT>
+__host__ __device__ inline size_t sort_band_lds_bytes(int cells) {
+  return (size_t)(17 * NT + NT / kWave + 17 + 17 + 1) * 4 + (size_t)(cells + 1) * 2;
+}
+template <int NT = kBlock, bool DYN = false>
 __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_t *cells,
-                          int32_t *chunk) {
+                          int32_t *chunk, void *lds = nullptr) {
   // [w][thread], then exclusive offsets; entry e at e + e / 16 (one pad word
   // per 16), so a thread's 16 consecutive entries and its neighbours' fall in
   // different LDS banks
-  __shared__ int cnt[17 * NT];
+  int *cnt, *wtot, *s_start, *s_pchunk, *s_Cp;
+  uint16_t *cs;
+  if constexpr (DYN) {
+    cnt = (int *)lds;
+    wtot = cnt + 17 * NT;
+    s_start = wtot + NT / kWave;
+    s_pchunk = s_start + 17;
+    s_Cp = s_pchunk + 17;
+    cs = (uint16_t *)(s_Cp + 1);
+  } else {
+    __shared__ int cnt_s[17 * NT];
+    __shared__ uint16_t cs_s[kSortMaxCells];
+    __shared__ int wtot_s[NT / kWave];
+    __shared__ int start_s[17], pchunk_s[17], c_s;
+    cnt = cnt_s;
+    cs = cs_s;
+    wtot = wtot_s;
+    s_start = start_s;
+    s_pchunk = pchunk_s;
+    s_Cp = &c_s;
+  }
   auto cx = [](int e) { return e + (e >> 4); };
-  __shared__ uint16_t cs[kSortMaxCells];
-  __shared__ int wtot[NT / kWave];
-  __shared__ int s_start[17], s_pchunk[17], s_C;
   const int tid = threadIdx.x;
   const int S = c_hi - c_lo;
   // the band's signatures, coalesced, eight loads in flight per thread
@@ -305,7 +330,7 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     }
     s_start[16] = Sf;
     s_pchunk[16] = pc;
-    s_C = C;
+    *s_Cp = C;
   }
   // scatter: each thread walks its cells again in order
   int o[16];
@@ -331,8 +356,8 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     while (w < 16 && s_pchunk[w + 1] <= tid) ++w;
     int j0 = 0, j1 = 0;
     if (w < 16) {
-      j0 = s_start[w] + (tid - s_pchunk[w]) * s_C;
-      j1 = min(j0 + s_C, s_start[w + 1]);
+      j0 = s_start[w] + (tid - s_pchunk[w]) * *s_Cp;
+      j1 = min(j0 + *s_Cp, s_start[w + 1]);
     }
     chunk[2 * tid] = c_lo + j0;
     chunk[2 * tid + 1] = c_lo + j1;
@@ -1266,12 +1291,26 @@ __device__ void stats_parent_item(const DevModel &m, const LevelArgs &lv, int p,
 // a parent go to different XCDs (workgroups are dealt to the XCDs in turn),
 // so every XCD gets an equal share of every present parent's bands (a band
 // is read by one workgroup only, for all actions; the same bands recur on an
-// XCD, whose L2 then holds their rows of R).
+// XCD, whose L2 then holds their rows of R).  SORT: lv.sort_bands extra
+// workgroups ahead of the items sort the last level's bands (as
+// k_prep_sort); the level-0 launch, one item per CU, has room for them.
+template <bool SORT>
 __global__ __launch_bounds__(kBlock) void k_stats_parent(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ ParentShared sh;
-  const int p = blockIdx.x / lv.tiles;
-  stats_parent_item(m, lv, p, blockIdx.x - p * lv.tiles, smem, sh);
+  int i = blockIdx.x;
+  if constexpr (SORT) {
+    if (i < lv.sort_bands) {   // the launch's dynamic LDS holds the sort's tables
+      const int c_lo = i * lv.sort_tc;
+      sort_band<kBlock, true>(c_lo, min(m.S, c_lo + lv.sort_tc), m.L, lv.sig,
+                              (int32_t *)lv.sort_cells,
+                              (int32_t *)lv.sort_chunk + (size_t)i * kSortChunkInts, smem);
+      return;
+    }
+    i -= lv.sort_bands;
+  }
+  const int p = i / lv.tiles;
+  stats_parent_item(m, lv, p, i - p * lv.tiles, smem, sh);
 }
 
 // The draws of the Q-nodes of a banded level once every band has written its
@@ -1287,7 +1326,7 @@ __global__ __launch_bounds__(kWave) void k_stats_draws(DevModel m, LevelArgs lv)
 }
 
 __device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p, int tile,
-                                   float *smem, ParentShared &sh) {
+                                   int a_lo, int a_hi, float *smem, ParentShared &sh) {
   if (!lv.pvalid[p]) return;
   const int A = m.A, n = lv.n, K = lv.K, tid = threadIdx.x;
   // the drawn children of every action (valid ones are packed first)
@@ -1327,50 +1366,52 @@ __device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p
       sg[j] = ok ? sv : 0u;
       bt[j] = ok ? bv : 0.f;
     }
-    for (int a = 0; a < A; ++a) {
+    for (int a = a_lo; a < a_hi; ++a) {
       const int U = sh.U[a];
       if (U == 0) continue;
       const float *sl = &m.slip[a * 9];
       const float *stay_a = sh.stay + a * 256;
       const int cb = p * K + a * n;
+      float bp[kCellBatch];
 #pragma unroll
       for (int j = 0; j < kCellBatch; ++j) {
         const int i = i0 + j * kBlock;
-        if (i >= ncell) break;
         const int ly = fdiv(i, W, rW), lx = i - ly * W;
-        const int t = t00 + i;
-        const float bp = predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]);
-        const uint32_t w = sig_wall(sg[j]), lm = sig_lm(sg[j]);
-        for (int r = 0; r < U; ++r) {
-          const int zz = sh.zr[a * n + r];
-          const float o = wall_lik(m.flip, (uint32_t)(zz & 15), w) *
-                          lm_lik(rho, (uint32_t)(zz >> 4), lm);
-          lv.cbel[(size_t)(cb + r) * S + t] = o * bp * sh.inv[a * n + r];
+        bp[j] = i < ncell ? predict_cell_v(band, BW, ly, lx, sg[j], sl, stay_a, bt[j]) : 0.f;
+      }
+      // child by child, so each child's rows of the band go out together
+      for (int r = 0; r < U; ++r) {
+        const int zz = sh.zr[a * n + r];
+        const float inv = sh.inv[a * n + r];
+        float *out = lv.cbel + (size_t)(cb + r) * S + t00;
+#pragma unroll
+        for (int j = 0; j < kCellBatch; ++j) {
+          const int i = i0 + j * kBlock;
+          if (i >= ncell) break;
+          const float o = wall_lik(m.flip, (uint32_t)(zz & 15), sig_wall(sg[j])) *
+                          lm_lik(rho, (uint32_t)(zz >> 4), sig_lm(sg[j]));
+          out[i] = o * bp[j] * inv;
         }
       }
     }
   }
 }
 
-// Workgroup i takes band i mod tiles of parent i / tiles (see k_stats_parent).
-// SORT: the launch carries lv.sort_bands extra workgroups at the end that sort
-// the last level's bands (as k_prep_sort); the level-0 launch, one workgroup
-// per CU, has room for them.
-template <bool SORT>
+// Workgroup i takes band i mod tiles of parent i / (tiles G), actions of
+// group (i / tiles) mod G (see k_stats_parent for the band order).
 __global__ __launch_bounds__(kBlock) void k_update_parent(DevModel m, LevelArgs lv) {
   extern __shared__ float smem[];
   __shared__ ParentShared sh;
-  if constexpr (SORT) {
-    const int items = (int)gridDim.x - lv.sort_bands;
-    if ((int)blockIdx.x >= items) {
-      const int band = blockIdx.x - items, c_lo = band * lv.sort_tc;
-      sort_band(c_lo, min(m.S, c_lo + lv.sort_tc), m.L, lv.sig, (int32_t *)lv.sort_cells,
-                (int32_t *)lv.sort_chunk + (size_t)band * kSortChunkInts);
-      return;
-    }
-  }
-  const int p = blockIdx.x / lv.tiles;
-  update_parent_item(m, lv, p, blockIdx.x - p * lv.tiles, smem, sh);
+  const int i = blockIdx.x;
+  // item i: parent i / (tiles G), action group (i / tiles) mod G, band i mod
+  // tiles (G = lv.agroups: a level with few items splits each band's
+  // actions over G workgroups)
+  const int G = lv.agroups > 1 ? lv.agroups : 1;
+  const int per = lv.tiles * G;
+  const int p = i / per, rem = i - p * per;
+  const int g = rem / lv.tiles, tile = rem - g * lv.tiles;
+  const int apg = (m.A + G - 1) / G;
+  update_parent_item(m, lv, p, tile, g * apg, min(m.A, (g + 1) * apg), smem, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2764,16 +2805,16 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       if (e != hipSuccess) return e;
     }
   }
-  // on the banded path with D >= 2 the level-0 update launch sorts the leaf
-  // bands; otherwise a launch of its own does
-  const bool sort_in_update = leaf_parent && !small && per_parent && D >= 2;
+  // on the banded path with D >= 2 the level-0 statistics launch sorts the
+  // leaf bands; otherwise a launch of its own does
+  const bool sort_in_stats = leaf_parent && !small && per_parent && D >= 2;
   // banded path, D >= 3, default flags: levels 1..D-2 take their statistics
   // from the basis pass over the sorted leaf bands with R in place of Q
   // (k_leaf_parent + k_inner_finish), which also forms every child's reward;
   // QV_PLAN_TILED keeps the per-action statistics of the batched path
-  const bool basis_inner = sort_in_update && D >= 3 && !(flags & QV_PLAN_TILED);
+  const bool basis_inner = sort_in_stats && D >= 3 && !(flags & QV_PLAN_TILED);
   const bool r_vec = (A == 4 || A == 8) && ((uintptr_t)m.R % 16 == 0);
-  if (leaf_parent && !sort_in_l0 && !sort_in_update) {
+  if (leaf_parent && !sort_in_l0 && !sort_in_stats) {
     QV_LAUNCH(k_prep_sort, dim3(L.leaf_tiles), dim3(kBlock), 0, st, m.S, L.leaf_rows * m.W, m.L,
               sig, sort_cells, sort_chunk);
   }
@@ -2842,6 +2883,7 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
     lv.slot_n = slot_n + 2 * (d + 1);
     lv.slot_cap = order_next ? (int)T.level_slots[d + 1] : 0;
     lv.porder = (leaf_parent && d >= 1 && d == D - 1) ? slot_list + loff[d] : nullptr;
+    lv.agroups = 1;
     if (last && leaf_parent) {
       lv.TH = L.leaf_rows;
       lv.tiles = L.leaf_tiles;
@@ -2920,26 +2962,38 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       lv.part = part;
       lv.leaf_finish = 0;
       lv.Q = Q;
-      QV_LAUNCH_L(d, k_update_parent<false>, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
+      QV_LAUNCH_L(d, k_update_parent, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
       continue;
     }
-    if (per_parent) {
+    if (per_parent && d == 0 && sort_in_stats) {
+      // the leaf-band sort runs beside the level-0 statistics, its tables in
+      // the launch's dynamic LDS
       lv.draws_apart = 1;
-      QV_LAUNCH_L(d, k_stats_parent, dim3(npar), dim3(kBlock), lds_spar, st, m, lv);
+      lv.sort_bands = L.leaf_tiles;
+      lv.sort_tc = L.leaf_rows * m.W;
+      const size_t lds_sort = sort_band_lds_bytes<kBlock>(lv.sort_tc);
+      QV_LAUNCH_L(d, k_stats_parent<true>, dim3(npar + L.leaf_tiles), dim3(kBlock),
+                  lds_spar > lds_sort ? lds_spar : lds_sort, st, m, lv);
+      lv.sort_bands = 0;
+      lv.sort_tc = 0;
+      QV_LAUNCH_L(d, k_stats_draws, dim3((unsigned)((long long)lv.nslots * A)), dim3(kWave),
+                  (size_t)(2 * m.L + 32) * sizeof(float), st, m, lv);
+      lv.draws_apart = 0;
+    } else if (per_parent) {
+      lv.draws_apart = 1;
+      QV_LAUNCH_L(d, k_stats_parent<false>, dim3(npar), dim3(kBlock), lds_spar, st, m, lv);
       QV_LAUNCH_L(d, k_stats_draws, dim3((unsigned)((long long)lv.nslots * A)), dim3(kWave),
                   (size_t)(2 * m.L + 32) * sizeof(float), st, m, lv);
       lv.draws_apart = 0;
     } else
       QV_LAUNCH_L(d, k_stats, dim3(nblk), dim3(kBlock), lds_stats, st, m, lv);
-    if ((!last || store_leaves) && per_parent && d == 0 && sort_in_update) {
-      lv.sort_bands = L.leaf_tiles;
-      lv.sort_tc = L.leaf_rows * m.W;
-      QV_LAUNCH_L(d, k_update_parent<true>, dim3(npar + L.leaf_tiles), dim3(kBlock), lds_band, st,
-                  m, lv);
-      lv.sort_bands = 0;
-      lv.sort_tc = 0;
-    } else if ((!last || store_leaves) && per_parent) {
-      QV_LAUNCH_L(d, k_update_parent<false>, dim3(npar), dim3(kBlock), lds_band, st, m, lv);
+    // a level of few (parent, band) items splits each item's actions over up
+    // to 4 workgroups, so that about 1024 of them share the writes
+    int agroups = 1;
+    while (agroups < 4 && agroups * 2 <= A && (long long)npar * agroups * 2 <= 1024) agroups *= 2;
+    lv.agroups = agroups;
+    if ((!last || store_leaves) && per_parent) {
+      QV_LAUNCH_L(d, k_update_parent, dim3(npar * agroups), dim3(kBlock), lds_band, st, m, lv);
     } else if (!last || store_leaves) {
       QV_LAUNCH_L(d, k_update, dim3(nblk), dim3(kBlock), lds_band, st, m, lv);
     } else if (A <= 4) {

@@ -72,8 +72,14 @@ def level_grids(workload: str):
             out[(fam, slots * tiles * A * BLOCK)] = d
         for fam in ("k_stats_parent", "k_update_parent"):
             out[(fam, slots * tiles * BLOCK)] = d
-        if d == 0:   # the level-0 update launch also carries the leaf-band sort
-            out[("k_update_parent", (slots * tiles + leaf_tiles) * BLOCK)] = d
+        # a level of few items splits each (parent, band)'s actions over G
+        # workgroups of the update launch
+        G = 1
+        while G < 4 and G * 2 <= A and slots * tiles * G * 2 <= 1024:
+            G *= 2
+        out[("k_update_parent", slots * tiles * G * BLOCK)] = d
+        if d == 0:   # the level-0 statistics launch also carries the leaf-band sort
+            out[("k_stats_parent", (slots * tiles + leaf_tiles) * BLOCK)] = d
         out[("k_stats_draws", slots * A * 64)] = d
     for d in range(1, D - 1):   # basis inner levels (the leaf kernel with R for Q)
         out[("k_leaf_parent", K ** d * leaf_tiles * NODE_BLOCK)] = d
