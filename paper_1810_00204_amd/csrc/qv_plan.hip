@@ -232,7 +232,7 @@ constexpr int kSortMaxCells = 16384;   // cells of one sorted band (leaf bands <
 // small.
 template <int NT>
 __host__ __device__ inline size_t sort_band_lds_bytes(int cells) {
-  return (size_t)(17 * NT + NT / kWave + 17 + 17 + 1) * 4 + (size_t)(cells + 1) * 2;
+  return (size_t)(17 * NT + NT / kWave + 17 + 17 + 1) * 4 + (size_t)(cells + NT + 2) * 2;
 }
 template <int NT = kBlock, bool DYN = false>
 __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_t *cells,
@@ -251,7 +251,7 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     cs = (uint16_t *)(s_Cp + 1);
   } else {
     __shared__ int cnt_s[17 * NT];
-    __shared__ uint16_t cs_s[kSortMaxCells];
+    __shared__ uint16_t cs_s[kSortMaxCells + NT + 2];
     __shared__ int wtot_s[NT / kWave];
     __shared__ int start_s[17], pchunk_s[17], c_s;
     cnt = cnt_s;
@@ -264,21 +264,30 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
   auto cx = [](int e) { return e + (e >> 4); };
   const int tid = threadIdx.x;
   const int S = c_hi - c_lo;
-  // the band's signatures, coalesced, eight loads in flight per thread
-  for (int i0 = tid; i0 < S; i0 += 8 * NT) {
-    uint32_t sg[8];
+  // thread i counts and scatters cells [i R, (i+1) R); cell c sits at
+  // c + c / R in cs, so each thread's cells are R + 1 entries apart from its
+  // neighbour's (an odd stride in 16-bit words: two lanes per LDS bank
+  // instead of R)
+  static_assert(kSortMaxCells / NT < 256, "a thread's counts fit 8-bit fields");
+  const int R = (S + NT - 1) / NT;
+  const float rR = 1.0f / (float)R;
+  // the band's signatures, coalesced, all of a thread's loads in flight
+  // together for a band of 8192 cells
+  constexpr int LB = 8192 / NT;
+  for (int i0 = tid; i0 < S; i0 += LB * NT) {
+    uint32_t sg[LB];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < LB; ++k) {
       const int i = i0 + k * NT;
       const uint32_t sv = sig[c_lo + (i < S ? i : 0)];   // every lane loads, then masks
       sg[k] = i < S ? sv : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 0; k < LB; ++k) {
       const int i = i0 + k * NT;
       if (i < S) {
         const uint32_t lm = sig_lm(sg[k]);
-        cs[i] = (uint16_t)(sig_out8(sg[k]) | (sig_wall(sg[k]) << 8) |
+        cs[i + fdiv(i, R, rR)] = (uint16_t)(sig_out8(sg[k]) | (sig_wall(sg[k]) << 8) |
                            ((sg[k] & kSigFree) ? 1u << 12 : 0u) |
                            ((sg[k] & kSigGoal) ? 1u << 13 : 0u) |
                            ((lm && lm <= (uint32_t)L) ? 1u << 14 : 0u));
@@ -286,19 +295,26 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     }
   }
   __syncthreads();
-  const int R = (S + NT - 1) / NT;
   const int c0 = min(S, tid * R), c1 = min(S, c0 + R);   // band-relative
-  int n[16];
+  const uint16_t *mine = cs + tid;                        // cell t at mine[t]
+  // free cells per wall reading, as 8-bit fields (a thread has <= 64 cells):
+  // readings 0..7 in lo, 8..15 in hi; eight LDS reads in flight at a time
+  uint64_t nlo = 0, nhi = 0;
+  for (int t0 = c0; t0 < c1; t0 += 8) {
+    uint32_t v[8];
 #pragma unroll
-  for (int w = 0; w < 16; ++w) n[w] = 0;
-  for (int t = c0; t < c1; ++t) {
-    const uint32_t c = cs[t];
-    const int w = (c & (1u << 12)) ? (int)((c >> 8) & 15u) : -1;
+    for (int k = 0; k < 8; ++k) v[k] = t0 + k < c1 ? (uint32_t)mine[t0 + k] : 0u;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) n[k] += (w == k) ? 1 : 0;
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t w = (v[k] >> 8) & 15u;
+      const uint64_t one = (v[k] & (1u << 12)) ? 1ull << (8 * (w & 7u)) : 0ull;
+      nlo += w < 8u ? one : 0ull;
+      nhi += w < 8u ? 0ull : one;
+    }
   }
 #pragma unroll
-  for (int w = 0; w < 16; ++w) cnt[cx(w * NT + tid)] = n[w];
+  for (int w = 0; w < 16; ++w)
+    cnt[cx(w * NT + tid)] = (int)(((w < 8 ? nlo : nhi) >> (8 * (w & 7))) & 255u);
   __syncthreads();
   // exclusive scan of cnt in (w, thread) order: thread i owns entries
   // [16 i, 16 i + 16), then the NT owner totals are scanned
@@ -332,21 +348,31 @@ __device__ void sort_band(int c_lo, int c_hi, int L, const uint32_t *sig, int32_
     s_pchunk[16] = pc;
     *s_Cp = C;
   }
-  // scatter: each thread walks its cells again in order
-  int o[16];
+  // scatter: each thread walks its cells again in order; a cell's position
+  // is its reading's offset for this thread (cnt, read from LDS) plus the
+  // thread's earlier cells of that reading (the same 8-bit fields)
+  uint64_t rlo = 0, rhi = 0;
+  for (int t0 = c0; t0 < c1; t0 += 8) {
+    uint32_t v[8];
 #pragma unroll
-  for (int w = 0; w < 16; ++w) o[w] = cnt[cx(w * NT + tid)];
-  for (int t = c0; t < c1; ++t) {
-    const uint32_t c = cs[t];
-    if (!(c & (1u << 12))) continue;
-    const int w = (int)((c >> 8) & 15u);
-    int pos = 0;
+    for (int k = 0; k < 8; ++k) v[k] = t0 + k < c1 ? (uint32_t)mine[t0 + k] : 0u;
+    int base[8];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-      if (w == k) pos = o[k]++;
-    cells[c_lo + pos] = (int32_t)((uint32_t)(c_lo + t) | ((c & 0xFFu) << kSortOutShift) |
-                                  ((c & (1u << 13)) ? kSortGoal : 0u) |
-                                  ((c & (1u << 14)) ? kSortLandmark : 0u));
+    for (int k = 0; k < 8; ++k) base[k] = cnt[cx((int)((v[k] >> 8) & 15u) * NT + tid)];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t c = v[k];
+      if (!(c & (1u << 12))) continue;   // blocked, or past the thread's cells
+      const uint32_t w = (c >> 8) & 15u, sh8 = 8 * (w & 7u);
+      const int pos = base[k] + (int)(((w < 8u ? rlo : rhi) >> sh8) & 255u);
+      if (w < 8u)
+        rlo += 1ull << sh8;
+      else
+        rhi += 1ull << sh8;
+      cells[c_lo + pos] = (int32_t)((uint32_t)(c_lo + t0 + k) | ((c & 0xFFu) << kSortOutShift) |
+                                    ((c & (1u << 13)) ? kSortGoal : 0u) |
+                                    ((c & (1u << 14)) ? kSortLandmark : 0u));
+    }
   }
   __syncthreads();
   // chunk k (one per thread of the leaf kernel, kBlock of them) belongs to
