@@ -64,7 +64,9 @@ extern "C" {
 #define QV_PLAN_STORE_LEAVES 1
 /* Use the banded multi-pass kernels even where the whole belief would fit
  * in one workgroup's LDS (the default for such grids is one workgroup per
- * Q-node); results are the same up to FP32 summation order. */
+ * Q-node), with the layout's bands and per-action statistics at every level
+ * (the batched path's arithmetic); results are the same up to FP32
+ * summation order. */
 #define QV_PLAN_TILED 2
 
 /* Check the start belief on the device before planning: the call becomes

@@ -2955,8 +2955,25 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
       }
       continue;
     }
-    const unsigned nblk = (unsigned)((long long)lv.nslots * tiles * A);
-    const unsigned npar = (unsigned)((long long)lv.nslots * tiles);
+    // a level of few parents runs the per-parent kernels on thinner bands,
+    // so that at least two band items share each CU (level 0: one parent,
+    // 512 bands of one row at 512 x 512); the partials buffer holds
+    // part_slots x tiles bands of each action.  QV_PLAN_TILED keeps the
+    // layout's bands at every level, as the batched path does (its trees
+    // are bitwise those of the batch)
+    int TH_d = TH, tiles_d = tiles;
+    if (per_parent && !small && !(flags & QV_PLAN_TILED)) {
+      while (TH_d > 1 && (long long)lv.nslots * tiles_d < 512) {
+        const int th2 = (TH_d + 1) / 2, t2 = (m.H + th2 - 1) / th2;
+        if ((long long)lv.nslots * t2 > (long long)L.part_slots * tiles) break;
+        TH_d = th2;
+        tiles_d = t2;
+      }
+    }
+    lv.TH = TH_d;
+    lv.tiles = tiles_d;
+    const unsigned nblk = (unsigned)((long long)lv.nslots * tiles_d * A);
+    const unsigned npar = (unsigned)((long long)lv.nslots * tiles_d);
     if (basis_inner && d >= 1) {
       // statistics by the leaf kernel's basis pass over the sorted leaf bands,
       // with the rows of R in place of those of Q: per action, the predicted
@@ -2983,8 +3000,8 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
         QV_LAUNCH_L(d, k_inner_finish<4>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv);
       else
         QV_LAUNCH_L(d, k_inner_finish<8>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv);
-      lv.TH = TH;
-      lv.tiles = tiles;
+      lv.TH = TH_d;
+      lv.tiles = tiles_d;
       lv.part = part;
       lv.leaf_finish = 0;
       lv.Q = Q;

@@ -65,21 +65,26 @@ def level_grids(workload: str):
     out = {}
     for d in range(D):
         slots = K ** d
+        # per-parent levels of few items run on thinner bands (as the planner)
+        th_d, tiles_d = th, tiles
+        while th_d > 1 and slots * tiles_d < 512:
+            th_d = (th_d + 1) // 2
+            tiles_d = (prob.H + th_d - 1) // th_d
         out[("k_node", slots * A * NODE_BLOCK)] = d
         if d == 0:   # level 0 also carries the leaf-band sort workgroups
             out[("k_node", (slots * A + leaf_tiles) * NODE_BLOCK)] = d
         for fam in ("k_stats", "k_update", "k_leaf"):
             out[(fam, slots * tiles * A * BLOCK)] = d
         for fam in ("k_stats_parent", "k_update_parent"):
-            out[(fam, slots * tiles * BLOCK)] = d
+            out[(fam, slots * tiles_d * BLOCK)] = d
         # a level of few items splits each (parent, band)'s actions over G
         # workgroups of the update launch
         G = 1
-        while G < 4 and G * 2 <= A and slots * tiles * G * 2 <= 1024:
+        while G < 4 and G * 2 <= A and slots * tiles_d * G * 2 <= 1024:
             G *= 2
-        out[("k_update_parent", slots * tiles * G * BLOCK)] = d
+        out[("k_update_parent", slots * tiles_d * G * BLOCK)] = d
         if d == 0:   # the level-0 statistics launch also carries the leaf-band sort
-            out[("k_stats_parent", (slots * tiles + leaf_tiles) * BLOCK)] = d
+            out[("k_stats_parent", (slots * tiles_d + leaf_tiles) * BLOCK)] = d
         out[("k_stats_draws", slots * A * 64)] = d
     for d in range(1, D - 1):   # basis inner levels (the leaf kernel with R for Q)
         out[("k_leaf_parent", K ** d * leaf_tiles * NODE_BLOCK)] = d
