@@ -2510,91 +2510,107 @@ __global__ __launch_bounds__(kLeafBlock) void k_leaf_finish(DevModel m, LevelArg
 }
 
 // Completion of parent p of an inner level whose band items ran the basis
-// pass with R in place of Q (leaf_parent_item; own_reward as for the root):
-// HQ holds, per action, the predicted mass by wall reading (column AM) and the
-// reward-weighted sums RH_a[w][c] = sum over cells x of reading w of
-// lambda(x) b'_a(x) R(x,c).  Wavefront w draws for actions w, w + NW, ...
-// (Alg. 3/4), writes the child records and the next level's visiting order,
-// and (the parent's own R(b,a) when the items formed it); then every drawn
-// child's reward row follows from the same algebra as a leaf score (Sec. III
-// update, Alg. 5):
-//   R(Phi(b,a,z), c) = (1/P(z)) sum_w O_w(zw|w) RH_a[w][c]   (no landmark seen)
-//                    = (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) R(x_l,c)   (landmark l),
-// written to the child level's reward rows, so that level's band items need no
-// R(b,a) pass.  X: LDS scratch of (1 + NW) L + 32 NW floats.
-template <int AM, int NT>
-__device__ void inner_parent_finish(const DevModel &m, const LevelArgs &lv, int p, float *X,
-                                    const float *HQ, LeafParentShared &sh) {
+// pass with R in place of Q (leaf_parent_item; own_reward as for the root),
+// one workgroup per (parent, action), after every band item has written its
+// record.  The band records hold, per action, the predicted mass by wall
+// reading (column AM) and the reward-weighted sums RH_a[w][c] = sum over cells
+// x of reading w of lambda(x) b'_a(x) R(x, c), plus R(b,a).  The workgroup
+// sums its action's part in band order, draws the action's observations
+// (wavefront 0; the present children go to the front of the next level's
+// visiting order), and forms each drawn child's rewards (Sec. III update, the
+// wall readings' likelihoods applied to the sums):
+//   R(Phi(b,a,z), c) = (1/P(z)) sum_w O_w(zw|w) RH_a[w][c]           (zl = 0)
+//   R(Phi(b,a,z), c) = (1/P(z)) O_w(zw|w_l) rho b'_a(x_l) R(x_l, c)   (zl = l)
+// Items i: parent i / A, action i mod A.  Absent parents mark their
+// children absent and send them to the back of the visiting order.
+struct InnerFinishShared {
+  DrawOut draw;
+  float rb;   // R(b,a)
+};
+// dynamic LDS floats: the landmarks' wall readings and masses, the sampler's
+// tables, then the action's sums
+__host__ __device__ inline size_t inner_finish_lds_floats(int L, int AM) {
+  return (size_t)2 * L + 32 + (size_t)16 * (AM + 1);
+}
+template <int AM>
+__global__ __launch_bounds__(kBlock) void k_inner_finish(DevModel m, LevelArgs lv) {
+  extern __shared__ float smem[];
+  __shared__ InnerFinishShared sh;
   constexpr int NV = AM + 1;
-  constexpr int NW = NT / kWave;
+  constexpr int RECN = AM * 16 * NV + AM;   // band record: HQ, then R(b,a)
   const int A = m.A, L = m.L, K = lv.K, n = lv.n;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
-  const float rho = m.lm_p;
-  uint32_t *lw = (uint32_t *)X;
-  for (int l = tid; l < L; l += NT) lw[l] = lv.lm_wall[l];
+  const int p = blockIdx.x / A, a = blockIdx.x - p * A;
+  const int cb = p * K + a * n;
+  if (!lv.pvalid[p]) {
+    if (tid < n) {
+      lv.cvalid[cb + tid] = 0;
+      lv.cz[cb + tid] = -1;
+      lv.ccount[cb + tid] = 0;
+      lv.cpz[cb + tid] = 0.f;
+    }
+    list_absent_children(lv, cb);
+    return;
+  }
+  uint32_t *lw = (uint32_t *)smem;   // [L] wall readings of the landmarks
+  float *lvv = smem + L;             // [L] predicted masses of the landmark cells
+  float *p0tab = smem + 2 * L;       // [32] sampler tables
+  float *HQ = smem + 2 * L + 32;     // [16][NV] the action's sums
+  // the action's sums and R(b,a): band records summed in band order, the
+  // loads of up to 32 bands in flight together
+  const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
+  for (int i = tid; i <= 16 * NV; i += kBlock) {
+    const int off = i < 16 * NV ? a * 16 * NV + i : AM * 16 * NV + a;
+    float sum = 0.f;
+    for (int t0 = 0; t0 < lv.tiles; t0 += 32) {
+      float x[32];
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        x[k] = t0 + k < lv.tiles ? ld_coherent(rec0 + (size_t)(t0 + k) * RECN + off) : 0.f;
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        if (t0 + k < lv.tiles) sum += x[k];
+    }
+    if (i < 16 * NV)
+      HQ[i] = sum;
+    else
+      sh.rb = sum;
+  }
+  for (int l = tid; l < L; l += kBlock) {
+    lw[l] = lv.lm_wall[l];
+    lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
+  }
   wait_mem();
   __syncthreads();
-  float *lvv = X + L + wave * L;
-  for (int a = wave; a < A; a += NW) {
-    for (int l = lane; l < L; l += kWave) lvv[l] = ld_coherent(lv.lmv + ((size_t)p * A + a) * L + l);
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
-    float hs = 0.f;
-    if (lane < 16) hs = HQ[(a * 16 + lane) * NV + AM];
-    const int U = sample_draws(m, lv, p, a, hs, lw, lvv, X + (1 + NW) * L + 32 * wave, &sh.draw[a]);
-    if (lv.own_reward && lane == 0) lv.reward[p * A + a] = sh.rb[a];
+  if (wave == 0) {
+    const float hs = lane < 16 ? HQ[lane * NV + AM] : 0.f;
+    const int U = sample_draws(m, lv, p, a, hs, lw, lvv, p0tab, &sh.draw);
+    if (lv.own_reward && lane == 0) lv.reward[p * A + a] = sh.rb;
     if (lv.slot_list) {
       ListPos lp = {0, 0};
       if (lane == 0) lp = list_take(lv, U);
-      list_put(lv, p * K + a * n, U, lp);
+      list_put(lv, cb, U, lp);
     }
-    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  for (int i = tid; i < A * n * A; i += NT) {
-    const int a = i / (n * A), r = (i / A) - a * n, c = i - (i / A) * A;
-    if (r >= sh.draw[a].U) continue;
-    const int z = sh.draw[a].z[r];
+  const float rho = m.lm_p;
+  for (int i = tid; i < n * A; i += kBlock) {
+    const int r = i / A, c = i - r * A;
+    if (r >= sh.draw.U) continue;
+    const int z = sh.draw.z[r];
     const uint32_t zw = (uint32_t)(z & 15);
     const int zl = z >> 4;
     float v = 0.f;
     if (zl == 0) {
 #pragma unroll
       for (int w = 0; w < 16; ++w)
-        v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[(a * 16 + w) * NV + c], v);
+        v = fmaf(wall_lik(m.flip, zw, (uint32_t)w), HQ[w * NV + c], v);
     } else {
       const int cell = m.lm_cell[zl - 1];
-      v = wall_lik(m.flip, zw, lw[zl - 1]) * rho *
-          ld_coherent(lv.lmv + ((size_t)p * A + a) * L + zl - 1) * m.R[(size_t)cell * A + c];
+      v = wall_lik(m.flip, zw, lw[zl - 1]) * rho * lvv[zl - 1] * m.R[(size_t)cell * A + c];
     }
-    lv.creward[((size_t)p * K + a * n + r) * A + c] = v * sh.draw[a].inv[r];
+    lv.creward[((size_t)cb + r) * A + c] = v * sh.draw.inv[r];
   }
-}
-
-// Inner-level completion (inner_parent_finish), one workgroup per parent
-// after every band item has written its record.  Absent parents mark their
-// children absent and send them to the back of the visiting order.
-template <int AM>
-__global__ __launch_bounds__(kLeafBlock) void k_inner_finish(DevModel m, LevelArgs lv) {
-  extern __shared__ float smem[];
-  __shared__ LeafParentShared sh;
-  const int p = blockIdx.x;
-  if (!lv.pvalid[p]) {
-    for (int i = threadIdx.x; i < lv.K; i += kLeafBlock) {
-      const int c = p * lv.K + i;
-      lv.cvalid[c] = 0;
-      lv.cz[c] = -1;
-      lv.ccount[c] = 0;
-      lv.cpz[c] = 0.f;
-    }
-    for (int a = 0; a < m.A; ++a) list_absent_children(lv, p * lv.K + a * lv.n);
-    return;
-  }
-  float *X = smem;
-  float *HQ = smem + leaf_finish_x_floats(m.L, lv.K, m.A, kLeafBlock);
-  leaf_parent_sum_records<AM, kLeafBlock>(lv, p, HQ, sh);
-  __syncthreads();
-  inner_parent_finish<AM, kLeafBlock>(m, lv, p, X, HQ, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -2995,11 +3011,13 @@ hipError_t launch_plan(const qv_model *mm, const float *Q, const float *b0, int 
         QV_LAUNCH_L(d, (k_leaf_parent<8, 1>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
       else
         QV_LAUNCH_L(d, (k_leaf_parent<8, 0>), dim3(nb), dim3(kLeafBlock), lds_lp, st, m, lv, tr);
-      const size_t lds_fin = leaf_finish_lds_floats(m.L, K, A, AM) * sizeof(float);
+      // draws and children's rewards, one workgroup per (parent, action)
+      const size_t lds_fin = inner_finish_lds_floats(m.L, AM) * sizeof(float);
+      const unsigned nfin = (unsigned)((long long)lv.nslots * A);
       if (AM == 4)
-        QV_LAUNCH_L(d, k_inner_finish<4>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv);
+        QV_LAUNCH_L(d, k_inner_finish<4>, dim3(nfin), dim3(kBlock), lds_fin, st, m, lv);
       else
-        QV_LAUNCH_L(d, k_inner_finish<8>, dim3(lv.nslots), dim3(kLeafBlock), lds_fin, st, m, lv);
+        QV_LAUNCH_L(d, k_inner_finish<8>, dim3(nfin), dim3(kBlock), lds_fin, st, m, lv);
       lv.TH = TH_d;
       lv.tiles = tiles_d;
       lv.part = part;

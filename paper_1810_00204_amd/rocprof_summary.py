@@ -88,7 +88,7 @@ def level_grids(workload: str):
         out[("k_stats_draws", slots * A * 64)] = d
     for d in range(1, D - 1):   # basis inner levels (the leaf kernel with R for Q)
         out[("k_leaf_parent", K ** d * leaf_tiles * NODE_BLOCK)] = d
-        out[("k_inner_finish", K ** d * NODE_BLOCK)] = d
+        out[("k_inner_finish", K ** d * A * BLOCK)] = d
     out[("k_leaf_parent", K ** (D - 1) * leaf_tiles * NODE_BLOCK)] = D - 1
     out[("k_leaf_finish", K ** (D - 1) * NODE_BLOCK)] = D - 1
     return out

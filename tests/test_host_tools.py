@@ -39,15 +39,16 @@ def test_level_grids_of_the_64x64_workload():
 
 def test_level_grids_of_the_512x512_workload():
     """Level 1 of the 512x512 plan runs the leaf kernel over its parents'
-    bands (the basis inner level) and k_inner_finish; the last level runs the
-    same kernel over 32 bands of every slot."""
+    bands (the basis inner level) and its completion per (parent, action);
+    the last level runs the leaf kernel over 32 bands of every slot and its
+    completion per parent."""
     prob = wl.make_large(seed=0)
     g = rs.level_grids("large512")
     K = prob.A * prob.n
     bands = (prob.H + 8192 // prob.W - 1) // (8192 // prob.W)
     assert bands == 32
     assert g[("k_leaf_parent", K * bands * rs.NODE_BLOCK)] == 1
-    assert g[("k_inner_finish", K * rs.NODE_BLOCK)] == 1
+    assert g[("k_inner_finish", K * prob.A * rs.BLOCK)] == 1
     assert g[("k_leaf_parent", K ** 2 * bands * rs.NODE_BLOCK)] == 2
     assert g[("k_leaf_finish", K ** 2 * rs.NODE_BLOCK)] == 2
 
