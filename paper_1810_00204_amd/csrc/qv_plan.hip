@@ -2013,16 +2013,17 @@ __device__ void leaf_parent_sum_records(const LevelArgs &lv, int p, float *HQ,
   constexpr int RECN = AM * 16 * NV + AM;
   const float *rec0 = lv.part + (size_t)p * lv.tiles * RECN;
   for (int i = threadIdx.x; i < RECN; i += NT) {
+    // the loads of up to 32 bands in flight together, summed in band order
     float sum = 0.f;
-    int t0 = 0;
-    for (; t0 + 4 <= lv.tiles; t0 += 4) {
-      float x[4];
+    for (int t0 = 0; t0 < lv.tiles; t0 += 32) {
+      float x[32];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) x[k] = ld_coherent(rec0 + (size_t)(t0 + k) * RECN + i);
+      for (int k = 0; k < 32; ++k)
+        x[k] = t0 + k < lv.tiles ? ld_coherent(rec0 + (size_t)(t0 + k) * RECN + i) : 0.f;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) sum += x[k];
+      for (int k = 0; k < 32; ++k)
+        if (t0 + k < lv.tiles) sum += x[k];
     }
-    for (; t0 < lv.tiles; ++t0) sum += ld_coherent(rec0 + (size_t)t0 * RECN + i);
     if (i < AM * 16 * NV)
       HQ[i] = sum;
     else
