@@ -1416,7 +1416,7 @@ __device__ void update_parent_item(const DevModel &m, const LevelArgs &lv, int p
           if (i >= ncell) break;
           const float o = wall_lik(m.flip, (uint32_t)(zz & 15), sig_wall(sg[j])) *
                           lm_lik(rho, (uint32_t)(zz >> 4), sig_lm(sg[j]));
-          out[i] = o * bp[j] * inv;
+          __builtin_nontemporal_store(o * bp[j] * inv, out + i);   // streamed: read back much later
         }
       }
     }
