@@ -153,6 +153,8 @@ __global__ __launch_bounds__(256) void k_prep_plan(DevModel m, uint32_t *sig, fl
                                                    int32_t *err, PrepExtra x) {
   static_assert(QV_MAX_LANDMARKS <= 2 * 256, "two landmarks per thread");
   __shared__ int s_lm[QV_MAX_LANDMARKS];
+  __shared__ uint32_t s_v[256];   // this workgroup's cells' signatures
+  __shared__ int s_id[256];       // the smallest landmark id on each of them
   const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int s = (int)g;
   // every load first, at valid addresses (masked afterwards), so that one
@@ -174,7 +176,8 @@ __global__ __launch_bounds__(256) void k_prep_plan(DevModel m, uint32_t *sig, fl
 #pragma unroll
   for (int k = 0; k < 2; ++k)
     if (threadIdx.x + k * 256 < m.L) s_lm[threadIdx.x + k * 256] = lmc[k];
-  if (g < m.S) sig[s] = v;   // landmark ids are added below
+  s_v[threadIdx.x] = v;
+  s_id[threadIdx.x] = 0x7fffffff;
   if (g < m.A * 256) staytab[s] = stay_value(sl, s & 255);
   if (g == 0) {
     err[0] = 0;
@@ -187,14 +190,24 @@ __global__ __launch_bounds__(256) void k_prep_plan(DevModel m, uint32_t *sig, fl
   }
   if (g < x.nzero) x.zero[g] = 0;
   __syncthreads();
-  if (g < m.S) {
-    uint32_t id = 0;
-    for (int l = m.L - 1; l >= 0; --l)
-      if (s_lm[l] == s) {
-        id = (uint32_t)(l + 1);
-        x.lm_wall[l] = sig_wall(v);
+  // landmarks on this workgroup's cells: the cell takes the smallest id of
+  // those on it; every such landmark records the cell's wall reading
+  const long long base = (long long)blockIdx.x * blockDim.x;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int l = threadIdx.x + k * 256;
+    if (l < m.L) {
+      const long long c = lmc[k];
+      if (c >= base && c < base + 256 && c < m.S) {
+        atomicMin(&s_id[c - base], l + 1);
+        x.lm_wall[l] = sig_wall(s_v[c - base]);
       }
-    if (id) sig[s] = v | (id << 14);
+    }
+  }
+  __syncthreads();
+  if (g < m.S) {
+    const int id = s_id[threadIdx.x];
+    sig[s] = id != 0x7fffffff ? v | ((uint32_t)id << 14) : v;
   }
   if (g < m.L) {
     const int c = s_lm[g];
