@@ -3512,73 +3512,96 @@ __global__ __launch_bounds__(kBlock) void k_search_expand(DevModel m, SearchArgs
 // Alg. 6 for every action of expanded node v, then Alg. 7 (gamma in the
 // Q-node backup; H(b,a) = 1 only for the action of largest U_Q; the child
 // of largest gamma * weight * H gives H_Q and E_Q; first maximum on ties).
-__device__ void search_update_node(const DevModel &m, const SearchArgs &sa, int v) {
-  const int A = m.A, n = sa.n, cb = sa.cbase[v];
+// One wavefront: lane a backs up action a over its children in order, then
+// every lane takes the actions in order.  Child records are read past the
+// cache (lane 0 wrote the previous node of the climb).
+__device__ void search_update_node(const DevModel &m, const SearchArgs &sa, int v, int cb) {
+  const int A = m.A, n = sa.n;
+  const int lane = threadIdx.x & (kWave - 1);
   const float g = m.gamma;
-  float bestU = -INFINITY, bestL = -INFINITY, Hs = 0.f;
-  int Es = v;
-  for (int a = 0; a < A; ++a) {
+  float uq = -INFINITY, lq = -INFINITY, hq = -INFINITY;
+  int eq = v;
+  if (lane < A) {
+    const int a = lane;
     const float r = sa.rb[(size_t)v * A + a];
-    float su = 0.f, sl = 0.f, hq = -INFINITY;
-    int eq = v;
+    float su = 0.f, sl = 0.f;
     for (int i = 0; i < n; ++i) {
       const int c = cb + a * n + i;
       if (!sa.valid[c]) continue;
-      su = fmaf(sa.w[c], sa.U[c], su);
-      sl = fmaf(sa.w[c], sa.L[c], sl);
-      const float h = g * sa.w[c] * sa.H[c];
+      const float w = sa.w[c];
+      su = fmaf(w, ld_coherent(sa.U + c), su);
+      sl = fmaf(w, ld_coherent(sa.L + c), sl);
+      const float h = g * w * ld_coherent(sa.H + c);
       if (h > hq) {
         hq = h;
-        eq = sa.E[c];
+        eq = __hip_atomic_load(sa.E + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
-    const float uq = fmaf(g, su, r), lq = fmaf(g, sl, r);
+    uq = fmaf(g, su, r);
+    lq = fmaf(g, sl, r);
     sa.UQ[(size_t)v * A + a] = uq;
     sa.LQ[(size_t)v * A + a] = lq;
     sa.HQ[(size_t)v * A + a] = hq;
     sa.EQ[(size_t)v * A + a] = eq;
-    if (uq > bestU) {
-      bestU = uq;
-      Hs = hq;
-      Es = eq;
-    }
-    bestL = fmaxf(bestL, lq);
   }
-  sa.U[v] = bestU;
-  sa.L[v] = bestL;
-  sa.H[v] = Hs;
-  sa.E[v] = Es;
+  float bestU = -INFINITY, bestL = -INFINITY, Hs = 0.f;
+  int Es = v;
+  for (int a = 0; a < A; ++a) {
+    const float u = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uq), a));
+    const float l = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lq), a));
+    if (u > bestU) {
+      bestU = u;
+      Hs = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(hq), a));
+      Es = __builtin_amdgcn_readlane(eq, a);
+    }
+    bestL = fmaxf(bestL, l);
+  }
+  if (lane == 0) {
+    st_coherent(sa.U + v, bestU);
+    st_coherent(sa.L + v, bestL);
+    st_coherent(sa.H + v, Hs);
+    __hip_atomic_store(sa.E + v, Es, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  wait_mem();
+  __builtin_amdgcn_wave_barrier();
 }
 
+// One wavefront: lane 0 keeps the control words, every lane takes part in
+// the climb.
 __global__ void k_search_update(DevModel m, SearchArgs sa) {
-  if (threadIdx.x != 0) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  if (threadIdx.x >= kWave) return;
   const int v = sa.ctl[kCtlSelect], base = sa.ctl[kCtlNext];
   if (sa.ctl[kCtlFlags] || v < 0) return;
   if (sa.expanded[v]) {
-    sa.ctl[kCtlFlags] |= kSearchDone;
+    if (lane == 0) sa.ctl[kCtlFlags] |= kSearchDone;
     return;
   }
   if (base + sa.K > sa.NV) {
-    sa.ctl[kCtlFlags] |= kSearchFull;
+    if (lane == 0) sa.ctl[kCtlFlags] |= kSearchFull;
     return;
   }
   // child slots that the draws left empty
-  for (int i = 0; i < sa.K; ++i)
+  for (int i = lane; i < sa.K; i += kWave)
     if (!sa.valid[base + i]) sa.E[base + i] = -1;
-  sa.expanded[v] = 1;
-  sa.cbase[v] = base;
-  sa.ctl[kCtlNext] = base + sa.K;
-  sa.log[sa.ctl[kCtlExpansions]] = v;
-  sa.ctl[kCtlExpansions] += 1;
   const int root = sa.ctl[kCtlRoot];
-  int p = v;
+  if (lane == 0) {
+    sa.expanded[v] = 1;
+    sa.cbase[v] = base;
+    sa.ctl[kCtlNext] = base + sa.K;
+    sa.log[sa.ctl[kCtlExpansions]] = v;
+    sa.ctl[kCtlExpansions] += 1;
+  }
+  int p = v, cb = base;
   while (p >= 0) {
-    search_update_node(m, sa, p);
+    search_update_node(m, sa, p, cb);
     if (p == root) break;
     const int pq = sa.parent[p];
     p = pq >= 0 ? pq / m.A : -1;
+    if (p >= 0) cb = sa.cbase[p];
   }
-  sa.ctl[kCtlSelect] = sa.E[root];
+  if (lane == 0)
+    sa.ctl[kCtlSelect] = __hip_atomic_load(sa.E + root, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // getOptimalAction: the lowest action whose L_Q at the root is within 1e-9
