@@ -158,6 +158,7 @@ struct SearchArgs {
   int32_t *EQ;                  // [NV][A]
   int32_t *ctl;                 // root, select, next, expansions, flags, err
   int32_t *log;                 // [NV] node expanded by each expansion
+  float *bpa;                   // [A][S] predicted beliefs of the node being expanded
 };
 
 // Point-based value iteration state in its workspace (device pointers).

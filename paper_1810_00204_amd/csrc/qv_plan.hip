@@ -3497,16 +3497,29 @@ __global__ __launch_bounds__(kBlock) void k_search_expand(DevModel m, SearchArgs
                  base);
   }
   if (tid == 0) sa.rb[(size_t)v * A + a] = s_H[16];
-  __syncthreads();
-  // children Phi(b,a,z_r) and their bounds (Alg. 3, Alg. 5)
-  for (int r = 0; r < s_draw.U; ++r) {
-    const int c = base + a * sa.n + r;
-    float U, L;
-    search_bounds(m, sa, bpl, s_draw.z[r], s_draw.inv[r], sa.bel + (size_t)c * S, s_red, U, L);
-    if (tid == 0)
-      search_new_node(sa, c, v * A + a, (float)s_draw.count[r] / (float)sa.n, s_draw.z[r],
-                      lv.d + 1, U, L);
-  }
+  // b'_a for the children's workgroups (k_search_child)
+  for (int t = tid; t < S; t += kBlock) sa.bpa[(size_t)a * S + t] = bpl[t];
+}
+
+// Child base + a n + r of the node expanded by k_search_expand (one
+// workgroup per (action, draw), after it): its belief Phi(b,a,z_r) and its
+// bounds (Alg. 3, Alg. 5) from b'_a, then its records.  Draws left empty
+// return.
+__global__ __launch_bounds__(kBlock) void k_search_child(DevModel m, SearchArgs sa) {
+  __shared__ float s_red[4 * 32];
+  const int a = blockIdx.x / sa.n, r = blockIdx.x - a * sa.n;
+  const int v = sa.ctl[kCtlSelect], base = sa.ctl[kCtlNext];
+  if (sa.ctl[kCtlFlags] || v < 0 || sa.expanded[v] || base + sa.K > sa.NV) return;
+  const int c = base + a * sa.n + r;
+  if (!sa.valid[c]) return;
+  const int S = m.S;
+  const int z = sa.z[c];
+  float U, L;
+  search_bounds(m, sa, sa.bpa + (size_t)a * S, z, 1.0f / sa.pz[c], sa.bel + (size_t)c * S, s_red,
+                U, L);
+  if (threadIdx.x == 0)
+    search_new_node(sa, c, v * m.A + a, (float)sa.count[c] / (float)sa.n, z, sa.depth[v] + 1, U,
+                    L);
 }
 
 // Alg. 6 for every action of expanded node v, then Alg. 7 (gamma in the
@@ -3732,6 +3745,7 @@ hipError_t launch_search(int what, const DevModel &m, const SearchArgs &sa, cons
       break;
     case 1:
       QV_LAUNCH(k_search_expand, dim3(m.A), dim3(kBlock), lds, st, m, sa);
+      QV_LAUNCH(k_search_child, dim3(m.A * sa.n), dim3(kBlock), 0, st, m, sa);
       QV_LAUNCH(k_search_update, dim3(1), dim3(kWave), 0, st, m, sa);
       break;
     case 2:

@@ -63,9 +63,13 @@ static bool search_layout_impl(const qv_model *m, int n, int max_nodes, qv_searc
   L->ctl = take(64);
   L->log = take(NV * 4);
   L->err = take(256);
+  take((size_t)A * S * 4);   // predicted beliefs of the expanded node (search_bpa_offset)
   L->total_bytes = off;
   return true;
 }
+
+// The scratch of predicted beliefs b'_a that follows the error word.
+static size_t search_bpa_offset(const qv_search_layout &L) { return L.err + 256; }
 
 static SearchArgs search_args(const qv_search_layout &L, const float *Ut, const float *Lt,
                               int lcols, uint64_t seed, uint32_t qid, char *ws) {
@@ -104,6 +108,7 @@ static SearchArgs search_args(const qv_search_layout &L, const float *Ut, const 
   sa.EQ = (int32_t *)(ws + L.EQ);
   sa.ctl = (int32_t *)(ws + L.ctl);
   sa.log = (int32_t *)(ws + L.log);
+  sa.bpa = (float *)(ws + search_bpa_offset(L));
   return sa;
 }
 
