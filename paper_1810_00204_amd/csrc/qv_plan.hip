@@ -615,6 +615,7 @@ __device__ __forceinline__ int count_arrival(int32_t *ctr) {
 // value on the DPP network (total in lane 63), lane 63 stores its 32 totals,
 // and thread i < 32 adds the four wavefronts' totals of value i in order.
 // red: [4][32] floats.  Ends with a barrier.
+template <int NT = kBlock>
 __device__ __forceinline__ float block_sum32(float (&v)[32], float *red) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
 #pragma unroll
@@ -627,7 +628,7 @@ __device__ __forceinline__ float block_sum32(float (&v)[32], float *red) {
   float out = 0.f;
   if (threadIdx.x < 32) {
 #pragma unroll
-    for (int w = 0; w < kBlock / kWave; ++w) out += red[w * 32 + threadIdx.x];
+    for (int w = 0; w < NT / kWave; ++w) out += red[w * 32 + threadIdx.x];
   }
   __syncthreads();
   return out;
@@ -3327,6 +3328,7 @@ __host__ __device__ inline size_t search_lds_floats(int W, int H) {
 // them).  o(t) = 1 when zr < 0.  The first pass also writes v to out_b and
 // takes the U columns with the first 16 L columns; further passes take 32 L
 // columns each.
+template <int NT = kBlock>
 __device__ void search_bounds(const DevModel &m, const SearchArgs &sa, const float *bpl,
                               int zr, float scale, float *out_b, float *red, float &U,
                               float &L) {
@@ -3340,7 +3342,7 @@ __device__ void search_bounds(const DevModel &m, const SearchArgs &sa, const flo
     float acc[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) acc[i] = 0.f;
-    for (int t = threadIdx.x; t < S; t += kBlock) {
+    for (int t = threadIdx.x; t < S; t += NT) {
       const uint32_t sg = sa.sig[t];
       float o = 1.f;
       if (zr >= 0) o = wall_lik(m.flip, zw, sig_wall(sg)) * lm_lik(m.lm_p, zl, sig_lm(sg));
@@ -3358,7 +3360,7 @@ __device__ void search_bounds(const DevModel &m, const SearchArgs &sa, const flo
           if (c0 + c < LC) acc[c] = fmaf(v, sa.Lt[(size_t)t * LC + c0 + c], acc[c]);
       }
     }
-    const float tot = block_sum32(acc, red);
+    const float tot = block_sum32<NT>(acc, red);
     // thread c < 32 holds the total of value c; the maxima through LDS
     if (threadIdx.x < 32) red[threadIdx.x] = tot;
     __syncthreads();
@@ -3505,8 +3507,9 @@ __global__ __launch_bounds__(kBlock) void k_search_expand(DevModel m, SearchArgs
 // workgroup per (action, draw), after it): its belief Phi(b,a,z_r) and its
 // bounds (Alg. 3, Alg. 5) from b'_a, then its records.  Draws left empty
 // return.
-__global__ __launch_bounds__(kBlock) void k_search_child(DevModel m, SearchArgs sa) {
-  __shared__ float s_red[4 * 32];
+constexpr int kSearchChildBlock = 1024;   // threads of a k_search_child workgroup
+__global__ __launch_bounds__(kSearchChildBlock) void k_search_child(DevModel m, SearchArgs sa) {
+  __shared__ float s_red[kSearchChildBlock / kWave * 32];
   const int a = blockIdx.x / sa.n, r = blockIdx.x - a * sa.n;
   const int v = sa.ctl[kCtlSelect], base = sa.ctl[kCtlNext];
   if (sa.ctl[kCtlFlags] || v < 0 || sa.expanded[v] || base + sa.K > sa.NV) return;
@@ -3515,8 +3518,8 @@ __global__ __launch_bounds__(kBlock) void k_search_child(DevModel m, SearchArgs 
   const int S = m.S;
   const int z = sa.z[c];
   float U, L;
-  search_bounds(m, sa, sa.bpa + (size_t)a * S, z, 1.0f / sa.pz[c], sa.bel + (size_t)c * S, s_red,
-                U, L);
+  search_bounds<kSearchChildBlock>(m, sa, sa.bpa + (size_t)a * S, z, 1.0f / sa.pz[c],
+                                   sa.bel + (size_t)c * S, s_red, U, L);
   if (threadIdx.x == 0)
     search_new_node(sa, c, v * m.A + a, (float)sa.count[c] / (float)sa.n, z, sa.depth[v] + 1, U,
                     L);
@@ -3745,7 +3748,7 @@ hipError_t launch_search(int what, const DevModel &m, const SearchArgs &sa, cons
       break;
     case 1:
       QV_LAUNCH(k_search_expand, dim3(m.A), dim3(kBlock), lds, st, m, sa);
-      QV_LAUNCH(k_search_child, dim3(m.A * sa.n), dim3(kBlock), 0, st, m, sa);
+      QV_LAUNCH(k_search_child, dim3(m.A * sa.n), dim3(kSearchChildBlock), 0, st, m, sa);
       QV_LAUNCH(k_search_update, dim3(1), dim3(kWave), 0, st, m, sa);
       break;
     case 2:
